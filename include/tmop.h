@@ -1,0 +1,217 @@
+/*
+ * tmop.h -- C ABI of the MI355X partially assembled TMOP library.
+ *
+ * The library evaluates the TMOP objective of high-order node-movement mesh
+ * optimisation, its gradient and its Hessian action with partial assembly
+ * (matrix-free, sum-factorized) on quad (2D) and hex (3D) meshes of order p,
+ * and drives the Newton-MINRES solve with its backtracking line search.
+ *
+ *   Mesh nodes           x (Sec. 2.1, eq. eq_x): a global vector of d x N_x
+ *                        coordinates, the element map x = sum_i x_{E,i} w_i.
+ *   Target / metric      T = A W^{-1} (Sec. 2.2, eqs. eq_A, eq_T); mu_2 for
+ *                        quads, mu_303 for hexes (Sec. 2.2, Sec. 4.1).
+ *   Objective            F(x) = sum_E int mu(T) (Sec. 2.2, eq. eq_F_full, first
+ *                        term, spatial weight 1; Sec. 3.3, eq. D0_expression).
+ *   Gradient             Sec. 3.3, eq. eq_vm_pa_grad.
+ *   Hessian action       Sec. 3.4, eq. eq_vm_pa_hess, with the quadrature data
+ *                        stored once per Newton step and applied matrix-free.
+ *   Hessian diagonal     Sec. 3.4 (Jacobi preconditioning from tensor
+ *                        contractions).
+ *   Solve                Sec. 2.3: x <- x - alpha dx, dx = H^{-1} g by MINRES
+ *                        with Jacobi preconditioning; alpha halved from 1 until
+ *                        det A > 0 at every quadrature point, F < 1.2 F_old and
+ *                        |g| < 1.2 |g_old|; stop when |g|/|g_0| <= eps.
+ *
+ * Conventions for every entry point:
+ *   - Vectors are caller-owned DEVICE buffers of doubles, SoA by component:
+ *     x[c * N_x + g], c < dim.  For a structured box of n_0 x n_1 (x n_2)
+ *     elements the global node g is lexicographic on the (n_k p + 1) grid,
+ *     first axis fastest; local element nodes are lexicographic
+ *     i = i_0 + (p+1) (i_1 + (p+1) i_2).
+ *   - The reference element is [0,1]^d; the 1D basis is the Lagrange basis on
+ *     the p+1 Gauss-Lobatto-Legendre points of [0,1]; quadrature is the
+ *     tensor Gauss-Legendre rule with nq1d points per direction.
+ *   - Fixed (essential) DoFs enter as H_c = P H P + (I - P), g_c = P g, where P
+ *     zeroes the fixed entries.  By default every component of every node on
+ *     the boundary of a structured box is fixed.
+ *   - Calls are asynchronous on the stream given at creation except those
+ *     that return host scalars, which synchronise that stream.
+ *   - Every function returns a tmop_status; on failure tmop_last_error()
+ *     returns a thread-local message.  No C++ exception crosses this ABI.
+ *   - The context owns its workspace (quadrature tensor, element-vector
+ *     scratch, reduction scratch, solver vectors); it never frees or keeps
+ *     pointers the caller passes in, except elem_to_node / ess_mask, which
+ *     must stay valid for the context's lifetime.
+ */
+#ifndef TMOP_H
+#define TMOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TMOP_OK = 0,
+    TMOP_ERR_INVALID_ARG = 1,   /* bad pointer, size, order or combination   */
+    TMOP_ERR_UNSUPPORTED = 2,   /* valid request this build has no kernel for */
+    TMOP_ERR_INVERTED = 3,      /* det A <= 0 at a quadrature point of input */
+    TMOP_ERR_LINESEARCH = 4,    /* no step length accepted                   */
+    TMOP_ERR_NOT_CONVERGED = 5, /* max_newton reached                         */
+    TMOP_ERR_NONFINITE = 6,     /* NaN / Inf in input or iterate              */
+    TMOP_ERR_OOM = 7,           /* device allocation failed                   */
+    TMOP_ERR_BUDGET = 8,        /* request larger than a pool's HBM budget    */
+    TMOP_ERR_BUSY = 9,          /* pool full right now; retry later           */
+    TMOP_ERR_HIP = 10,          /* HIP runtime error                          */
+    TMOP_ERR_STATE = 11         /* call out of order (e.g. apply before setup) */
+} tmop_status;
+
+enum { TMOP_FP64 = 0, TMOP_MIXED = 1 };       /* tmop_params.precision */
+enum { TMOP_ESS_BOUNDARY = 0, TMOP_ESS_NONE = 1, TMOP_ESS_MASK = 2 };
+
+typedef struct tmop_ctx tmop_ctx;
+
+/* Mesh description.  Structured box: elem_to_node == NULL, nx, ny (, nz) > 0.
+ * General mesh: elem_to_node = device int32 array [num_elems][(p+1)^dim]
+ * (lexicographic local order), num_elems and num_nodes set. */
+typedef struct {
+    int dim;                      /* 2 or 3 */
+    int order_p;                  /* 1..4 */
+    int nx, ny, nz;               /* elements per axis (structured box) */
+    int num_elems;                /* general mesh only */
+    int num_nodes;                /* general mesh only: N_x */
+    const int32_t *elem_to_node;  /* device, or NULL for the structured box */
+    int ess_mode;                 /* TMOP_ESS_BOUNDARY (box only) / _NONE / _MASK */
+    const uint8_t *ess_mask;      /* device [dim*N_x], nonzero = fixed, for _MASK */
+} tmop_mesh_desc;
+
+/* Discretisation, target and precision. */
+typedef struct {
+    int metric;     /* 2 (mu_2, dim 2) or 303 (mu_303, dim 3) */
+    int nq1d;       /* quadrature points per direction, p+1 .. p+3 */
+    int has_W;      /* 0: ideal target W = I; 1: use the constant W below */
+    double W[9];    /* constant target matrix, row-major dim x dim, det > 0 */
+    int precision;  /* TMOP_FP64, or TMOP_MIXED: FP32 quadrature tensor and
+                       FP32 Hessian action (FP32 accumulation); energy,
+                       gradient, det, line search and reductions stay FP64 */
+} tmop_params;
+
+typedef struct {
+    double rel_grad_tol;  /* stop when |g_c|/|g_c(x_0)| <= this (e.g. 1e-8)   */
+    int max_newton;       /* Newton iteration cap                             */
+    int max_minres;       /* MINRES iterations per Newton step (e.g. 50)      */
+    double minres_rtol;   /* relative preconditioned-residual tolerance       */
+    int max_halvings;     /* line-search halvings before TMOP_ERR_LINESEARCH  */
+    int jacobi;           /* 1: Jacobi-preconditioned MINRES, 0: plain        */
+    double g0_norm;       /* > 0: |g_c(x_0)| of an earlier run (resume); else computed */
+} tmop_solve_params;
+
+typedef struct {
+    int newton_its;       /* accepted Newton updates   */
+    int minres_its_total; /* MINRES iterations, summed */
+    int halvings_total;   /* line-search halvings      */
+    int status;           /* tmop_status of the solve  */
+    double F0, F;         /* initial and final objective                */
+    double g0_norm, g_norm; /* initial and final |g_c| (l2, all DoFs)  */
+    double t_setup_ms, t_minres_ms, t_linesearch_ms, t_total_ms; /* phase times */
+} tmop_solve_report;
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on the current HIP device; hip_stream may be NULL (the
+ * null stream).  Allocates the workspace for the Hessian tensor of this mesh
+ * (N_e N_q d^2(d^2+1)/2 entries of 8 or 4 bytes) and the element scratch.
+ * Errors: INVALID_ARG, UNSUPPORTED (order/nq combination without a kernel),
+ * OOM. */
+int tmop_create(tmop_ctx **out, const tmop_mesh_desc *mesh, const tmop_params *prm,
+                void *hip_stream);
+int tmop_destroy(tmop_ctx *ctx);
+
+/* Device bytes a context for this mesh/params would allocate (excluding the
+ * solver's work vectors when with_solver == 0). */
+int tmop_workspace_bytes(const tmop_mesh_desc *mesh, const tmop_params *prm, int with_solver,
+                         size_t *bytes);
+
+/* Number of global nodes N_x and DoFs d*N_x of the context's mesh. */
+int tmop_sizes(const tmop_ctx *ctx, int *num_nodes, int *num_dofs);
+
+/* The 1D node positions (p+1 values on [0,1]) the library places element
+ * nodes at, written to host memory; lets a caller build uniform meshes. */
+int tmop_basis_nodes(int order_p, double *nodes_host);
+
+/* ---------------------------------------------------------------------- */
+/* Evaluations (Sec. 3.3, 3.4)                                             */
+/* ---------------------------------------------------------------------- */
+
+/* F(x) to host.  Synchronises.  If det A <= 0 at a quadrature point the
+ * return is TMOP_ERR_INVERTED and *F_host = +inf. */
+int tmop_energy(tmop_ctx *ctx, const double *x_dev, double *F_host);
+
+/* min over all quadrature points of det A(x), to host.  Synchronises. */
+int tmop_min_det(tmop_ctx *ctx, const double *x_dev, double *mindet_host);
+
+/* F and min det A in one pass (both to host).  Synchronises.  Returns
+ * TMOP_ERR_INVERTED (F = +inf) when min det <= 0. */
+int tmop_energy_mindet(tmop_ctx *ctx, const double *x_dev, double *F_host, double *mindet_host);
+
+/* g_c = P dF/dx (device, d*N_x).  Asynchronous. */
+int tmop_gradient(tmop_ctx *ctx, const double *x_dev, double *g_dev);
+
+/* Store the per-quadrature-point Hessian data of F at x (symmetric
+ * d^2 x d^2 tensor times quadrature weight, d^2(d^2+1)/2 entries per point).
+ * Asynchronous.  Subsequent apply/diag calls use it. */
+int tmop_hessian_setup(tmop_ctx *ctx, const double *x_dev);
+
+/* y = H_c v with the data of the last setup.  Asynchronous.  In MIXED
+ * precision the element work runs in FP32; v and y stay FP64 in memory.
+ * v and y must not alias.  Errors: STATE if no setup was done. */
+int tmop_hessian_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev);
+
+/* Diagonal of H_c (fixed entries 1) from the last setup.  Asynchronous. */
+int tmop_hessian_diag(tmop_ctx *ctx, double *d_dev);
+
+/* ---------------------------------------------------------------------- */
+/* Newton-MINRES solve (Sec. 2.3)                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Optimise x in place.  Returns the solve status (also in rep->status). */
+int tmop_solve(tmop_ctx *ctx, double *x_dev_inout, const tmop_solve_params *sp,
+               tmop_solve_report *rep);
+
+/* One Newton step with exactly n_minres MINRES iterations from x, without
+ * the convergence test: setup, diagonal, MINRES, line search and update of x
+ * in place.  Reports as tmop_solve.  Used to time a fixed amount of work. */
+int tmop_newton_step(tmop_ctx *ctx, double *x_dev_inout, int n_minres, int jacobi,
+                     tmop_solve_report *rep);
+
+/* Preconditioned MINRES on H_c dx = b with the last setup (and, when
+ * jacobi != 0, the diagonal of the last setup).  dx is overwritten.
+ * *its receives the iteration count.  Synchronises. */
+int tmop_minres(tmop_ctx *ctx, const double *b_dev, double *dx_dev, int max_its, double rtol,
+                int jacobi, int *its);
+
+/* ---------------------------------------------------------------------- */
+/* Timing helpers                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Run the Hessian action n times on the context's stream and return the
+ * mean device time per call in milliseconds, measured with HIP events
+ * recorded on that stream around the calls (elem_ms: element kernel only,
+ * total_ms: element kernel plus the node gather). */
+int tmop_time_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev, int n, double *elem_ms,
+                    double *total_ms);
+
+/* Thread-local description of the last error. */
+const char *tmop_last_error(void);
+
+/* Library version string. */
+const char *tmop_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMOP_H */

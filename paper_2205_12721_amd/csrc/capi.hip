@@ -1,0 +1,779 @@
+// C ABI of the PA-TMOP library: context, evaluations, Newton-MINRES driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tmop.h"
+#include "ops.hpp"
+#include "tmop_dev.hpp"
+#include "vec.hpp"
+
+using namespace tmop;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,             \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+#define CHK(call)                   \
+    do {                            \
+        int r_ = (call);            \
+        if (r_ != TMOP_OK) return r_; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// 1D bases on [0,1] (Sec. 3.1): Gauss-Lobatto-Legendre nodes for the Lagrange
+// basis, Gauss-Legendre points and weights for quadrature.
+// ---------------------------------------------------------------------------
+
+// P_n(t) and P_n'(t) by the three-term recurrence.
+void legendre(int n, double t, double &P, double &dP)
+{
+    double p0 = 1.0, p1 = t;
+    if (n == 0) {
+        P = 1.0;
+        dP = 0.0;
+        return;
+    }
+    for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    P = p1;
+    // derivative from (1 - t^2) P_n' = n (P_{n-1} - t P_n)
+    dP = (std::fabs(1.0 - t * t) > 0.0) ? n * (p0 - t * p1) / (1.0 - t * t)
+                                         : 0.5 * n * (n + 1.0) * std::pow(t, n + 1);
+}
+
+void gauss_legendre01(int n, double *x, double *w)
+{
+    for (int k = 0; k < n; ++k) {
+        double t = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+        double P, dP;
+        for (int it = 0; it < 100; ++it) {
+            legendre(n, t, P, dP);
+            const double dt = P / dP;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        legendre(n, t, P, dP);
+        // t descends with k: store ascending on [0,1]
+        x[n - 1 - k] = 0.5 * (1.0 + t);
+        w[n - 1 - k] = 1.0 / ((1.0 - t * t) * dP * dP);  // (2/((1-t^2)P'^2)) / 2
+    }
+}
+
+void gll_nodes01(int p, double *x)
+{
+    x[0] = 0.0;
+    x[p] = 1.0;
+    for (int j = 1; j < p; ++j) {
+        // interior nodes: roots of P_p'; Newton with P_p'' from Legendre's equation
+        double t = -std::cos(M_PI * j / p);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(p, t, P, dP);
+            const double d2P = (2.0 * t * dP - p * (p + 1.0) * P) / (1.0 - t * t);
+            const double dt = dP / d2P;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        x[j] = 0.5 * (1.0 + t);
+    }
+    // exact symmetry about 1/2
+    for (int j = 0; j <= p / 2; ++j) {
+        const double a = 0.5 * (x[j] + (1.0 - x[p - j]));
+        x[j] = a;
+        x[p - j] = 1.0 - a;
+    }
+}
+
+// B[q][i] = l_i(chi_q), G[q][i] = l_i'(chi_q) with barycentric weights.
+void lagrange_tables(int p, int nq, const double *xi, const double *chi, double *B, double *G)
+{
+    const int ni = p + 1;
+    std::vector<double> lam(ni);
+    for (int i = 0; i < ni; ++i) {
+        double d = 1.0;
+        for (int m = 0; m < ni; ++m)
+            if (m != i) d *= xi[i] - xi[m];
+        lam[i] = 1.0 / d;
+    }
+    for (int q = 0; q < nq; ++q) {
+        const double t = chi[q];
+        for (int i = 0; i < ni; ++i) {
+            double v = lam[i];
+            for (int m = 0; m < ni; ++m)
+                if (m != i) v *= t - xi[m];
+            double dv = 0.0;
+            for (int r = 0; r < ni; ++r) {
+                if (r == i) continue;
+                double prod = lam[i];
+                for (int m = 0; m < ni; ++m)
+                    if (m != i && m != r) prod *= t - xi[m];
+                dv += prod;
+            }
+            B[q * ni + i] = v;
+            G[q * ni + i] = dv;
+        }
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_HV, SV_V, SV_W, SV_W1, SV_W2, SV_COUNT };
+
+struct tmop_ctx {
+    Geom g{};
+    Tables tb{};
+    Target tg{};
+    Ops ops{};
+    int dim = 0, p = 0, nq = 0, ni = 0, np = 0, nqe = 0, ne = 0, nx = 0, ndof = 0;
+    int precision = TMOP_FP64;
+    int grid = 0;
+    hipStream_t s = nullptr;
+    void *H = nullptr;
+    size_t H_bytes = 0;
+    bool have_setup = false;
+    void *eV = nullptr;
+    size_t eV_bytes = 0;
+    double *part = nullptr;
+    int part_len = 0;
+    double *scal = nullptr;   // device scalars
+    double *hscal = nullptr;  // pinned host mirror
+    int32_t *csr_ptr = nullptr, *csr_ent = nullptr;
+    double *diag = nullptr, *minv = nullptr;
+    bool have_diag = false;
+    double *sv[SV_COUNT] = {};
+    MinresState *mst = nullptr;
+    MinresState *hmst = nullptr;
+};
+
+static int ctx_sizes(const tmop_mesh_desc *m, const tmop_params *prm, long &ne, long &nx,
+                     int &nqe, int &np)
+{
+    if (!m || !prm) return fail(TMOP_ERR_INVALID_ARG, "null mesh or params");
+    if (m->dim != 2 && m->dim != 3) return fail(TMOP_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (m->order_p < 1 || m->order_p > 4)
+        return fail(TMOP_ERR_UNSUPPORTED, "order_p must be in 1..4");
+    const int p = m->order_p, d = m->dim;
+    np = d == 3 ? (p + 1) * (p + 1) * (p + 1) : (p + 1) * (p + 1);
+    if (prm->nq1d < 2 || prm->nq1d > MAXNQ) return fail(TMOP_ERR_INVALID_ARG, "nq1d out of range");
+    nqe = d == 3 ? prm->nq1d * prm->nq1d * prm->nq1d : prm->nq1d * prm->nq1d;
+    if (m->elem_to_node) {
+        if (m->num_elems <= 0 || m->num_nodes <= 0)
+            return fail(TMOP_ERR_INVALID_ARG, "general mesh needs num_elems and num_nodes");
+        ne = m->num_elems;
+        nx = m->num_nodes;
+    } else {
+        if (m->nx <= 0 || m->ny <= 0 || (d == 3 && m->nz <= 0))
+            return fail(TMOP_ERR_INVALID_ARG, "structured box needs nx, ny (, nz) > 0");
+        ne = (long)m->nx * m->ny * (d == 3 ? m->nz : 1);
+        nx = (long)(m->nx * p + 1) * (m->ny * p + 1) * (d == 3 ? (m->nz * p + 1) : 1);
+    }
+    if (ne * (long)np * d > INT_MAX || nx * (long)d > INT_MAX)
+        return fail(TMOP_ERR_INVALID_ARG, "mesh too large for 32-bit indexing");
+    return TMOP_OK;
+}
+
+extern "C" int tmop_workspace_bytes(const tmop_mesh_desc *m, const tmop_params *prm,
+                                    int with_solver, size_t *bytes)
+{
+    long ne, nx;
+    int nqe, np;
+    CHK(ctx_sizes(m, prm, ne, nx, nqe, np));
+    const int d = m->dim, S = d * d * (d * d + 1) / 2;
+    const size_t tb = prm->precision == TMOP_MIXED ? 4 : 8;
+    size_t b = align256((size_t)ne * nqe * S * tb);
+    b += align256((size_t)ne * d * np * 8);
+    b += align256(sizeof(double) * (3 * ((ne + 0) + 1024) + 64));
+    b += 2 * align256((size_t)d * nx * 8);  // diag, minv
+    if (m->elem_to_node) b += align256((nx + 1) * 4) + align256((size_t)ne * np * 4);
+    if (with_solver) b += SV_COUNT * align256((size_t)d * nx * 8);
+    *bytes = b;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_sizes(const tmop_ctx *c, int *num_nodes, int *num_dofs)
+{
+    if (!c) return fail(TMOP_ERR_INVALID_ARG, "null context");
+    if (num_nodes) *num_nodes = c->nx;
+    if (num_dofs) *num_dofs = c->ndof;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_basis_nodes(int p, double *nodes)
+{
+    if (p < 1 || p >= MAXNI || !nodes) return fail(TMOP_ERR_INVALID_ARG, "bad order or pointer");
+    gll_nodes01(p, nodes);
+    return TMOP_OK;
+}
+
+static void free_ctx(tmop_ctx *c)
+{
+    if (!c) return;
+    hipFree(c->H);
+    hipFree(c->eV);
+    hipFree(c->part);
+    hipFree(c->scal);
+    if (c->hscal) hipHostFree(c->hscal);
+    hipFree(c->csr_ptr);
+    hipFree(c->csr_ent);
+    hipFree(c->diag);
+    hipFree(c->minv);
+    for (auto &v : c->sv) hipFree(v);
+    hipFree(c->mst);
+    if (c->hmst) hipHostFree(c->hmst);
+    delete c;
+}
+
+extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_params *prm,
+                           void *stream)
+{
+    if (!out) return fail(TMOP_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    long ne, nx;
+    int nqe, np;
+    CHK(ctx_sizes(m, prm, ne, nx, nqe, np));
+    const int d = m->dim, p = m->order_p, nq = prm->nq1d;
+    if (!((d == 2 && prm->metric == 2) || (d == 3 && prm->metric == 303)))
+        return fail(TMOP_ERR_UNSUPPORTED, "metric must be 2 (dim 2) or 303 (dim 3)");
+    if (prm->precision != TMOP_FP64 && prm->precision != TMOP_MIXED)
+        return fail(TMOP_ERR_INVALID_ARG, "precision must be TMOP_FP64 or TMOP_MIXED");
+    if (m->ess_mode == TMOP_ESS_BOUNDARY && m->elem_to_node)
+        return fail(TMOP_ERR_INVALID_ARG, "TMOP_ESS_BOUNDARY needs the structured box");
+    if (m->ess_mode == TMOP_ESS_MASK && !m->ess_mask)
+        return fail(TMOP_ERR_INVALID_ARG, "TMOP_ESS_MASK needs ess_mask");
+    if (m->ess_mode < 0 || m->ess_mode > 2) return fail(TMOP_ERR_INVALID_ARG, "bad ess_mode");
+    Ops ops;
+    if (!find_ops(d, p, nq, &ops))
+        return fail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d); nq1d must be p+1..p+3");
+
+    tmop_ctx *c = new tmop_ctx();
+    c->ops = ops;
+    c->dim = d;
+    c->p = p;
+    c->nq = nq;
+    c->ni = p + 1;
+    c->np = np;
+    c->nqe = nqe;
+    c->ne = (int)ne;
+    c->nx = (int)nx;
+    c->ndof = (int)(d * nx);
+    c->precision = prm->precision;
+    c->s = (hipStream_t)stream;
+    c->grid = (int)((ne + ops.epb - 1) / ops.epb);
+
+    Geom &g = c->g;
+    g.dim = d;
+    g.p = p;
+    g.ne = (int)ne;
+    g.nx = (int)nx;
+    if (!m->elem_to_node) {
+        g.nel[0] = m->nx;
+        g.nel[1] = m->ny;
+        g.nel[2] = d == 3 ? m->nz : 1;
+        for (int k = 0; k < 3; ++k) g.M[k] = g.nel[k] * p + 1;
+        if (d == 2) g.M[2] = 1;
+    }
+    g.e2n = m->elem_to_node;
+    g.ess_mode = m->ess_mode;
+    g.ess = m->ess_mask;
+
+    // tables
+    double xi[MAXNI], chi[MAXNQ], w[MAXNQ];
+    gll_nodes01(p, xi);
+    gauss_legendre01(nq, chi, w);
+    lagrange_tables(p, nq, xi, chi, c->tb.B, c->tb.G);
+    for (int q = 0; q < nq; ++q) c->tb.w[q] = w[q];
+
+    // target
+    Target &t = c->tg;
+    t.metric = prm->metric;
+    t.ideal = prm->has_W ? 0 : 1;
+    t.detW = 1.0;
+    for (int k = 0; k < 9; ++k) t.Winv[k] = 0.0;
+    if (prm->has_W) {
+        const double *W = prm->W;
+        double det, inv[9];
+        if (d == 2) {
+            det = W[0] * W[3] - W[1] * W[2];
+            inv[0] = W[3] / det;
+            inv[1] = -W[1] / det;
+            inv[2] = -W[2] / det;
+            inv[3] = W[0] / det;
+        } else {
+            const double c00 = W[4] * W[8] - W[5] * W[7], c01 = W[5] * W[6] - W[3] * W[8],
+                         c02 = W[3] * W[7] - W[4] * W[6];
+            det = W[0] * c00 + W[1] * c01 + W[2] * c02;
+            // inverse = adj / det, adj = cof^T
+            inv[0] = c00 / det;
+            inv[3] = c01 / det;
+            inv[6] = c02 / det;
+            inv[1] = (W[2] * W[7] - W[1] * W[8]) / det;
+            inv[4] = (W[0] * W[8] - W[2] * W[6]) / det;
+            inv[7] = (W[1] * W[6] - W[0] * W[7]) / det;
+            inv[2] = (W[1] * W[5] - W[2] * W[4]) / det;
+            inv[5] = (W[2] * W[3] - W[0] * W[5]) / det;
+            inv[8] = (W[0] * W[4] - W[1] * W[3]) / det;
+        }
+        if (!(det > 0.0) || !std::isfinite(det)) {
+            delete c;
+            return fail(TMOP_ERR_INVALID_ARG, "target W must have det > 0");
+        }
+        t.detW = det;
+        for (int k = 0; k < d * d; ++k) t.Winv[k] = inv[k];
+    }
+
+    // workspace
+    const int S = d * d * (d * d + 1) / 2;
+    const size_t tbytes = c->precision == TMOP_MIXED ? 4 : 8;
+    c->H_bytes = (size_t)ne * nqe * S * tbytes;
+    c->eV_bytes = (size_t)ne * d * np * 8;
+    c->part_len = 3 * std::max(c->grid, 1024) + 64;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes)                                       \
+    if (e == hipSuccess) e = hipMalloc((void **)&(ptr), (bytes));
+    ALLOC(c->H, c->H_bytes);
+    ALLOC(c->eV, c->eV_bytes);
+    ALLOC(c->part, sizeof(double) * c->part_len);
+    ALLOC(c->scal, sizeof(double) * 64);
+    ALLOC(c->diag, sizeof(double) * c->ndof);
+    ALLOC(c->minv, sizeof(double) * c->ndof);
+    ALLOC(c->mst, sizeof(MinresState));
+#undef ALLOC
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscal, sizeof(double) * 64, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmst, sizeof(MinresState), 0);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(e == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,
+                    std::string("workspace allocation: ") + hipGetErrorString(e));
+    }
+
+    // general mesh: node -> (element, local) CSR for the deterministic G^T
+    if (m->elem_to_node) {
+        std::vector<int32_t> e2n((size_t)ne * np);
+        e = hipMemcpy(e2n.data(), m->elem_to_node, e2n.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            free_ctx(c);
+            return fail(TMOP_ERR_HIP, "copying elem_to_node");
+        }
+        std::vector<int32_t> ptr(nx + 1, 0), ent(e2n.size());
+        for (size_t k = 0; k < e2n.size(); ++k) {
+            if (e2n[k] < 0 || e2n[k] >= nx) {
+                free_ctx(c);
+                return fail(TMOP_ERR_INVALID_ARG, "elem_to_node entry out of range");
+            }
+            ptr[e2n[k] + 1]++;
+        }
+        for (long k = 0; k < nx; ++k) ptr[k + 1] += ptr[k];
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (size_t k = 0; k < e2n.size(); ++k) ent[fill[e2n[k]]++] = (int32_t)k;
+        e = hipMalloc((void **)&c->csr_ptr, ptr.size() * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->csr_ent, ent.size() * 4);
+        if (e == hipSuccess) e = hipMemcpy(c->csr_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_ctx(c);
+            return fail(TMOP_ERR_HIP, "uploading node map");
+        }
+    }
+    *out = c;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_destroy(tmop_ctx *c)
+{
+    if (!c) return TMOP_OK;
+    hipStreamSynchronize(c->s);
+    free_ctx(c);
+    return TMOP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Evaluations
+// ---------------------------------------------------------------------------
+
+static int energy_mindet_impl(tmop_ctx *c, const double *x, double *F, double *mindet)
+{
+    c->ops.energy(c->grid, c->s, c->g, c->tb, c->tg, x, c->part);
+    launch_reduce3(c->part, c->grid, c->scal, c->s);
+    HIPCHK(hipMemcpyAsync(c->hscal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    const double bad = c->hscal[2];
+    if (mindet) *mindet = c->hscal[1];
+    if (F) *F = bad > 0.0 ? INFINITY : c->hscal[0];
+    if (bad > 0.0) return fail(TMOP_ERR_INVERTED, "det T <= 0 at a quadrature point");
+    return TMOP_OK;
+}
+
+extern "C" int tmop_energy(tmop_ctx *c, const double *x, double *F)
+{
+    if (!c || !x || !F) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    return energy_mindet_impl(c, x, F, nullptr);
+}
+
+extern "C" int tmop_min_det(tmop_ctx *c, const double *x, double *md)
+{
+    if (!c || !x || !md) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    const int r = energy_mindet_impl(c, x, nullptr, md);
+    return r == TMOP_ERR_INVERTED ? TMOP_OK : r;
+}
+
+extern "C" int tmop_energy_mindet(tmop_ctx *c, const double *x, double *F, double *md)
+{
+    if (!c || !x) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    return energy_mindet_impl(c, x, F, md);
+}
+
+static void gradient_impl(tmop_ctx *c, const double *x, double *g)
+{
+    c->ops.gradient(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->eV, c->part);
+    launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, g, 0, nullptr, c->s);
+}
+
+extern "C" int tmop_gradient(tmop_ctx *c, const double *x, double *g)
+{
+    if (!c || !x || !g) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    gradient_impl(c, x, g);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
+static void setup_impl(tmop_ctx *c, const double *x)
+{
+    if (c->precision == TMOP_MIXED)
+        c->ops.setup32(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, c->part);
+    else
+        c->ops.setup64(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, c->part);
+    c->have_setup = true;
+    c->have_diag = false;
+}
+
+extern "C" int tmop_hessian_setup(tmop_ctx *c, const double *x)
+{
+    if (!c || !x) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    setup_impl(c, x);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
+static void apply_elem(tmop_ctx *c, const double *v)
+{
+    if (c->precision == TMOP_MIXED)
+        c->ops.apply32(c->grid, c->s, c->g, c->tb, (const float *)c->H, v, (float *)c->eV);
+    else
+        c->ops.apply64(c->grid, c->s, c->g, c->tb, (const double *)c->H, v, (double *)c->eV);
+}
+
+static void apply_gather(tmop_ctx *c, const double *v, double *y)
+{
+    launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, c->precision == TMOP_MIXED, y, 2, v, c->s);
+}
+
+extern "C" int tmop_hessian_apply(tmop_ctx *c, const double *v, double *y)
+{
+    if (!c || !v || !y) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    if (v == y) return fail(TMOP_ERR_INVALID_ARG, "v and y must not alias");
+    if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
+    apply_elem(c, v);
+    apply_gather(c, v, y);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
+static void diag_impl(tmop_ctx *c, double *d)
+{
+    if (c->precision == TMOP_MIXED)
+        c->ops.diag32(c->grid, c->s, c->g, c->tb, (const float *)c->H, (double *)c->eV);
+    else
+        c->ops.diag64(c->grid, c->s, c->g, c->tb, (const double *)c->H, (double *)c->eV);
+    launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, d, 1, nullptr, c->s);
+}
+
+extern "C" int tmop_hessian_diag(tmop_ctx *c, double *d)
+{
+    if (!c || !d) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
+    diag_impl(c, d);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
+extern "C" int tmop_time_apply(tmop_ctx *c, const double *v, double *y, int n, double *elem_ms,
+                               double *total_ms)
+{
+    if (!c || !v || !y || n <= 0) return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
+    std::vector<hipEvent_t> ev(3 * n);
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    for (int k = 0; k < n; ++k) {
+        HIPCHK(hipEventRecord(ev[3 * k], c->s));
+        apply_elem(c, v);
+        HIPCHK(hipEventRecord(ev[3 * k + 1], c->s));
+        apply_gather(c, v, y);
+        HIPCHK(hipEventRecord(ev[3 * k + 2], c->s));
+    }
+    HIPCHK(hipStreamSynchronize(c->s));
+    double se = 0.0, st = 0.0;
+    for (int k = 0; k < n; ++k) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
+        HIPCHK(hipEventElapsedTime(&b, ev[3 * k], ev[3 * k + 2]));
+        se += a;
+        st += b;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    if (elem_ms) *elem_ms = se / n;
+    if (total_ms) *total_ms = st / n;
+    return TMOP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solver
+// ---------------------------------------------------------------------------
+
+static int ensure_solver(tmop_ctx *c)
+{
+    if (c->sv[0]) return TMOP_OK;
+    for (int k = 0; k < SV_COUNT; ++k) HIPCHK(hipMalloc((void **)&c->sv[k], sizeof(double) * c->ndof));
+    return TMOP_OK;
+}
+
+// |a|^2 to host (synchronises).
+static int dot_host(tmop_ctx *c, const double *a, const double *b, double *out)
+{
+    launch_dot(c->ndof, a, b, c->part, c->scal + 8, c->s);
+    HIPCHK(hipMemcpyAsync(c->hscal + 8, c->scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    *out = c->hscal[8];
+    return TMOP_OK;
+}
+
+static void make_jacobi(tmop_ctx *c)
+{
+    diag_impl(c, c->diag);
+    launch_absmax(c->ndof, c->diag, c->part, c->scal + 9, c->s);
+    launch_jacobi(c->ndof, c->diag, c->scal + 9, c->minv, c->s);
+    c->have_diag = true;
+}
+
+// MINRES on H_c dx = b.  Buffers from the solver pool.
+static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
+                       bool jacobi, int check_every, int *its_out)
+{
+    CHK(ensure_solver(c));
+    const long n = c->ndof;
+    double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *Y = c->sv[SV_Y], *HV = c->sv[SV_HV];
+    double *V = c->sv[SV_V], *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
+    const double *minv = jacobi ? c->minv : nullptr;
+    mr_init(n, b, minv, R1, R2, Y, dx, W, W1, W2, c->part, c->mst, rtol, c->s);
+    for (int j = 0; j < max_its; ++j) {
+        mr_v(n, j, c->mst, Y, V, c->s);
+        apply_elem(c, V);
+        apply_gather(c, V, HV);
+        mr_lanczos1(n, j, c->mst, HV, R1, V, c->part, c->s);
+        mr_lanczos2(n, j, c->mst, HV, R2, minv, R1, c->part, c->s);
+        // new w goes to the old w1 buffer; (w1, w2) of the formula = (old w2, old w)
+        mr_update(n, j, c->mst, V, W2, W, W1, dx, c->s);
+        double *oY = Y, *oR1 = R1, *oR2 = R2, *oHV = HV;
+        Y = oR1;
+        R1 = oR2;
+        R2 = oHV;
+        HV = oY;
+        double *oW = W, *oW1 = W1, *oW2 = W2;
+        W1 = oW2;
+        W2 = oW;
+        W = oW1;
+        if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
+            HIPCHK(hipMemcpyAsync(c->hmst, c->mst, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
+            if (c->hmst->stop != 0x7fffffff) break;
+        }
+    }
+    // keep the rotated pointers consistent for the next call
+    c->sv[SV_R1] = R1;
+    c->sv[SV_R2] = R2;
+    c->sv[SV_Y] = Y;
+    c->sv[SV_HV] = HV;
+    c->sv[SV_W] = W;
+    c->sv[SV_W1] = W1;
+    c->sv[SV_W2] = W2;
+    HIPCHK(hipMemcpyAsync(c->hmst, c->mst, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    HIPCHK(hipGetLastError());
+    if (its_out) *its_out = c->hmst->its;
+    if (c->hmst->indefinite_precond) return fail(TMOP_ERR_NONFINITE, "preconditioner not SPD");
+    return TMOP_OK;
+}
+
+extern "C" int tmop_minres(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
+                           int jacobi, int *its)
+{
+    if (!c || !b || !dx || max_its < 0) return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
+    if (jacobi && !c->have_diag) make_jacobi(c);
+    return minres_impl(c, b, dx, max_its, rtol, jacobi != 0, 8, its);
+}
+
+static double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// One Newton update of x (in place): setup, Jacobi, MINRES, line search.
+// F, gn, g (in c->sv[SV_G]) describe x on entry and are updated on accept.
+static int newton_update(tmop_ctx *c, double *x, double &F, double &gn, int max_minres,
+                         double rtol, int max_halvings, bool jacobi, int check_every,
+                         tmop_solve_report *rep)
+{
+    double t0 = now_ms();
+    setup_impl(c, x);
+    if (jacobi) make_jacobi(c);
+    HIPCHK(hipStreamSynchronize(c->s));
+    double t1 = now_ms();
+    int its = 0;
+    CHK(minres_impl(c, c->sv[SV_G], c->sv[SV_DX], max_minres, rtol, jacobi, check_every, &its));
+    double t2 = now_ms();
+    rep->minres_its_total += its;
+    double alpha = 1.0;
+    bool ok = false;
+    double Ft = 0.0, gtn = 0.0;
+    for (int h = 0; h <= max_halvings; ++h) {
+        launch_step(c->ndof, x, c->sv[SV_DX], alpha, c->sv[SV_XT], c->s);
+        double md = 0.0;
+        const int r = energy_mindet_impl(c, c->sv[SV_XT], &Ft, &md);
+        if (r != TMOP_OK && r != TMOP_ERR_INVERTED) return r;
+        if (r == TMOP_OK && md > 0.0 && Ft < 1.2 * F) {
+            gradient_impl(c, c->sv[SV_XT], c->sv[SV_GT]);
+            double g2;
+            CHK(dot_host(c, c->sv[SV_GT], c->sv[SV_GT], &g2));
+            gtn = std::sqrt(g2);
+            if (gtn < 1.2 * gn) {
+                ok = true;
+                break;
+            }
+        }
+        alpha *= 0.5;
+        rep->halvings_total++;
+    }
+    double t3 = now_ms();
+    rep->t_setup_ms += t1 - t0;
+    rep->t_minres_ms += t2 - t1;
+    rep->t_linesearch_ms += t3 - t2;
+    if (!ok) return fail(TMOP_ERR_LINESEARCH, "line search found no admissible step");
+    HIPCHK(hipMemcpyAsync(x, c->sv[SV_XT], sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->s));
+    std::swap(c->sv[SV_G], c->sv[SV_GT]);
+    F = Ft;
+    gn = gtn;
+    rep->newton_its++;
+    return TMOP_OK;
+}
+
+static int solve_start(tmop_ctx *c, double *x, double &F, double &gn, tmop_solve_report *rep)
+{
+    CHK(ensure_solver(c));
+    double xx;
+    CHK(dot_host(c, x, x, &xx));
+    if (!std::isfinite(xx)) return fail(TMOP_ERR_NONFINITE, "non-finite node coordinates");
+    double md;
+    const int r = energy_mindet_impl(c, x, &F, &md);
+    if (r != TMOP_OK) return r;
+    if (!(md > 0.0)) return fail(TMOP_ERR_INVERTED, "det A <= 0 at a quadrature point");
+    gradient_impl(c, x, c->sv[SV_G]);
+    double g2;
+    CHK(dot_host(c, c->sv[SV_G], c->sv[SV_G], &g2));
+    gn = std::sqrt(g2);
+    rep->F0 = F;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_solve(tmop_ctx *c, double *x, const tmop_solve_params *sp,
+                          tmop_solve_report *rep)
+{
+    if (!c || !x || !sp || !rep) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    std::memset(rep, 0, sizeof(*rep));
+    const double t0 = now_ms();
+    double F = 0.0, gn = 0.0;
+    int r = solve_start(c, x, F, gn, rep);
+    if (r != TMOP_OK) {
+        rep->status = r;
+        return r;
+    }
+    const double n0 = sp->g0_norm > 0.0 ? sp->g0_norm : gn;
+    rep->g0_norm = n0;
+    int status = TMOP_ERR_NOT_CONVERGED;
+    for (int it = 0; it <= sp->max_newton; ++it) {
+        if (n0 == 0.0 || F == 0.0 || gn <= sp->rel_grad_tol * n0) {
+            status = TMOP_OK;
+            break;
+        }
+        if (it == sp->max_newton) break;
+        r = newton_update(c, x, F, gn, sp->max_minres, sp->minres_rtol, sp->max_halvings,
+                          sp->jacobi != 0, 8, rep);
+        if (r != TMOP_OK) {
+            status = r;
+            break;
+        }
+    }
+    rep->F = F;
+    rep->g_norm = gn;
+    rep->status = status;
+    rep->t_total_ms = now_ms() - t0;
+    if (status != TMOP_OK && status != TMOP_ERR_NOT_CONVERGED && status != TMOP_ERR_LINESEARCH)
+        return status;
+    if (status == TMOP_ERR_NOT_CONVERGED) g_err = "max_newton reached";
+    return status;
+}
+
+extern "C" int tmop_newton_step(tmop_ctx *c, double *x, int n_minres, int jacobi,
+                                tmop_solve_report *rep)
+{
+    if (!c || !x || !rep || n_minres < 0) return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    std::memset(rep, 0, sizeof(*rep));
+    const double t0 = now_ms();
+    double F = 0.0, gn = 0.0;
+    int r = solve_start(c, x, F, gn, rep);
+    if (r == TMOP_OK) {
+        rep->g0_norm = gn;
+        // fixed amount of linear work: rtol 0, no early exit checks
+        r = newton_update(c, x, F, gn, n_minres, 0.0, 30, jacobi != 0, 0, rep);
+    }
+    rep->F = F;
+    rep->g_norm = gn;
+    rep->status = r;
+    rep->t_total_ms = now_ms() - t0;
+    return r;
+}
+
+extern "C" const char *tmop_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *tmop_version(void) { return "tmop-mi355x 0.1 (gfx950)"; }

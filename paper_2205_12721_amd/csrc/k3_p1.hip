@@ -1,0 +1,17 @@
+// Hex kernel instantiations for order p = 1, n_q = p+1 .. p+3.
+#include "kernels3d.hpp"
+#include "ops.hpp"
+
+namespace tmop {
+
+bool ops3_p1(int nq, Ops *out)
+{
+    switch (nq) {
+    case 1 + 1: TMOP_OPS_BODY(k3, S3, 1, 1 + 1)
+    case 1 + 2: TMOP_OPS_BODY(k3, S3, 1, 1 + 2)
+    case 1 + 3: TMOP_OPS_BODY(k3, S3, 1, 1 + 3)
+    default: return false;
+    }
+}
+
+}  // namespace tmop

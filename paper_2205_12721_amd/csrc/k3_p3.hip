@@ -1,0 +1,17 @@
+// Hex kernel instantiations for order p = 3, n_q = p+1 .. p+3.
+#include "kernels3d.hpp"
+#include "ops.hpp"
+
+namespace tmop {
+
+bool ops3_p3(int nq, Ops *out)
+{
+    switch (nq) {
+    case 3 + 1: TMOP_OPS_BODY(k3, S3, 3, 3 + 1)
+    case 3 + 2: TMOP_OPS_BODY(k3, S3, 3, 3 + 2)
+    case 3 + 3: TMOP_OPS_BODY(k3, S3, 3, 3 + 3)
+    default: return false;
+    }
+}
+
+}  // namespace tmop

@@ -1,0 +1,17 @@
+// Hex kernel instantiations for order p = 4, n_q = p+1 .. p+3.
+#include "kernels3d.hpp"
+#include "ops.hpp"
+
+namespace tmop {
+
+bool ops3_p4(int nq, Ops *out)
+{
+    switch (nq) {
+    case 4 + 1: TMOP_OPS_BODY(k3, S3, 4, 4 + 1)
+    case 4 + 2: TMOP_OPS_BODY(k3, S3, 4, 4 + 2)
+    case 4 + 3: TMOP_OPS_BODY(k3, S3, 4, 4 + 3)
+    default: return false;
+    }
+}
+
+}  // namespace tmop

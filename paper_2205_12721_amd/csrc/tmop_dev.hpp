@@ -1,0 +1,308 @@
+// Device-side building blocks of the PA-TMOP kernels for gfx950.
+//
+// One workgroup of BLOCK = 256 lanes (four wave64s) processes EPB elements;
+// every stage is a flattened loop over (element, index) pairs with the
+// innermost index fastest, so the lanes of a wave touch consecutive LDS
+// words and consecutive HBM addresses.  Element data (nodes, sum-factorized
+// partial contractions, quadrature values) live in LDS; the quadrature
+// tensor streams from HBM once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmop {
+
+constexpr int BLOCK = 256;
+constexpr int MAXNI = 9;   // p <= 8
+constexpr int MAXNQ = 10;  // up to 10 points per direction
+
+// Mesh geometry passed by value to every kernel.
+struct Geom {
+    int dim;
+    int p;
+    int ne;                // number of elements
+    int nel[3];            // elements per axis (structured box)
+    int M[3];              // grid nodes per axis, nel*p + 1
+    int nx;                // global nodes N_x
+    const int32_t *e2n;    // general mesh connectivity or nullptr
+    int ess_mode;          // 0 box boundary, 1 none, 2 mask
+    const uint8_t *ess;    // [dim * nx] for mode 2
+};
+
+// 1D tables: B[q][i] = l_i(chi_q), G[q][i] = l_i'(chi_q), w[q] (Sec. 3.1, eq. eq_B_G_1D).
+struct Tables {
+    double B[MAXNQ * MAXNI];
+    double G[MAXNQ * MAXNI];
+    double w[MAXNQ];
+};
+
+// Constant target: W^{-1} (row-major) and det W; ideal != 0 means W = I.
+struct Target {
+    double Winv[9];
+    double detW;
+    int ideal;
+    int metric;
+};
+
+// Symmetric packing of a d^2 x d^2 tensor: entry (r, s), r <= s, row-major
+// upper triangle.
+template <int D2>
+__host__ __device__ constexpr int sym_index(int r, int s)
+{
+    return r <= s ? r * D2 - (r * (r - 1)) / 2 + (s - r) : s * D2 - (s * (s - 1)) / 2 + (r - s);
+}
+
+// ------------------------------------------------------------------------
+// Fixed-DoF predicate
+// ------------------------------------------------------------------------
+
+__device__ inline bool box_boundary(const Geom &g, int gx, int gy, int gz)
+{
+    bool b = gx == 0 || gx == g.M[0] - 1 || gy == 0 || gy == g.M[1] - 1;
+    if (g.dim == 3) b = b || gz == 0 || gz == g.M[2] - 1;
+    return b;
+}
+
+// Is component c of global node `node` (grid coordinates gx,gy,gz when the
+// mesh is a box) fixed?
+__device__ inline bool is_fixed(const Geom &g, int c, int node, int gx, int gy, int gz)
+{
+    if (g.ess_mode == 1) return false;
+    if (g.ess_mode == 2) return g.ess[(size_t)c * g.nx + node] != 0;
+    return box_boundary(g, gx, gy, gz);
+}
+
+// ------------------------------------------------------------------------
+// Block reductions (deterministic order)
+// ------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum over the workgroup; result valid in thread 0.
+__device__ inline double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+    return s;
+}
+
+__device__ inline double block_min(double v, double *red)
+{
+    v = wave_min(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    if (threadIdx.x == 0)
+        for (int k = 1; k < BLOCK / 64; ++k) s = fmin(s, red[k]);
+    return s;
+}
+
+// ------------------------------------------------------------------------
+// Quality metrics at one point (T = A W^{-1}); closed-form derivatives of
+// mu_2 = |T|^2/(2 tau) - 1 and mu_303 = |T|^2/(3 tau^{2/3}) - 1.
+//
+// With I1 = |T|^2, tau = det T and C = cof T = d tau / dT:
+//   dmu   = cT T + cC C
+//   d2mu  = c_id Id + c_tc (T (x) C + C (x) T) + c_cc C (x) C + c_dc dC/dT
+// ------------------------------------------------------------------------
+
+struct MetricCoef {
+    double mu, cT, cC, c_id, c_tc, c_cc, c_dc;
+};
+
+__device__ inline MetricCoef metric_coef(int metric, double I1, double tau)
+{
+    MetricCoef m;
+    if (metric == 2) {
+        const double it = 1.0 / tau;
+        m.mu = 0.5 * I1 * it - 1.0;
+        m.cT = it;
+        m.cC = -0.5 * I1 * it * it;
+        m.c_id = it;
+        m.c_tc = -it * it;
+        m.c_cc = I1 * it * it * it;
+        m.c_dc = -0.5 * I1 * it * it;
+    } else {
+        const double r = 1.0 / cbrt(tau);  // tau^{-1/3}
+        const double r2 = r * r;           // tau^{-2/3}
+        const double r5 = r2 * r2 * r;     // tau^{-5/3}
+        const double r8 = r5 * r2 * r;     // tau^{-8/3}
+        m.mu = I1 * r2 / 3.0 - 1.0;
+        m.cT = 2.0 * r2 / 3.0;
+        m.cC = -2.0 * I1 * r5 / 9.0;
+        m.c_id = 2.0 * r2 / 3.0;
+        m.c_tc = -4.0 * r5 / 9.0;
+        m.c_cc = 10.0 * I1 * r8 / 27.0;
+        m.c_dc = -2.0 * I1 * r5 / 9.0;
+    }
+    return m;
+}
+
+template <int D>
+__device__ inline void apply_winv(const Target &t, const double *A, double *T)
+{
+    if (t.ideal) {
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) T[k] = A[k];
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < D; ++n) s += A[a * D + n] * t.Winv[n * D + k];
+            T[a * D + k] = s;
+        }
+}
+
+template <int D>
+__device__ inline double det_cof(const double *T, double *C)
+{
+    if constexpr (D == 2) {
+        C[0] = T[3];
+        C[1] = -T[2];
+        C[2] = -T[1];
+        C[3] = T[0];
+        return T[0] * T[3] - T[1] * T[2];
+    } else {
+        C[0] = T[4] * T[8] - T[5] * T[7];
+        C[1] = T[5] * T[6] - T[3] * T[8];
+        C[2] = T[3] * T[7] - T[4] * T[6];
+        C[3] = T[2] * T[7] - T[1] * T[8];
+        C[4] = T[0] * T[8] - T[2] * T[6];
+        C[5] = T[1] * T[6] - T[0] * T[7];
+        C[6] = T[1] * T[5] - T[2] * T[4];
+        C[7] = T[2] * T[3] - T[0] * T[5];
+        C[8] = T[0] * T[4] - T[1] * T[3];
+        return T[0] * C[0] + T[1] * C[1] + T[2] * C[2];
+    }
+}
+
+template <int D>
+__device__ inline double det_only(const double *A)
+{
+    if constexpr (D == 2) return A[0] * A[3] - A[1] * A[2];
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// dC_{(ij)} / dT_{(kl)}.  3D: eps_ikm eps_jln T_mn, i.e. nonzero only for
+// i != k and j != l, with m, n the remaining indices.  2D: constant.
+template <int D>
+__device__ inline double dcof(const double *T, int r, int s)
+{
+    const int i = r / D, j = r % D, k = s / D, l = s % D;
+    if constexpr (D == 2) {
+        if (i != k && j != l) return (i == j) ? 1.0 : -1.0;
+        return 0.0;
+    } else {
+        if (i == k || j == l) return 0.0;
+        const int m = 3 - i - k, n = 3 - j - l;
+        const double sik = (k == (i + 1) % 3) ? 1.0 : -1.0;
+        const double sjl = (l == (j + 1) % 3) ? 1.0 : -1.0;
+        return sik * sjl * T[m * 3 + n];
+    }
+}
+
+// mu and z * P with P = dmu/dT W^{-T}.  Returns false if tau <= 0.
+template <int D>
+__device__ inline bool metric_first(const Target &t, const double *A, double z, double *mu,
+                                    double *P)
+{
+    double T[D * D], C[D * D];
+    apply_winv<D>(t, A, T);
+    const double tau = det_cof<D>(T, C);
+    if (!(tau > 0.0)) return false;
+    double I1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) I1 += T[k] * T[k];
+    const MetricCoef m = metric_coef(t.metric, I1, tau);
+    *mu = m.mu;
+    double dmu[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) dmu[k] = m.cT * T[k] + m.cC * C[k];
+    if (t.ideal) {
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) P[k] = z * dmu[k];
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int n = 0; n < D; ++n) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += dmu[a * D + k] * t.Winv[n * D + k];
+                P[a * D + n] = z * s;
+            }
+    }
+    return true;
+}
+
+// z * H_A, packed symmetric (D^2 (D^2+1)/2 entries), where
+// H_A[an][bp] = sum_kl d2mu[ak][bl] Winv_nk Winv_pl.  Returns false if tau <= 0.
+template <int D>
+__device__ inline bool metric_second(const Target &t, const double *A, double z, double *Hp)
+{
+    constexpr int D2 = D * D;
+    double T[D2], C[D2];
+    apply_winv<D>(t, A, T);
+    const double tau = det_cof<D>(T, C);
+    if (!(tau > 0.0)) return false;
+    double I1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D2; ++k) I1 += T[k] * T[k];
+    const MetricCoef m = metric_coef(t.metric, I1, tau);
+    if (t.ideal) {
+#pragma unroll
+        for (int r = 0; r < D2; ++r)
+#pragma unroll
+            for (int s = r; s < D2; ++s) {
+                double v = m.c_tc * (T[r] * C[s] + C[r] * T[s]) + m.c_cc * C[r] * C[s] +
+                           m.c_dc * dcof<D>(T, r, s);
+                if (r == s) v += m.c_id;
+                Hp[sym_index<D2>(r, s)] = z * v;
+            }
+        return true;
+    }
+    // general constant W: each entry H_A[an][bp] = sum_kl d2mu[ak][bl] Winv_nk Winv_pl,
+    // with d2mu evaluated entry by entry (keeps register use low)
+    for (int r = 0; r < D2; ++r)
+        for (int s = r; s < D2; ++s) {
+            const int a = r / D, n = r % D, b = s / D, p = s % D;
+            double acc = 0.0;
+            for (int k = 0; k < D; ++k)
+                for (int l = 0; l < D; ++l) {
+                    const int rr = a * D + k, ss = b * D + l;
+                    double v = m.c_tc * (T[rr] * C[ss] + C[rr] * T[ss]) + m.c_cc * C[rr] * C[ss] +
+                               m.c_dc * dcof<D>(T, rr, ss);
+                    if (rr == ss) v += m.c_id;
+                    acc += v * t.Winv[n * D + k] * t.Winv[p * D + l];
+                }
+            Hp[sym_index<D2>(r, s)] = z * acc;
+        }
+    return true;
+}
+
+}  // namespace tmop

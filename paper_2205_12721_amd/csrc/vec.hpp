@@ -1,0 +1,43 @@
+// Host launchers of the node-level kernels (vec.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tmop_dev.hpp"
+
+namespace tmop {
+
+// Device-resident scalar state of one MINRES solve.
+struct MinresState {
+    double tmp;
+    double beta1, beta, oldb, alpha, dbar, eps, oldeps, phibar, phi, cs, sn, gamma, delta, rtol;
+    int its;
+    int stop;  // last iteration index that runs; INT_MAX while running
+    int indefinite_precond;
+    int pad;
+};
+
+void launch_gather(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
+                   bool fp32, double *out, int fix_mode, const double *src, hipStream_t s);
+void launch_reduce3(const double *part, int nb, double *out, hipStream_t s);
+void launch_reduce_sum(const double *part, int nb, double *out, hipStream_t s);
+int reduce_blocks(long n);
+void launch_dot(long n, const double *a, const double *b, double *part, double *out,
+                hipStream_t s);
+void launch_absmax(long n, const double *a, double *part, double *out, hipStream_t s);
+void launch_step(long n, const double *x, const double *dx, double alpha, double *xt,
+                 hipStream_t s);
+void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hipStream_t s);
+
+void mr_init(long n, const double *b, const double *minv, double *r1, double *r2, double *y,
+             double *x, double *w, double *w1, double *w2, double *part, MinresState *st,
+             double rtol, hipStream_t s);
+void mr_v(long n, int j, const MinresState *st, const double *y, double *v, hipStream_t s);
+void mr_lanczos1(long n, int j, MinresState *st, double *hv, const double *r1, const double *v,
+                 double *part, hipStream_t s);
+void mr_lanczos2(long n, int j, MinresState *st, double *hv, const double *r2, const double *minv,
+                 double *z, double *part, hipStream_t s);
+void mr_update(long n, int j, const MinresState *st, const double *v, const double *w1,
+               const double *w2, double *wout, double *x, hipStream_t s);
+
+}  // namespace tmop

@@ -1,0 +1,293 @@
+"""Python binding of libtmop_hip.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors (device memory owned by the caller) to pointers, passes the current
+torch stream, and turns status codes into exceptions.  There is no fallback:
+if the library is missing or no GPU is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmop_hip.so")
+
+TMOP_FP64, TMOP_MIXED = 0, 1
+ESS_BOUNDARY, ESS_NONE, ESS_MASK = 0, 1, 2
+
+STATUS = {
+    0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_INVERTED",
+    4: "ERR_LINESEARCH", 5: "ERR_NOT_CONVERGED", 6: "ERR_NONFINITE", 7: "ERR_OOM",
+    8: "ERR_BUDGET", 9: "ERR_BUSY", 10: "ERR_HIP", 11: "ERR_STATE",
+}
+OK, ERR_INVERTED, ERR_LINESEARCH, ERR_NOT_CONVERGED, ERR_NONFINITE = 0, 3, 4, 5, 6
+
+
+class TmopError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("order_p", ctypes.c_int), ("nx", ctypes.c_int),
+                ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("num_elems", ctypes.c_int),
+                ("num_nodes", ctypes.c_int), ("elem_to_node", ctypes.c_void_p),
+                ("ess_mode", ctypes.c_int), ("ess_mask", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("metric", ctypes.c_int), ("nq1d", ctypes.c_int), ("has_W", ctypes.c_int),
+                ("W", ctypes.c_double * 9), ("precision", ctypes.c_int)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("rel_grad_tol", ctypes.c_double), ("max_newton", ctypes.c_int),
+                ("max_minres", ctypes.c_int), ("minres_rtol", ctypes.c_double),
+                ("max_halvings", ctypes.c_int), ("jacobi", ctypes.c_int),
+                ("g0_norm", ctypes.c_double)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int), ("minres_its_total", ctypes.c_int),
+                ("halvings_total", ctypes.c_int), ("status", ctypes.c_int),
+                ("F0", ctypes.c_double), ("F", ctypes.c_double), ("g0_norm", ctypes.c_double),
+                ("g_norm", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
+                ("t_minres_ms", ctypes.c_double), ("t_linesearch_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, "?")
+        return d
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_lib_handle = None
+
+# (name, argtypes) of every exported entry point declared in include/tmop.h
+SIGNATURES = {
+    "tmop_create": [ctypes.POINTER(_P), ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), _P],
+    "tmop_destroy": [_P],
+    "tmop_workspace_bytes": [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_size_t)],
+    "tmop_sizes": [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+    "tmop_basis_nodes": [ctypes.c_int, _D],
+    "tmop_energy": [_P, _P, _D],
+    "tmop_min_det": [_P, _P, _D],
+    "tmop_energy_mindet": [_P, _P, _D, _D],
+    "tmop_gradient": [_P, _P, _P],
+    "tmop_hessian_setup": [_P, _P],
+    "tmop_hessian_apply": [_P, _P, _P],
+    "tmop_hessian_diag": [_P, _P],
+    "tmop_solve": [_P, _P, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveReport)],
+    "tmop_newton_step": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveReport)],
+    "tmop_minres": [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                    ctypes.POINTER(ctypes.c_int)],
+    "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
+    "tmop_last_error": [],
+    "tmop_version": [],
+}
+
+
+def lib():
+    """Load libtmop_hip.so (raises if it was not built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtmop_hip.so is not built; run python -m paper_2205_12721_amd.build")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(h, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name in ("tmop_last_error", "tmop_version") else ctypes.c_int
+        _lib_handle = h
+    return _lib_handle
+
+
+def _check(code):
+    if code != 0:
+        raise TmopError(code, lib().tmop_last_error().decode())
+
+
+def basis_nodes(p):
+    """The p+1 node positions on [0,1] at which the library places element nodes."""
+    out = np.zeros(p + 1)
+    _check(lib().tmop_basis_nodes(int(p), out.ctypes.data_as(_D)))
+    return out
+
+
+def _ptr(t, n=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected dtype %s, got %s" % (dtype, t.dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("tensor has %d entries, expected %d" % (t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A PA-TMOP problem on one GPU.
+
+    Structured box: ``Context(dim, n, p, nq1d)`` with ``n`` an int or a tuple of
+    elements per axis.  General mesh: pass ``elem_to_node`` (int32 CUDA tensor,
+    (E, (p+1)^dim)) and ``num_nodes``.
+    ``ess``: "boundary" (box only), "none", or a uint8 CUDA mask of d*N_x.
+    ``precision``: "fp64" or "mixed".
+    """
+
+    def __init__(self, dim, n=None, p=1, nq1d=None, metric=None, precision="fp64", W=None,
+                 ess="boundary", elem_to_node=None, num_nodes=None, stream=None):
+        import torch
+        self._torch = torch
+        self.dim, self.p = dim, p
+        self.nq1d = nq1d if nq1d is not None else p + 2
+        self.metric = metric if metric is not None else (2 if dim == 2 else 303)
+        self.precision = precision
+        md = MeshDesc()
+        md.dim, md.order_p = dim, p
+        self._keep = []
+        if elem_to_node is None:
+            ns = (n,) * dim if np.isscalar(n) else tuple(n)
+            if len(ns) != dim:
+                raise ValueError("need one element count per axis")
+            md.nx, md.ny = ns[0], ns[1]
+            md.nz = ns[2] if dim == 3 else 0
+            self.shape = ns
+        else:
+            md.elem_to_node = _ptr(elem_to_node, dtype=torch.int32).value
+            md.num_elems = elem_to_node.shape[0]
+            md.num_nodes = int(num_nodes)
+            self._keep.append(elem_to_node)
+            self.shape = None
+        if isinstance(ess, str):
+            md.ess_mode = {"boundary": ESS_BOUNDARY, "none": ESS_NONE}[ess]
+        else:
+            md.ess_mode = ESS_MASK
+            md.ess_mask = _ptr(ess, dtype=torch.uint8).value
+            self._keep.append(ess)
+        prm = Params()
+        prm.metric = self.metric
+        prm.nq1d = self.nq1d
+        if W is not None:
+            Wa = np.asarray(W, dtype=np.float64).reshape(dim, dim)
+            prm.has_W = 1
+            for k, v in enumerate(Wa.ravel()):
+                prm.W[k] = v
+        prm.precision = {"fp64": TMOP_FP64, "mixed": TMOP_MIXED}[precision]
+        self._md, self._prm = md, prm
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._stream = s
+        h = ctypes.c_void_p()
+        _check(lib().tmop_create(ctypes.byref(h), ctypes.byref(md), ctypes.byref(prm),
+                                 ctypes.c_void_p(s.cuda_stream)))
+        self._h = h
+        nn, nd = ctypes.c_int(), ctypes.c_int()
+        _check(lib().tmop_sizes(h, ctypes.byref(nn), ctypes.byref(nd)))
+        self.num_nodes, self.ndof = nn.value, nd.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tmop_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers ----------------------------------------------------------
+    def _vec(self, t):
+        return _ptr(t, self.ndof, self._torch.float64)
+
+    def new_vector(self):
+        return self._torch.zeros(self.ndof, dtype=self._torch.float64, device="cuda")
+
+    def workspace_bytes(self, with_solver=True):
+        b = ctypes.c_size_t()
+        _check(lib().tmop_workspace_bytes(ctypes.byref(self._md), ctypes.byref(self._prm),
+                                          int(with_solver), ctypes.byref(b)))
+        return b.value
+
+    # -- evaluations --------------------------------------------------------
+    def energy(self, x):
+        F = ctypes.c_double()
+        _check(lib().tmop_energy(self._h, self._vec(x), ctypes.byref(F)))
+        return F.value
+
+    def min_det(self, x):
+        m = ctypes.c_double()
+        _check(lib().tmop_min_det(self._h, self._vec(x), ctypes.byref(m)))
+        return m.value
+
+    def energy_mindet(self, x):
+        F, m = ctypes.c_double(), ctypes.c_double()
+        code = lib().tmop_energy_mindet(self._h, self._vec(x), ctypes.byref(F), ctypes.byref(m))
+        if code not in (0, ERR_INVERTED):
+            _check(code)
+        return F.value, m.value
+
+    def gradient(self, x, out=None):
+        out = self.new_vector() if out is None else out
+        _check(lib().tmop_gradient(self._h, self._vec(x), self._vec(out)))
+        return out
+
+    def hessian_setup(self, x):
+        _check(lib().tmop_hessian_setup(self._h, self._vec(x)))
+
+    def hessian_apply(self, v, out=None):
+        out = self.new_vector() if out is None else out
+        _check(lib().tmop_hessian_apply(self._h, self._vec(v), self._vec(out)))
+        return out
+
+    def hessian_diag(self, out=None):
+        out = self.new_vector() if out is None else out
+        _check(lib().tmop_hessian_diag(self._h, self._vec(out)))
+        return out
+
+    def minres(self, b, max_its=50, rtol=1e-12, jacobi=True, out=None):
+        out = self.new_vector() if out is None else out
+        its = ctypes.c_int()
+        _check(lib().tmop_minres(self._h, self._vec(b), self._vec(out), int(max_its),
+                                 float(rtol), int(bool(jacobi)), ctypes.byref(its)))
+        return out, its.value
+
+    def time_apply(self, v, y, n):
+        e, t = ctypes.c_double(), ctypes.c_double()
+        _check(lib().tmop_time_apply(self._h, self._vec(v), self._vec(y), int(n),
+                                     ctypes.byref(e), ctypes.byref(t)))
+        return e.value, t.value
+
+    # -- solve ----------------------------------------------------------------
+    def solve(self, x, rel_grad_tol=1e-8, max_newton=200, max_minres=50, minres_rtol=1e-12,
+              max_halvings=30, jacobi=True, g0_norm=0.0, raise_on_error=False):
+        """Optimise x in place; returns the report as a dict (status in 'status')."""
+        sp = SolveParams(rel_grad_tol, max_newton, max_minres, minres_rtol, max_halvings,
+                         int(bool(jacobi)), g0_norm)
+        rep = SolveReport()
+        code = lib().tmop_solve(self._h, self._vec(x), ctypes.byref(sp), ctypes.byref(rep))
+        if raise_on_error and code != 0:
+            _check(code)
+        d = rep.as_dict()
+        d["message"] = lib().tmop_last_error().decode() if code else ""
+        return d
+
+    def newton_step(self, x, n_minres=20, jacobi=True):
+        rep = SolveReport()
+        code = lib().tmop_newton_step(self._h, self._vec(x), int(n_minres), int(bool(jacobi)),
+                                      ctypes.byref(rep))
+        _check(code)
+        return rep.as_dict()

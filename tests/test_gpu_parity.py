@@ -1,0 +1,180 @@
+"""GPU parity: every entry point of the HIP library against the FP64 oracle.
+
+Sizes span several workgroups with a ragged last workgroup (element counts
+not multiple of the elements-per-workgroup of each (p, n_q)), both
+dimensions, p = 1..4 and n_q = p+1..p+3.  Tolerance: 1e-11 relative (l2 over
+all DoFs) for FP64 energy, gradient, Hessian action and diagonal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import basis
+from paper_2205_12721_amd import inputs
+from tests.gpu_common import TOL64, log, make_case, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# (dim, elements per axis, p, nq)
+CASES = [
+    (2, (8, 8), 2, 4),
+    (2, (5, 7), 1, 3),
+    (2, (3, 5), 3, 5),
+    (2, (4, 3), 4, 6),
+    (2, (6, 5), 2, 5),
+    (3, (2, 3, 4), 1, 3),
+    (3, (2, 2, 3), 1, 2),
+    (3, (3, 3, 3), 2, 4),
+    (3, (3, 2, 2), 2, 3),
+    (3, (3, 3, 3), 3, 5),
+    (3, (2, 3, 2), 3, 4),
+    (3, (2, 2, 3), 3, 6),
+    (3, (2, 2, 2), 4, 6),
+    (3, (2, 2, 2), 4, 7),
+]
+
+
+def _ctx(dim, ns, p, nq, **kw):
+    from paper_2205_12721_amd.tmop import Context
+    return Context(dim, ns, p, nq, **kw)
+
+
+@pytest.mark.parametrize("dim,ns,p,nq", CASES)
+def test_kernels_match_oracle(dim, ns, p, nq):
+    log("case", dim, ns, p, nq)
+    pb, x = make_case(dim, ns, p, nq, seed=3)
+    v = inputs.gaussian_vector(pb.ndof, 11, pb.ess)
+    v_raw = inputs.gaussian_vector(pb.ndof, 12)  # nonzero on fixed DoFs too
+    ctx = _ctx(dim, ns, p, nq)
+    assert ctx.ndof == pb.ndof
+    xd = to_dev(x)
+    F, md = ctx.energy_mindet(xd)
+    assert abs(F - pb.energy(x)) <= TOL64 * abs(pb.energy(x))
+    assert abs(md - pb.min_det(x)) <= 1e-12 * abs(pb.min_det(x))
+    g = to_host(ctx.gradient(xd))
+    assert rel(g, pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    y = to_host(ctx.hessian_apply(to_dev(v)))
+    assert rel(y, pb.hvp(x, v)) <= TOL64
+    y2 = to_host(ctx.hessian_apply(to_dev(v_raw)))
+    assert rel(y2, pb.hvp(x, v_raw)) <= TOL64
+    d = to_host(ctx.hessian_diag())
+    assert rel(d, pb.diag(x)) <= TOL64
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,ns,p,nq", [(2, (5, 4), 2, 4), (3, (3, 2, 3), 3, 5), (3, (2, 2, 2), 2, 4)])
+def test_unconstrained_and_masked(dim, ns, p, nq):
+    import torch
+    pb, x = make_case(dim, ns, p, nq, seed=4, constrain=None)
+    v = inputs.gaussian_vector(pb.ndof, 13)
+    ctx = _ctx(dim, ns, p, nq, ess="none")
+    xd = to_dev(x)
+    assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    assert rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v)) <= TOL64
+    assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= TOL64
+    ctx.close()
+    # a random mask of fixed DoFs
+    mask = np.random.default_rng(5).uniform(size=pb.ndof) < 0.3
+    pbm = oracle.Problem(dim, p, nq, pb.e2n, pb.nx, ess=mask)
+    mdev = torch.as_tensor(mask.astype(np.uint8)).cuda()
+    ctx = _ctx(dim, ns, p, nq, ess=mdev)
+    assert rel(to_host(ctx.gradient(xd)), pbm.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    assert rel(to_host(ctx.hessian_apply(to_dev(v))), pbm.hvp(x, v)) <= TOL64
+    assert rel(to_host(ctx.hessian_diag()), pbm.diag(x)) <= TOL64
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,ns,p,nq", [(2, (4, 4), 2, 4), (3, (2, 3, 2), 2, 4)])
+def test_constant_target(dim, ns, p, nq):
+    rng = np.random.default_rng(7)
+    W = np.eye(dim) + 0.2 * rng.standard_normal((dim, dim))
+    if np.linalg.det(W) < 0:
+        W[:, 0] *= -1
+    pb, x = make_case(dim, ns, p, nq, seed=5, W=W)
+    v = inputs.gaussian_vector(pb.ndof, 14, pb.ess)
+    ctx = _ctx(dim, ns, p, nq, W=W)
+    xd = to_dev(x)
+    assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
+    assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    assert rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v)) <= TOL64
+    assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= TOL64
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,ns,p,nq", [(2, (3, 4), 3, 5), (3, (2, 3, 2), 2, 4)])
+def test_general_mesh_connectivity(dim, ns, p, nq):
+    """The element-to-node path (CSR gather) equals the structured box path."""
+    import torch
+    pb, x = make_case(dim, ns, p, nq, seed=6)
+    v = inputs.gaussian_vector(pb.ndof, 15, pb.ess)
+    e2n = torch.as_tensor(pb.e2n).cuda()
+    mdev = torch.as_tensor(pb.ess.astype(np.uint8)).cuda()
+    ctx = _ctx(dim, None, p, nq, elem_to_node=e2n, num_nodes=pb.nx, ess=mdev)
+    xd = to_dev(x)
+    assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
+    assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    assert rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v)) <= TOL64
+    assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= TOL64
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,ns,p,nq", [(2, (8, 8), 2, 4), (3, (3, 3, 3), 3, 5), (3, (3, 3, 2), 2, 4)])
+def test_mixed_precision_hvp(dim, ns, p, nq):
+    """FP32 tensor + FP32 action: error vs the FP64 oracle at FP32 level."""
+    pb, x = make_case(dim, ns, p, nq, seed=8)
+    v = inputs.gaussian_vector(pb.ndof, 16, pb.ess)
+    ctx = _ctx(dim, ns, p, nq, precision="mixed")
+    xd = to_dev(x)
+    # energy and gradient stay FP64
+    assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
+    assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    err = rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v))
+    log("mixed hvp rel err", err)
+    assert 0 < err <= 2e-6
+    assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= 2e-6
+    ctx.close()
+
+
+def test_deterministic_and_linear():
+    """Repeated applications are bitwise identical; the action is linear."""
+    pb, x = make_case(3, (3, 3, 3), 3, 5, seed=9)
+    v = inputs.gaussian_vector(pb.ndof, 17, pb.ess)
+    w = inputs.gaussian_vector(pb.ndof, 18, pb.ess)
+    ctx = _ctx(3, (3, 3, 3), 3, 5)
+    ctx.hessian_setup(to_dev(x))
+    a = to_host(ctx.hessian_apply(to_dev(v)))
+    b = to_host(ctx.hessian_apply(to_dev(v)))
+    assert np.array_equal(a, b)
+    c = to_host(ctx.hessian_apply(to_dev(2.0 * v - 3.0 * w)))
+    d = to_host(ctx.hessian_apply(to_dev(w)))
+    assert rel(c, 2.0 * a - 3.0 * d) <= 1e-13
+    ctx.close()
+
+
+def test_error_paths():
+    import torch
+    from paper_2205_12721_amd.tmop import TmopError, ERR_INVERTED
+    with pytest.raises(TmopError) as e:
+        _ctx(3, (2, 2, 2), 3, 9)
+    assert e.value.code == 2
+    ctx = _ctx(2, (2, 2), 1, 2, ess="none")
+    with pytest.raises(TmopError) as e:
+        ctx.hessian_apply(ctx.new_vector())
+    assert e.value.code == 11
+    xu = inputs.uniform_nodes((2, 2), 1, basis.gll_nodes(1))
+    xu[4] = 1.3
+    F, md = ctx.energy_mindet(to_dev(xu))
+    assert md < 0 and F == float("inf")
+    with pytest.raises(TmopError) as e:
+        ctx.energy(to_dev(xu))
+    assert e.value.code == ERR_INVERTED
+    v = ctx.new_vector()
+    with pytest.raises(ValueError):
+        ctx.gradient(torch.zeros(3, dtype=torch.float64, device="cuda"))
+    ctx.close()
