@@ -1,0 +1,241 @@
+"""Benchmark of the PA-TMOP hot path on one MI355X.
+
+A step is one Newton iteration of the TMOP solve on the initial perturbed mesh
+with a fixed number of MINRES iterations (20, as in the paper's throughput
+runs of Sec. 4.1): energy and det check, gradient, Hessian setup, Jacobi
+diagonal, 20 Hessian actions inside Jacobi-preconditioned MINRES, line search
+and node update.  Every step restarts from the same initial mesh, so each
+does the same work.
+
+Reported metric: Hessian-action throughput in GDoF/s (unique DoFs d*N_x times
+actions, over the summed device time of the actions measured with HIP events
+on the library's stream inside the timed steps), FP64 and mixed precision,
+with the HBM roofline fraction of the action and the plain FP64 oracle timed
+on the host cores as a reference baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+WORKLOADS = {
+    # name: (inputs config, dim, n, p, nq)
+    "c2": ("c2", 3, 24, 3, 5),
+    "c3a": ("c3a", 3, 64, 2, 4),
+    "c3b": ("c3b", 3, 32, 4, 6),
+    "c1": ("c1", 2, 8, 2, 4),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), GB/s."""
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
+
+
+def run_steps(ctx, x, x0, steps, n_minres):
+    import torch
+    acc = dict(t_apply_ms=0.0, t_apply_elem_ms=0.0, n_apply=0, t_setup_ms=0.0,
+               t_minres_ms=0.0, t_linesearch_ms=0.0, halvings=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.copy_(x0)
+        rep = ctx.newton_step(x, n_minres=n_minres, jacobi=True)
+        for k in ("t_apply_ms", "t_apply_elem_ms", "n_apply", "t_setup_ms", "t_minres_ms",
+                  "t_linesearch_ms"):
+            acc[k] += rep[k]
+        acc["halvings"] += rep["halvings_total"]
+    torch.cuda.synchronize()
+    acc["wall_s"] = time.perf_counter() - t0
+    acc["last"] = rep
+    return acc
+
+
+def roofline(ne, nqe, S, ndof, tbytes, acc):
+    napp = max(acc["n_apply"], 1)
+    t_app = acc["t_apply_ms"] / napp / 1e3
+    t_elem = acc["t_apply_elem_ms"] / napp / 1e3
+    b_alg = ne * nqe * S * tbytes + 2 * ndof * 8          # tensor + v in + y out
+    b_elem = ne * nqe * S * tbytes + ndof * 8             # tensor + v in
+    achieved = b_alg / t_app / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": "Hessian action = element kernel k3_apply + node gather k_gather_box",
+        "alg_bytes_per_launch": int(b_alg),
+        "avg_us": round(t_app * 1e6, 2),
+        "elem_avg_us": round(t_elem * 1e6, 2),
+        "gather_avg_us": round((t_app - t_elem) * 1e6, 2),
+        "elem_achieved_GBs": round(b_elem / t_elem / 1e9, 1),
+    }
+
+
+def cpu_baseline(cfg, x, v, seconds):
+    import numpy as np  # noqa: F401
+    import oracle
+    _, dim, n, p, nq = cfg
+    pb = oracle.Problem.box(dim, n, p, nq)
+    pb.hvp(x, v)  # warm up
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        pb.hvp(x, v)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {
+        "value": round(pb.ndof * reps / el / 1e9, 6),
+        "unit": "GDoF/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "%d Hessian actions of the FP64 oracle (direct, not sum-factorized) on the "
+                  "same mesh and vector, %.1f s" % (reps, el),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--minres", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-copy-bw", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design for sharding is described in DESIGN.md); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = WORKLOADS[args.workload]
+    cname, dim, n, p, nq = cfg
+    S = dim * dim * (dim * dim + 1) // 2
+
+    log("[bench] workload", cfg)
+    ctx = Context(dim, n, p, nq, precision="fp64")
+    ctx.set_timing(True)
+    probe = torch.empty(ctx.ndof, dtype=torch.float64, device="cuda")
+
+    def valid(xh):
+        probe.copy_(torch.as_tensor(xh))
+        return ctx.min_det(probe) > 0
+
+    xh, info = inputs.config_mesh(cname, basis_nodes(p), is_valid=valid)
+    log("[bench] mesh ready, tries", info["tries"], "ndof", ctx.ndof)
+    x0 = torch.as_tensor(xh).cuda()
+    x = torch.empty_like(x0)
+    ne = int(np.prod([n] * dim))
+    nqe = nq ** dim
+
+    # FP64
+    run_steps(ctx, x, x0, args.warmup, args.minres)
+    log("[bench] fp64 warmup done")
+    acc = run_steps(ctx, x, x0, args.steps, args.minres)
+    log("[bench] fp64 timed steps done")
+    napp = max(acc["n_apply"], 1)
+    gdofs = ctx.ndof * acc["n_apply"] / (acc["t_apply_ms"] / 1e3) / 1e9
+    rf = roofline(ne, nqe, S, ctx.ndof, 8, acc)
+    ms_step = acc["wall_s"] / args.steps * 1e3
+
+    out = {
+        "metric": "PA TMOP Hessian-apply GDoF/s + %HBM roofline (FP64 vs mixed); p99 solve ms",
+        "value": round(gdofs, 3),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D hex box %d^3, Q%d, %d^3 Gauss-Legendre points, mu_303, ideal target; "
+                        "one Newton step with %d Jacobi-MINRES iterations per step"
+                        % (n, p, nq, args.minres) if dim == 3 else
+                        "2D quad box %d^2, Q%d, %d^2 points, mu_2" % (n, p, nq),
+            "elements": ne, "order": p, "nq1d": nq, "dofs": ctx.ndof,
+            "minres_per_step": args.minres, "mesh_seed": inputs.CONFIGS[cname]["seed"],
+        },
+        "roofline": rf,
+        "step_gdof_s": round(ctx.ndof * args.minres / (ms_step / 1e3) / 1e9, 3),
+        "phases_ms_per_step": {k: round(acc[k] / args.steps, 3)
+                               for k in ("t_setup_ms", "t_minres_ms", "t_linesearch_ms")},
+        "apply_us": round(acc["t_apply_ms"] / napp * 1e3, 2),
+    }
+
+    if not args.no_mixed:
+        ctx32 = Context(dim, n, p, nq, precision="mixed")
+        ctx32.set_timing(True)
+        run_steps(ctx32, x, x0, args.warmup, args.minres)
+        acc32 = run_steps(ctx32, x, x0, args.steps, args.minres)
+        log("[bench] mixed timed steps done")
+        g32 = ctx32.ndof * acc32["n_apply"] / (acc32["t_apply_ms"] / 1e3) / 1e9
+        out["mixed"] = {
+            "value": round(g32, 3), "unit": "GDoF/s", "dtype": "f32 action / f64 rest",
+            "ms_per_step": round(acc32["wall_s"] / args.steps * 1e3, 3),
+            "roofline": roofline(ne, nqe, S, ctx32.ndof, 4, acc32),
+        }
+        ctx32.close()
+
+    if not args.no_copy_bw:
+        bw = copy_bandwidth(torch)
+        out["copy_bw_GBs"] = round(bw, 1)
+        out["roofline"]["frac_of_copy_bw"] = round(rf["achieved"] / bw, 4)
+
+    if not args.no_cpu_baseline:
+        v = inputs.gaussian_vector(ctx.ndof, inputs.CONFIGS[cname]["vec_seed"])
+        out["cpu_baseline"] = cpu_baseline(cfg, xh, v, args.cpu_seconds)
+        log("[bench] cpu baseline done")
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

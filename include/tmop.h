@@ -116,6 +116,12 @@ typedef struct {
     double F0, F;         /* initial and final objective                */
     double g0_norm, g_norm; /* initial and final |g_c| (l2, all DoFs)  */
     double t_setup_ms, t_minres_ms, t_linesearch_ms, t_total_ms; /* phase times */
+    /* Hessian actions inside MINRES, timed with HIP events on the context's
+     * stream when timing is enabled (tmop_set_timing); zero otherwise. */
+    double t_apply_ms;      /* summed device time of the actions (element + gather) */
+    double t_apply_elem_ms; /* summed device time of the element kernel alone       */
+    int n_apply;            /* number of timed actions                              */
+    int reserved;
 } tmop_solve_report;
 
 /* ---------------------------------------------------------------------- */
@@ -204,6 +210,10 @@ int tmop_minres(tmop_ctx *ctx, const double *b_dev, double *dx_dev, int max_its,
  * total_ms: element kernel plus the node gather). */
 int tmop_time_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev, int n, double *elem_ms,
                     double *total_ms);
+
+/* Enable (1) or disable (0) HIP-event timing of the Hessian actions inside
+ * MINRES; results land in tmop_solve_report.t_apply_ms / n_apply. */
+int tmop_set_timing(tmop_ctx *ctx, int enable);
 
 /* Thread-local description of the last error. */
 const char *tmop_last_error(void);

@@ -258,3 +258,17 @@ def _dense_tables(dim, p, nq1d):
 
 
 from .solver import minres, newton_solve  # noqa: E402,F401
+
+
+def restrict_to_nodes(pb, nodes):
+    """Sub-problem holding only the elements that touch ``nodes`` (global node ids).
+
+    Energy-derivative entries at those nodes depend only on these elements, so
+    the sub-problem's gradient, Hessian action and diagonal equal the full
+    problem's there; used to sample large meshes entry by entry.
+    """
+    nodes = np.asarray(nodes)
+    keep = np.isin(pb.e2n, nodes).any(axis=1)
+    sub = Problem(pb.dim, pb.p, pb.nq1d, pb.e2n[keep], pb.nx, metric_id=pb.metric, W=pb.W,
+                  ess=pb.ess)
+    return sub

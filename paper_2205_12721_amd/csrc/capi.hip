@@ -174,6 +174,12 @@ struct tmop_ctx {
     double *sv[SV_COUNT] = {};
     MinresState *mst = nullptr;
     MinresState *hmst = nullptr;
+    // HIP-event timing of the Hessian actions inside MINRES
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    int tev_used = 0;
+    double acc_apply_ms = 0.0, acc_elem_ms = 0.0;
+    int acc_napply = 0;
 };
 
 static int ctx_sizes(const tmop_mesh_desc *m, const tmop_params *prm, long &ne, long &nx,
@@ -239,6 +245,7 @@ extern "C" int tmop_basis_nodes(int p, double *nodes)
 static void free_ctx(tmop_ctx *c)
 {
     if (!c) return;
+    for (auto &e : c->tev) hipEventDestroy(e);
     hipFree(c->H);
     hipFree(c->eV);
     hipFree(c->part);
@@ -595,10 +602,18 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
     double *V = c->sv[SV_V], *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
     const double *minv = jacobi ? c->minv : nullptr;
     mr_init(n, b, minv, R1, R2, Y, dx, W, W1, W2, c->part, c->mst, rtol, c->s);
+    c->tev_used = 0;
     for (int j = 0; j < max_its; ++j) {
         mr_v(n, j, c->mst, Y, V, c->s);
+        const bool rec = c->timing && c->tev_used + 3 <= (int)c->tev.size();
+        if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used], c->s));
         apply_elem(c, V);
+        if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used + 1], c->s));
         apply_gather(c, V, HV);
+        if (rec) {
+            HIPCHK(hipEventRecord(c->tev[c->tev_used + 2], c->s));
+            c->tev_used += 3;
+        }
         mr_lanczos1(n, j, c->mst, HV, R1, V, c->part, c->s);
         mr_lanczos2(n, j, c->mst, HV, R2, minv, R1, c->part, c->s);
         // new w goes to the old w1 buffer; (w1, w2) of the formula = (old w2, old w)
@@ -630,6 +645,18 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
     HIPCHK(hipStreamSynchronize(c->s));
     HIPCHK(hipGetLastError());
     if (its_out) *its_out = c->hmst->its;
+    // applies after convergence are skipped by the kernels' own guards only in
+    // the vector kernels; the element work still ran, so every recorded
+    // action is counted
+    for (int k = 0; k + 2 < c->tev_used; k += 3) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, c->tev[k], c->tev[k + 1]));
+        HIPCHK(hipEventElapsedTime(&b, c->tev[k], c->tev[k + 2]));
+        c->acc_elem_ms += a;
+        c->acc_apply_ms += b;
+        c->acc_napply += 1;
+    }
+    c->tev_used = 0;
     if (c->hmst->indefinite_precond) return fail(TMOP_ERR_NONFINITE, "preconditioner not SPD");
     return TMOP_OK;
 }
@@ -664,6 +691,11 @@ static int newton_update(tmop_ctx *c, double *x, double &F, double &gn, int max_
     CHK(minres_impl(c, c->sv[SV_G], c->sv[SV_DX], max_minres, rtol, jacobi, check_every, &its));
     double t2 = now_ms();
     rep->minres_its_total += its;
+    rep->t_apply_ms += c->acc_apply_ms;
+    rep->t_apply_elem_ms += c->acc_elem_ms;
+    rep->n_apply += c->acc_napply;
+    c->acc_apply_ms = c->acc_elem_ms = 0.0;
+    c->acc_napply = 0;
     double alpha = 1.0;
     bool ok = false;
     double Ft = 0.0, gtn = 0.0;
@@ -772,6 +804,17 @@ extern "C" int tmop_newton_step(tmop_ctx *c, double *x, int n_minres, int jacobi
     rep->status = r;
     rep->t_total_ms = now_ms() - t0;
     return r;
+}
+
+extern "C" int tmop_set_timing(tmop_ctx *c, int enable)
+{
+    if (!c) return fail(TMOP_ERR_INVALID_ARG, "null context");
+    c->timing = enable != 0;
+    if (c->timing && c->tev.empty()) {
+        c->tev.resize(3 * 256);
+        for (auto &e : c->tev) HIPCHK(hipEventCreate(&e));
+    }
+    return TMOP_OK;
 }
 
 extern "C" const char *tmop_last_error(void) { return g_err.c_str(); }

@@ -18,9 +18,14 @@ production ALE mesh; these perturbed boxes stand in for them):
 * ``smooth``: uniform mesh plus a smooth displacement
   u_c(x) = (0.2 h / 4) sum_{k<4} s_ck prod_j sin(pi m_ckj x_j)
   with m in {1,2,3} and s in {-1,+1} drawn from the seed (it vanishes on the
-  boundary), plus U[-0.05 h, 0.05 h] jitter on every node, with the jitter
-  component normal to a boundary face removed (boundary nodes slide only
-  along their face/edge; corners do not move).
+  boundary), plus U[-a, a] jitter on every node, with the jitter component
+  normal to a boundary face removed (boundary nodes slide only along their
+  face/edge; corners do not move).
+
+Jitter amplitude: a = amp * h * p * g_min, where g_min is the smallest gap
+between adjacent 1D element nodes on [0,1] (p * g_min = 1 for p <= 2, 0.83
+for p = 3, 0.69 for p = 4), so the jitter is the same fraction of the closest
+node spacing at every order.
 * ``pin``: the ``smooth`` geometry class but with interior-only jitter, so the
   uniform grid is the optimum of every shape metric with fixed boundary.
 
@@ -116,7 +121,8 @@ def perturbed_box(dim, n, p, nodes1d, seed, recipe="smooth", amp=0.05,
         base = x0 + smooth_displacement(ns, x0, rng)
     elif recipe not in ("interior_jitter", "pin"):
         raise ValueError("unknown recipe %r" % recipe)
-    hs = np.array([1.0 / v for v in ns])
+    gap = float(np.min(np.diff(np.asarray(nodes1d, dtype=np.float64)))) * p
+    hs = np.array([gap / v for v in ns])
     for t in range(1, max_tries + 1):
         jit = rng.uniform(-1.0, 1.0, size=(dim, nx)) * (amp * hs)[:, None]
         if recipe == "smooth":

@@ -55,7 +55,9 @@ class SolveReport(ctypes.Structure):
                 ("F0", ctypes.c_double), ("F", ctypes.c_double), ("g0_norm", ctypes.c_double),
                 ("g_norm", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("t_minres_ms", ctypes.c_double), ("t_linesearch_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double),
+                ("t_apply_elem_ms", ctypes.c_double), ("n_apply", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +89,7 @@ SIGNATURES = {
     "tmop_minres": [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                     ctypes.POINTER(ctypes.c_int)],
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
+    "tmop_set_timing": [_P, ctypes.c_int],
     "tmop_last_error": [],
     "tmop_version": [],
 }
@@ -264,6 +267,9 @@ class Context:
         _check(lib().tmop_minres(self._h, self._vec(b), self._vec(out), int(max_its),
                                  float(rtol), int(bool(jacobi)), ctypes.byref(its)))
         return out, its.value
+
+    def set_timing(self, enable=True):
+        _check(lib().tmop_set_timing(self._h, int(bool(enable))))
 
     def time_apply(self, v, y, n):
         e, t = ctypes.c_double(), ctypes.c_double()

@@ -46,7 +46,7 @@ def test_binding_struct_layouts():
     assert tmop.Params.W.offset == 16
     assert ctypes.sizeof(tmop.Params) == 16 + 72 + 8
     assert ctypes.sizeof(tmop.SolveParams) == 40
-    assert ctypes.sizeof(tmop.SolveReport) == 16 + 8 * 8
+    assert ctypes.sizeof(tmop.SolveReport) == 16 + 10 * 8 + 8
 
 
 def test_cpu_only_calls_without_gpu():
