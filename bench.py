@@ -209,19 +209,25 @@ def main():
         "apply_us": round(acc["t_apply_ms"] / napp * 1e3, 2),
     }
 
+    variants = [("compact", "fp64")]
     if not args.no_mixed:
-        ctx32 = Context(dim, n, p, nq, precision="mixed")
-        ctx32.set_timing(True)
-        run_steps(ctx32, x, x0, args.warmup, args.minres)
-        acc32 = run_steps(ctx32, x, x0, args.steps, args.minres)
-        log("[bench] mixed timed steps done")
-        g32 = ctx32.ndof * acc32["n_apply"] / (acc32["t_apply_ms"] / 1e3) / 1e9
-        out["mixed"] = {
-            "value": round(g32, 3), "unit": "GDoF/s", "dtype": "f32 action / f64 rest",
-            "ms_per_step": round(acc32["wall_s"] / args.steps * 1e3, 3),
-            "roofline": roofline(ne, nqe, S, ctx32.ndof, 4, acc32),
+        variants = [("tensor", "mixed"), ("compact", "fp64"), ("compact", "mixed")]
+    for storage, prec in variants:
+        cv = Context(dim, n, p, nq, precision=prec, storage=storage)
+        cv.set_timing(True)
+        run_steps(cv, x, x0, args.warmup, args.minres)
+        av = run_steps(cv, x, x0, args.steps, args.minres)
+        log("[bench] %s %s timed steps done" % (storage, prec))
+        gv = cv.ndof * av["n_apply"] / (av["t_apply_ms"] / 1e3) / 1e9
+        sv = S if storage == "tensor" else (13 if dim == 3 else 8)
+        out["%s_%s" % (storage, prec)] = {
+            "value": round(gv, 3), "unit": "GDoF/s",
+            "dtype": "f64" if prec == "fp64" else "f32 action / f64 rest",
+            "storage": storage, "values_per_point": sv,
+            "ms_per_step": round(av["wall_s"] / args.steps * 1e3, 3),
+            "roofline": roofline(ne, nqe, sv, cv.ndof, 8 if prec == "fp64" else 4, av),
         }
-        ctx32.close()
+        cv.close()
 
     if not args.no_copy_bw:
         bw = copy_bandwidth(torch)

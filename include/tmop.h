@@ -70,6 +70,7 @@ typedef enum {
 
 enum { TMOP_FP64 = 0, TMOP_MIXED = 1 };       /* tmop_params.precision */
 enum { TMOP_ESS_BOUNDARY = 0, TMOP_ESS_NONE = 1, TMOP_ESS_MASK = 2 };
+enum { TMOP_HESS_TENSOR = 0, TMOP_HESS_COMPACT = 1 };  /* tmop_params.hess_storage */
 
 typedef struct tmop_ctx tmop_ctx;
 
@@ -93,9 +94,16 @@ typedef struct {
     int nq1d;       /* quadrature points per direction, p+1 .. p+3 */
     int has_W;      /* 0: ideal target W = I; 1: use the constant W below */
     double W[9];    /* constant target matrix, row-major dim x dim, det > 0 */
-    int precision;  /* TMOP_FP64, or TMOP_MIXED: FP32 quadrature tensor and
+    int precision;  /* TMOP_FP64, or TMOP_MIXED: FP32 quadrature data and
                        FP32 Hessian action (FP32 accumulation); energy,
                        gradient, det, line search and reductions stay FP64 */
+    int hess_storage; /* TMOP_HESS_TENSOR: per point the packed symmetric
+                       d^2 x d^2 second-derivative tensor times the weight
+                       (45 / 10 entries, Sec. 3.4); TMOP_HESS_COMPACT: per
+                       point T and the four weighted scalar coefficients of
+                       the metric's second derivative (13 / 8 entries), the
+                       tensor applied in closed form in the action.  Same
+                       results; the compact form moves 3.5x fewer bytes. */
 } tmop_params;
 
 typedef struct {
@@ -199,6 +207,75 @@ int tmop_newton_step(tmop_ctx *ctx, double *x_dev_inout, int n_minres, int jacob
  * *its receives the iteration count.  Synchronises. */
 int tmop_minres(tmop_ctx *ctx, const double *b_dev, double *dx_dev, int max_its, double rtol,
                 int jacobi, int *its);
+
+/* ---------------------------------------------------------------------- */
+/* Batched and served solves                                               */
+/* ---------------------------------------------------------------------- */
+
+/* A pool advances many independent solves (structured boxes of any order,
+ * dimension, precision and storage) together through the Newton-MINRES loop
+ * of Sec. 2.3.  Each phase (setup, diagonal, MINRES iterations, line-search
+ * trials) is one launch per kernel class (dim, p, n_q, storage, precision)
+ * over the elements of every participating solve, and six MINRES iterations
+ * are replayed as one HIP graph.  Every solve owns a contiguous region of one
+ * device arena of hbm_budget bytes; a solve's arithmetic does not depend on
+ * the other solves in the pool (its reductions run over its own data in a
+ * fixed order), so its result is the same alone and in the mix.
+ *
+ * Calls on one pool are not thread-safe; the pool runs on its own HIP
+ * stream and synchronises with the caller's stream where it reads or writes
+ * caller buffers. */
+typedef struct tmop_pool tmop_pool;
+
+/* Create a pool with an arena of hbm_budget bytes and up to max_slots
+ * concurrent solves.  Errors: INVALID_ARG, OOM. */
+int tmop_pool_create(tmop_pool **out, size_t hbm_budget, int max_slots, void *hip_stream);
+int tmop_pool_destroy(tmop_pool *pool);
+
+/* Arena bytes one solve of this mesh/params takes (vectors, quadrature data,
+ * element scratch).  Structured boxes only (elem_to_node must be NULL). */
+int tmop_pool_request_bytes(const tmop_mesh_desc *mesh, const tmop_params *prm, size_t *bytes);
+
+/* Admit one solve: copies the caller's device nodes x_dev (d*N_x doubles,
+ * read after the work queued on src_stream) into the pool.  Returns the slot
+ * index.  Errors: BUDGET (the request alone exceeds the budget), BUSY (no
+ * free slot or no free arena region now: retry after a release),
+ * UNSUPPORTED, INVALID_ARG.  Does not run any solver work. */
+int tmop_pool_admit(tmop_pool *pool, const tmop_mesh_desc *mesh, const tmop_params *prm,
+                    const tmop_solve_params *sp, const double *x_dev, void *src_stream,
+                    int *slot);
+
+/* Advance every unfinished solve by one Newton iteration (new solves first
+ * get their initial energy, det check and gradient).  *n_active receives the
+ * number of unfinished solves.  Synchronises the pool's stream. */
+int tmop_pool_step(tmop_pool *pool, int *n_active);
+
+/* Status of a slot: *done = 1 once the solve has finished (report.status
+ * tells how); the report carries iteration counts, F, |g| and the wall time
+ * since admission. */
+int tmop_pool_poll(tmop_pool *pool, int slot, int *done, tmop_solve_report *rep);
+
+/* Copy a slot's current nodes to the caller's device buffer (synchronises). */
+int tmop_pool_result(tmop_pool *pool, int slot, double *x_dev, void *dst_stream);
+
+/* Free a slot and its arena region. */
+int tmop_pool_release(tmop_pool *pool, int slot);
+
+/* Bytes in use, budget, and occupied slots. */
+int tmop_pool_info(tmop_pool *pool, size_t *used_bytes, size_t *budget_bytes, int *slots_used);
+
+/* Enable (default) or disable HIP-graph replay of the MINRES iterations. */
+int tmop_pool_set_graph(tmop_pool *pool, int enable);
+
+/* Thread-local description of the last pool error. */
+const char *tmop_pool_last_error(void);
+
+/* Solve count independent meshes together (a pool sized to fit them all):
+ * x_devs[k] holds mesh k's nodes on entry and the optimised nodes on return;
+ * reps[k] its report.  Returns the first error, if any. */
+int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params *prms,
+                     double *const *x_devs, const tmop_solve_params *sps,
+                     tmop_solve_report *reps, void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* Timing helpers                                                          */

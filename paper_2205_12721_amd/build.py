@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libtmop_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["k2.hip", "k3_p1.hip", "k3_p2.hip", "k3_p3.hip", "k3_p4.hip", "vec.hip", "capi.hip"]
+SOURCES = ["k2.hip", "k3_p1.hip", "k3_p2.hip", "k3_p3.hip", "k3_p4.hip", "vec.hip", "batch.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

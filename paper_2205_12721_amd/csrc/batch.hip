@@ -1,0 +1,1297 @@
+// Batched and served TMOP solves: many meshes of different orders advance
+// together through the Newton-MINRES loop (Sec. 2.3), each phase issued as
+// one launch per kernel class (dim, p, n_q) over a tile list that spans every
+// participating mesh, plus chunked vector launches over all meshes' DoFs.
+//
+// Memory: one device arena sized by an HBM budget; each admitted mesh (slot)
+// takes one contiguous region holding its DoF vectors, quadrature data and
+// E-vector scratch (first-fit allocation).  Per-mesh reductions are segmented:
+// a vector tile never straddles two meshes, and a mesh's sums run over its
+// own tiles in a fixed order, so a mesh's arithmetic does not depend on the
+// other meshes in the batch.
+//
+// MINRES runs in lockstep for all meshes with a device-resident,
+// double-buffered state per mesh (iteration counter included), so a block of
+// six iterations is position independent and is captured once as a hipGraph
+// and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tmop.h"
+#include "ops.hpp"
+#include "tmop_dev.hpp"
+#include "gather.hpp"
+#include "vec.hpp"
+
+namespace tmop {
+
+// vector ids inside SlotDev::vec
+enum {
+    BX, BXT, BG, BGT, BDX, BR1, BR2, BHV, BV, BW, BW1, BW2, BMINV, BDIAG, BY, BNV
+};
+static_assert(BNV <= NVEC, "too many vectors per slot");
+
+constexpr int VB = 256;      // threads per vector block
+constexpr int VCH = 8 * VB;  // DoFs per vector tile
+
+struct VTile {
+    int slot;
+    int start;
+    int count;
+};
+
+// per-slot tile ranges for segmented reductions
+struct SlotRange {
+    int ebase;    // first element-tile partial (absolute index in the partial array)
+    int ecount;   // element tiles of the slot
+    int estride;  // tiles of the slot's class launch (stride between partial planes)
+    int vbegin;   // first vector tile
+    int vcount;   // vector tiles of the slot
+};
+
+// per-slot device scalars
+enum { SC_F, SC_MD, SC_BAD, SC_DOT, SC_DMAX, SC_ALPHA, NSC = 8 };
+
+// Per-slot MINRES state (double-buffered): like MinresState plus the
+// iteration counter and cap.
+struct BState {
+    double beta1, beta, oldb, dbar, eps, phibar, cs, sn, rtol;
+    int j, maxit, stop, indefinite;
+};
+
+__device__ inline bool bs_skip(const BState &s) { return s.j > s.stop || s.j >= s.maxit; }
+
+// sum of part[b .. b+n) in a fixed order, identical in every block
+__device__ inline double seg_sum(const double *__restrict__ part, int b, int n, double *red)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += VB) s += part[b + k];
+    s = block_sum(s, red);
+    __shared__ double bc;
+    if (threadIdx.x == 0) bc = s;
+    __syncthreads();
+    return bc;
+}
+
+// ---------------------------------------------------------------------------
+// Segmented reductions: one block per slot
+// ---------------------------------------------------------------------------
+
+// energy partials of element tiles -> F, min det, bad count
+__global__ __launch_bounds__(VB) void kr_energy(const SlotRange *__restrict__ rg,
+                                                const int *__restrict__ gate,
+                                                const double *__restrict__ part,
+                                                double *__restrict__ sc)
+{
+    const int s = blockIdx.x;
+    if (!gate[s]) return;
+    __shared__ double red[VB / 64];
+    const SlotRange r = rg[s];
+    double a = 0.0, m = 1.0e300, b = 0.0;
+    for (int k = threadIdx.x; k < r.ecount; k += VB) {
+        a += part[r.ebase + k];
+        m = fmin(m, part[r.ebase + r.estride + k]);
+        b += part[r.ebase + 2 * r.estride + k];
+    }
+    a = block_sum(a, red);
+    m = block_min(m, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        sc[s * NSC + SC_F] = a;
+        sc[s * NSC + SC_MD] = m;
+        sc[s * NSC + SC_BAD] = b;
+    }
+}
+
+// vector-tile partials -> per-slot sum (op 0) or max (op 1) into sc[slot*NSC + which]
+__global__ __launch_bounds__(VB) void kr_vec(const SlotRange *__restrict__ rg,
+                                             const int *__restrict__ gate,
+                                             const double *__restrict__ part, int op, int which,
+                                             double *__restrict__ sc)
+{
+    const int s = blockIdx.x;
+    if (!gate[s]) return;
+    __shared__ double red[VB / 64];
+    const SlotRange r = rg[s];
+    double a = 0.0;
+    for (int k = threadIdx.x; k < r.vcount; k += VB)
+        a = op == 0 ? a + part[r.vbegin + k] : fmax(a, part[r.vbegin + k]);
+    a = op == 0 ? block_sum(a, red) : -block_min(-a, red);
+    if (threadIdx.x == 0) sc[s * NSC + which] = a;
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels over vector tiles
+// ---------------------------------------------------------------------------
+
+#define VT_PROLOGUE                                     \
+    const VTile t = vt[blockIdx.x];                     \
+    if (gate && !gate[t.slot]) return;                  \
+    const SlotDev &S = slots[t.slot];                   \
+    const int i0 = t.start + threadIdx.x, i1 = t.start + t.count;
+
+__global__ __launch_bounds__(VB) void kv_step(const VTile *__restrict__ vt,
+                                              const SlotDev *__restrict__ slots,
+                                              const int *__restrict__ gate,
+                                              const double *__restrict__ sc)
+{
+    VT_PROLOGUE
+    const double a = sc[t.slot * NSC + SC_ALPHA];
+    const double *x = S.vec[BX], *dx = S.vec[BDX];
+    double *xt = S.vec[BXT];
+    for (int i = i0; i < i1; i += VB) xt[i] = x[i] - a * dx[i];
+}
+
+__global__ __launch_bounds__(VB) void kv_copy(const VTile *__restrict__ vt,
+                                              const SlotDev *__restrict__ slots,
+                                              const int *__restrict__ gate, int vs, int vd)
+{
+    VT_PROLOGUE
+    const double *a = S.vec[vs];
+    double *b = S.vec[vd];
+    for (int i = i0; i < i1; i += VB) b[i] = a[i];
+}
+
+__global__ __launch_bounds__(VB) void kv_dot(const VTile *__restrict__ vt,
+                                             const SlotDev *__restrict__ slots,
+                                             const int *__restrict__ gate, int va, int vb,
+                                             double *__restrict__ part)
+{
+    VT_PROLOGUE
+    __shared__ double red[VB / 64];
+    const double *a = S.vec[va], *b = S.vec[vb];
+    double s = 0.0;
+    for (int i = i0; i < i1; i += VB) s += a[i] * b[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(VB) void kv_absmax(const VTile *__restrict__ vt,
+                                                const SlotDev *__restrict__ slots,
+                                                const int *__restrict__ gate, int va,
+                                                double *__restrict__ part)
+{
+    VT_PROLOGUE
+    __shared__ double red[VB / 64];
+    const double *a = S.vec[va];
+    double s = 0.0;
+    for (int i = i0; i < i1; i += VB) s = fmax(s, fabs(a[i]));
+    s = -block_min(-s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(VB) void kv_jacobi(const VTile *__restrict__ vt,
+                                                const SlotDev *__restrict__ slots,
+                                                const int *__restrict__ gate,
+                                                const double *__restrict__ sc)
+{
+    VT_PROLOGUE
+    const double floor = 1e-14 * sc[t.slot * NSC + SC_DMAX];
+    const double *d = S.vec[BDIAG];
+    double *m = S.vec[BMINV];
+    for (int i = i0; i < i1; i += VB) {
+        const double a = fmax(fabs(d[i]), floor);
+        m[i] = a > 0.0 ? 1.0 / a : 1.0;
+    }
+}
+
+// out = G^T eV of the slot; fixed DoFs get 0 / 1 / vec[vsrc]
+template <int DIM, typename ET>
+__global__ __launch_bounds__(VB) void kv_gather(const VTile *__restrict__ vt,
+                                                const SlotDev *__restrict__ slots,
+                                                const int *__restrict__ gate, int vout,
+                                                int fix_mode, int vsrc)
+{
+    VT_PROLOGUE
+    const Geom &g = S.g;
+    const ET *eV = (const ET *)S.eV;
+    double *out = S.vec[vout];
+    const double *src = S.vec[vsrc];
+    for (int i = i0; i < i1; i += VB) {
+        const int c = i / g.nx, node = i - c * g.nx;
+        int gc[3];
+        gc[0] = node % g.M[0];
+        const int tt = node / g.M[0];
+        gc[1] = DIM == 3 ? tt % g.M[1] : tt;
+        gc[2] = DIM == 3 ? tt / g.M[1] : 0;
+        const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
+        double v;
+        if (fixed)
+            v = fix_mode == 0 ? 0.0 : (fix_mode == 1 ? 1.0 : src[i]);
+        else
+            v = (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
+        out[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MINRES (see vec.hip for the recurrences); per-slot state st[2*slot + parity]
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(VB) void kv_mr_init(const VTile *__restrict__ vt,
+                                                 const SlotDev *__restrict__ slots,
+                                                 const int *__restrict__ gate,
+                                                 const int *__restrict__ jac,
+                                                 double *__restrict__ part)
+{
+    VT_PROLOGUE
+    __shared__ double red[VB / 64];
+    const bool useM = jac[t.slot] != 0;
+    const double *b = S.vec[BG], *m = S.vec[BMINV];
+    double *r1 = S.vec[BR1], *r2 = S.vec[BR2], *y = S.vec[BY];
+    double s = 0.0;
+    for (int i = i0; i < i1; i += VB) {
+        const double bi = b[i];
+        const double yi = useM ? m[i] * bi : bi;
+        r1[i] = bi;
+        r2[i] = bi;
+        y[i] = yi;
+        s += bi * yi;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
+                                                  const SlotDev *__restrict__ slots,
+                                                  const int *__restrict__ gate,
+                                                  const SlotRange *__restrict__ rg,
+                                                  const double *__restrict__ part,
+                                                  const int *__restrict__ maxit, double rtol,
+                                                  BState *__restrict__ st,
+                                                  int *__restrict__ run)
+{
+    VT_PROLOGUE
+    __shared__ double red[VB / 64];
+    const SlotRange r = rg[t.slot];
+    const double bb = seg_sum(part, r.vbegin, r.vcount, red);
+    const double b1 = sqrt(fmax(bb, 0.0));
+    const double sv = b1 > 0.0 ? 1.0 / b1 : 0.0;
+    const double *y = S.vec[BY];
+    double *v = S.vec[BV], *x = S.vec[BDX], *w = S.vec[BW], *w1 = S.vec[BW1], *w2 = S.vec[BW2];
+    for (int i = i0; i < i1; i += VB) {
+        v[i] = sv * y[i];
+        x[i] = 0.0;
+        w[i] = 0.0;
+        w1[i] = 0.0;
+        w2[i] = 0.0;
+    }
+    if (t.start == 0 && threadIdx.x == 0) {
+        BState o;
+        o.beta1 = b1;
+        o.beta = b1;
+        o.oldb = 0.0;
+        o.dbar = 0.0;
+        o.eps = 0.0;
+        o.phibar = b1;
+        o.cs = -1.0;
+        o.sn = 0.0;
+        o.rtol = rtol;
+        o.j = 0;
+        o.maxit = maxit[t.slot];
+        o.stop = (b1 > 0.0 && bb >= 0.0) ? 0x7fffffff : -1;
+        o.indefinite = bb < 0.0 ? 1 : 0;
+        st[2 * t.slot] = o;
+        st[2 * t.slot + 1] = o;
+        run[t.slot] = bs_skip(o) ? 0 : 1;
+    }
+}
+
+template <int DIM, typename ET>
+__global__ __launch_bounds__(VB) void kv_mr_gather_l1(const VTile *__restrict__ vt,
+                                                      const SlotDev *__restrict__ slots,
+                                                      const int *__restrict__ gate,
+                                                      const BState *__restrict__ st, int par,
+                                                      int vr1, int vhv,
+                                                      double *__restrict__ part)
+{
+    VT_PROLOGUE
+    const BState &s = st[2 * t.slot + par];
+    if (bs_skip(s)) return;
+    __shared__ double red[VB / 64];
+    const double cr = s.j >= 1 ? s.beta / s.oldb : 0.0;
+    const Geom &g = S.g;
+    const ET *eV = (const ET *)S.eV;
+    const double *v = S.vec[BV], *r1 = S.vec[vr1];
+    double *hv = S.vec[vhv];
+    double acc = 0.0;
+    for (int i = i0; i < i1; i += VB) {
+        const int c = i / g.nx, node = i - c * g.nx;
+        int gc[3];
+        gc[0] = node % g.M[0];
+        const int tt = node / g.M[0];
+        gc[1] = DIM == 3 ? tt % g.M[1] : tt;
+        gc[2] = DIM == 3 ? tt / g.M[1] : 0;
+        const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
+        const double vi = v[i];
+        double h = fixed ? vi : (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
+        if (s.j >= 1) h -= cr * r1[i];
+        hv[i] = h;
+        acc += vi * h;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
+                                               const SlotDev *__restrict__ slots,
+                                               const int *__restrict__ gate,
+                                               const SlotRange *__restrict__ rg,
+                                               const int *__restrict__ jac,
+                                               const BState *__restrict__ st, int par,
+                                               const double *__restrict__ part1, int vhv, int vr2,
+                                               int vz, double *__restrict__ part2)
+{
+    VT_PROLOGUE
+    const BState &s = st[2 * t.slot + par];
+    if (bs_skip(s)) return;
+    __shared__ double red[VB / 64];
+    const SlotRange r = rg[t.slot];
+    const double alpha = seg_sum(part1, r.vbegin, r.vcount, red);
+    const double c = alpha / s.beta;
+    const bool useM = jac[t.slot] != 0;
+    const double *m = S.vec[BMINV], *r2 = S.vec[vr2];
+    double *hv = S.vec[vhv], *z = S.vec[vz];
+    double acc = 0.0;
+    for (int i = i0; i < i1; i += VB) {
+        const double h = hv[i] - c * r2[i];
+        hv[i] = h;
+        const double zi = useM ? m[i] * h : h;
+        z[i] = zi;
+        acc += h * zi;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part2[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(VB) void kv_mr_update(const VTile *__restrict__ vt,
+                                                   const SlotDev *__restrict__ slots,
+                                                   const int *__restrict__ gate,
+                                                   const SlotRange *__restrict__ rg,
+                                                   BState *__restrict__ st, int par,
+                                                   const double *__restrict__ part1,
+                                                   const double *__restrict__ part2, int vw1,
+                                                   int vw2, int vwout, int vz,
+                                                   int *__restrict__ run)
+{
+    VT_PROLOGUE
+    const BState si = st[2 * t.slot + par];
+    BState *so = st + 2 * t.slot + (par ^ 1);
+    if (bs_skip(si)) {
+        if (t.start == 0 && threadIdx.x == 0) {
+            *so = si;
+            run[t.slot] = 0;
+        }
+        return;
+    }
+    __shared__ double red[VB / 64];
+    const SlotRange r = rg[t.slot];
+    const double alpha = seg_sum(part1, r.vbegin, r.vcount, red);
+    const double bb = seg_sum(part2, r.vbegin, r.vcount, red);
+    const double beta = sqrt(fmax(bb, 0.0));
+    const double oldeps = si.eps;
+    const double delta = si.cs * si.dbar + si.sn * alpha;
+    const double gbar = si.sn * si.dbar - si.cs * alpha;
+    const double gamma = fmax(hypot(gbar, beta), 2.2250738585072014e-308);
+    const double cs = gbar / gamma, sn = beta / gamma;
+    const double phi = cs * si.phibar;
+    const double ig = 1.0 / gamma;
+    const double sv = beta > 0.0 ? 1.0 / beta : 0.0;
+    double *v = S.vec[BV], *x = S.vec[BDX], *wo = S.vec[vwout];
+    const double *w1 = S.vec[vw1], *w2 = S.vec[vw2], *z = S.vec[vz];
+    for (int i = i0; i < i1; i += VB) {
+        const double wn = (v[i] - oldeps * w1[i] - delta * w2[i]) * ig;
+        wo[i] = wn;
+        x[i] += phi * wn;
+        v[i] = sv * z[i];
+    }
+    if (t.start == 0 && threadIdx.x == 0) {
+        BState o = si;
+        o.oldb = si.beta;
+        o.beta = beta;
+        o.eps = si.sn * beta;
+        o.dbar = -si.cs * beta;
+        o.cs = cs;
+        o.sn = sn;
+        o.phibar = sn * si.phibar;
+        if (bb < 0.0) o.indefinite = 1;
+        if (o.phibar <= si.rtol * si.beta1 || beta == 0.0) o.stop = si.j;
+        o.j = si.j + 1;
+        *so = o;
+        run[t.slot] = bs_skip(o) ? 0 : 1;
+    }
+}
+
+}  // namespace tmop
+
+// ===========================================================================
+// Host engine
+// ===========================================================================
+
+using namespace tmop;
+
+namespace {
+
+thread_local std::string g_perr;
+
+int pfail(int code, const std::string &m)
+{
+    g_perr = m;
+    return code;
+}
+
+#define PHIP(call)                                                                           \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return pfail(e_ == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,            \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+#define PCHK(call)                    \
+    do {                              \
+        int r_ = (call);              \
+        if (r_ != TMOP_OK) return r_; \
+    } while (0)
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct ClassKey {
+    int dim, p, nq, storage, prec;
+    bool operator<(const ClassKey &o) const
+    {
+        return std::tie(dim, p, nq, storage, prec) < std::tie(o.dim, o.p, o.nq, o.storage, o.prec);
+    }
+};
+
+struct ClassH {
+    ClassKey key{};
+    BOps bops{};
+    Tables tb{};
+    std::vector<Tile> tiles;
+    Tile *d_tiles = nullptr;
+    int cap = 0;
+    int pbase = 0;
+};
+
+enum { PH_NEW = 0, PH_ITER = 1, PH_DONE = 2 };
+
+struct SlotH {
+    bool used = false;
+    int dim = 0, p = 0, nq = 0, storage = 0, prec = 0;
+    int ne = 0, nx = 0, ndof = 0, nqe = 0, np = 0, S = 0;
+    size_t off = 0, bytes = 0;
+    SlotDev dev{};
+    tmop_solve_params sp{};
+    int phase = PH_NEW;
+    int status = TMOP_OK;
+    double F = 0, F0 = 0, gn = 0, g0 = 0, alpha = 1.0;
+    int newton_its = 0, minres_its = 0, halvings = 0;
+    double t_start = 0, t_done = 0;
+    int first_vt = 0, nvt = 0;
+};
+
+}  // namespace
+
+// sizes of one request (mesh + params); returns false if invalid
+static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH &s, std::string &why)
+{
+    if (!m || !prm) {
+        why = "null mesh or params";
+        return TMOP_ERR_INVALID_ARG;
+    }
+    if (m->elem_to_node) {
+        why = "pooled solves take structured boxes (elem_to_node must be NULL)";
+        return TMOP_ERR_UNSUPPORTED;
+    }
+    if (m->dim != 2 && m->dim != 3) {
+        why = "dim must be 2 or 3";
+        return TMOP_ERR_INVALID_ARG;
+    }
+    if (!((m->dim == 2 && prm->metric == 2) || (m->dim == 3 && prm->metric == 303))) {
+        why = "metric must be 2 (dim 2) or 303 (dim 3)";
+        return TMOP_ERR_UNSUPPORTED;
+    }
+    if (m->ess_mode == TMOP_ESS_MASK && !m->ess_mask) {
+        why = "TMOP_ESS_MASK needs ess_mask";
+        return TMOP_ERR_INVALID_ARG;
+    }
+    const int d = m->dim, p = m->order_p;
+    if (p < 1 || p > 4 || m->nx <= 0 || m->ny <= 0 || (d == 3 && m->nz <= 0)) {
+        why = "order 1..4 and positive element counts required";
+        return TMOP_ERR_INVALID_ARG;
+    }
+    s.dim = d;
+    s.p = p;
+    s.nq = prm->nq1d;
+    s.storage = prm->hess_storage == TMOP_HESS_COMPACT ? 1 : 0;
+    s.prec = prm->precision == TMOP_MIXED ? 1 : 0;
+    const long ne = (long)m->nx * m->ny * (d == 3 ? m->nz : 1);
+    const long nx = (long)(m->nx * p + 1) * (m->ny * p + 1) * (d == 3 ? (m->nz * p + 1) : 1);
+    if (ne * (long)(p + 1) * (p + 1) * (p + 1) * 3 > 0x7fffffffL || nx * 3 > 0x7fffffffL) {
+        why = "mesh too large";
+        return TMOP_ERR_INVALID_ARG;
+    }
+    s.ne = (int)ne;
+    s.nx = (int)nx;
+    s.ndof = (int)(d * nx);
+    s.nqe = d == 3 ? s.nq * s.nq * s.nq : s.nq * s.nq;
+    s.np = d == 3 ? (p + 1) * (p + 1) * (p + 1) : (p + 1) * (p + 1);
+    s.S = s.storage ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
+    const size_t tb = s.prec ? 4 : 8;
+    s.bytes = BNV * up256((size_t)s.ndof * 8) + up256((size_t)s.ne * s.nqe * s.S * tb) +
+              up256((size_t)s.ne * d * s.np * 8);
+    return TMOP_OK;
+}
+
+
+struct tmop_pool {
+    hipStream_t s = nullptr;
+    size_t budget = 0, used = 0;
+    int max_slots = 0;
+    char *arena = nullptr;
+    std::map<size_t, size_t> free_;  // offset -> size
+    std::vector<SlotH> slots;
+    std::map<ClassKey, ClassH> classes;
+    // device tables
+    SlotDev *d_slots = nullptr;
+    SlotRange *d_rg = nullptr;
+    VTile *d_vt = nullptr;
+    int vt_cap = 0;
+    double *d_part = nullptr;
+    size_t part_cap = 0;
+    double *d_sc = nullptr;
+    BState *d_st = nullptr;
+    int *d_run = nullptr, *d_jac = nullptr, *d_maxit = nullptr;
+    int *d_gate[5] = {};
+    int *h_gate[5] = {};
+    double *h_sc = nullptr;
+    BState *h_st = nullptr;
+    int *h_int = nullptr;
+    // layout
+    std::vector<VTile> vts;
+    std::vector<SlotRange> rg;
+    int vt_range[4][2] = {};  // [dim3 fp64, dim3 mixed, dim2 fp64, dim2 mixed] -> [begin, count]
+    int epart = 0;            // element partials (3 planes per class)
+    bool dirty = true;
+    // graph of six MINRES iterations
+    bool use_graph = true;
+    bool graph_ok = false;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+static void pool_free_region(tmop_pool *P, size_t off, size_t bytes)
+{
+    // insert and merge
+    auto it = P->free_.emplace(off, bytes).first;
+    if (it != P->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            P->free_.erase(it);
+            it = pv;
+        }
+    }
+    auto nx = std::next(it);
+    if (nx != P->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        P->free_.erase(nx);
+    }
+}
+
+static bool pool_alloc_region(tmop_pool *P, size_t bytes, size_t *off)
+{
+    for (auto it = P->free_.begin(); it != P->free_.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes, noff = it->first + bytes;
+            P->free_.erase(it);
+            if (rest) P->free_.emplace(noff, rest);
+            return true;
+        }
+    }
+    return false;
+}
+
+static int upload_gate(tmop_pool *P, int k)
+{
+    PHIP(hipMemcpyAsync(P->d_gate[k], P->h_gate[k], sizeof(int) * P->max_slots,
+                        hipMemcpyHostToDevice, P->s));
+    return TMOP_OK;
+}
+
+static void invalidate_graph(tmop_pool *P)
+{
+    if (P->gexec) hipGraphExecDestroy(P->gexec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    P->graph_ok = false;
+}
+
+// Rebuild tile lists, vector tiles, ranges and partial layout for the used slots.
+static int pool_rebuild(tmop_pool *P)
+{
+    invalidate_graph(P);
+    for (auto &kv : P->classes) kv.second.tiles.clear();
+    // element tiles per class
+    for (int si = 0; si < P->max_slots; ++si) {
+        SlotH &s = P->slots[si];
+        if (!s.used) continue;
+        ClassKey k{s.dim, s.p, s.nq, s.storage, s.prec};
+        auto it = P->classes.find(k);
+        if (it == P->classes.end()) {
+            ClassH c;
+            c.key = k;
+            if (!find_bops(s.dim, s.p, s.nq, &c.bops))
+                return pfail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d)");
+            if (internal_tables(s.p, s.nq, &c.tb) != TMOP_OK)
+                return pfail(TMOP_ERR_INVALID_ARG, "bad order / quadrature");
+            it = P->classes.emplace(k, c).first;
+        }
+        ClassH &c = it->second;
+        for (int e = 0; e < s.ne; e += c.bops.epb) c.tiles.push_back(Tile{si, e});
+    }
+    int pb = 0;
+    P->rg.assign(P->max_slots, SlotRange{0, 0, 1, 0, 0});
+    for (auto &kv : P->classes) {
+        ClassH &c = kv.second;
+        c.pbase = pb;
+        const int nt = (int)c.tiles.size();
+        if (nt > c.cap) {
+            hipFree(c.d_tiles);
+            c.d_tiles = nullptr;
+            c.cap = std::max(nt, 2 * c.cap);
+            PHIP(hipMalloc((void **)&c.d_tiles, sizeof(Tile) * c.cap));
+        }
+        if (nt) PHIP(hipMemcpyAsync(c.d_tiles, c.tiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice, P->s));
+        for (int t = 0; t < nt; ++t) {
+            SlotRange &r = P->rg[c.tiles[t].slot];
+            if (r.ecount == 0) {
+                r.ebase = pb + t;
+                r.estride = nt;
+            }
+            r.ecount++;
+        }
+        pb += 3 * nt;
+    }
+    P->epart = pb;
+    // vector tiles grouped as (3D fp64, 3D mixed, 2D fp64, 2D mixed)
+    P->vts.clear();
+    for (int grp = 0; grp < 4; ++grp) {
+        const int gd = grp < 2 ? 3 : 2, gp = grp & 1;
+        P->vt_range[grp][0] = (int)P->vts.size();
+        for (int si = 0; si < P->max_slots; ++si) {
+            SlotH &s = P->slots[si];
+            if (!s.used || s.dim != gd || s.prec != gp) continue;
+            s.first_vt = (int)P->vts.size();
+            for (int st = 0; st < s.ndof; st += VCH)
+                P->vts.push_back(VTile{si, st, std::min(VCH, s.ndof - st)});
+            s.nvt = (int)P->vts.size() - s.first_vt;
+            P->rg[si].vbegin = s.first_vt;
+            P->rg[si].vcount = s.nvt;
+        }
+        P->vt_range[grp][1] = (int)P->vts.size() - P->vt_range[grp][0];
+    }
+    const int nvt = (int)P->vts.size();
+    if (nvt > P->vt_cap) {
+        hipFree(P->d_vt);
+        P->d_vt = nullptr;
+        P->vt_cap = std::max(nvt, 2 * P->vt_cap);
+        PHIP(hipMalloc((void **)&P->d_vt, sizeof(VTile) * P->vt_cap));
+    }
+    if (nvt) PHIP(hipMemcpyAsync(P->d_vt, P->vts.data(), sizeof(VTile) * nvt, hipMemcpyHostToDevice, P->s));
+    const size_t need = (size_t)P->epart + 2 * (size_t)nvt + 64;
+    if (need > P->part_cap) {
+        hipFree(P->d_part);
+        P->d_part = nullptr;
+        P->part_cap = std::max(need, 2 * P->part_cap);
+        PHIP(hipMalloc((void **)&P->d_part, sizeof(double) * P->part_cap));
+    }
+    PHIP(hipMemcpyAsync(P->d_rg, P->rg.data(), sizeof(SlotRange) * P->max_slots, hipMemcpyHostToDevice, P->s));
+    PHIP(hipStreamSynchronize(P->s));
+    P->dirty = false;
+    return TMOP_OK;
+}
+
+// --- batched phase launchers ------------------------------------------------
+
+static double *vpart1(tmop_pool *P) { return P->d_part + P->epart; }
+static double *vpart2(tmop_pool *P) { return P->d_part + P->epart + P->vts.size(); }
+
+static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
+{
+    for (auto &kv : P->classes) {
+        ClassH &c = kv.second;
+        const int nt = (int)c.tiles.size();
+        if (!nt) continue;
+        const int st = c.key.storage, pr = c.key.prec;
+        BLaunch f = which == 0   ? c.bops.energy
+                    : which == 1 ? c.bops.gradient
+                    : which == 2 ? c.bops.setup[st][pr]
+                    : which == 3 ? c.bops.apply[st][pr]
+                                 : c.bops.diag[st][pr];
+        f(nt, P->s, c.tb, c.d_tiles, P->d_slots, gate, vin, P->d_part + c.pbase);
+    }
+}
+
+static void launch_gather(tmop_pool *P, const int *gate, int vout, int fix_mode, int vsrc, bool ev32)
+{
+    for (int grp = 0; grp < 4; ++grp) {
+        const int b = P->vt_range[grp][0], n = P->vt_range[grp][1];
+        if (!n) continue;
+        const bool f32 = ev32 && (grp & 1);
+        const VTile *vt = P->d_vt + b;
+        if (grp < 2) {
+            if (f32)
+                hipLaunchKernelGGL((kv_gather<3, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, gate, vout, fix_mode, vsrc);
+            else
+                hipLaunchKernelGGL((kv_gather<3, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, gate, vout, fix_mode, vsrc);
+        } else {
+            if (f32)
+                hipLaunchKernelGGL((kv_gather<2, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, gate, vout, fix_mode, vsrc);
+            else
+                hipLaunchKernelGGL((kv_gather<2, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, gate, vout, fix_mode, vsrc);
+        }
+    }
+}
+
+static int nvt_all(tmop_pool *P) { return (int)P->vts.size(); }
+
+static void dot_to_sc(tmop_pool *P, const int *gate, int va, int vb, int which)
+{
+    const int n = nvt_all(P);
+    if (!n) return;
+    hipLaunchKernelGGL(kv_dot, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, gate, va, vb, vpart1(P));
+    hipLaunchKernelGGL(kr_vec, dim3(P->max_slots), dim3(VB), 0, P->s, P->d_rg, gate, vpart1(P), 0, which, P->d_sc);
+}
+
+static void energy_to_sc(tmop_pool *P, const int *gate, int vin)
+{
+    launch_elem(P, 0, gate, vin);
+    hipLaunchKernelGGL(kr_energy, dim3(P->max_slots), dim3(VB), 0, P->s, P->d_rg, gate, P->d_part, P->d_sc);
+}
+
+static void gradient_to(tmop_pool *P, const int *gate, int vin, int vout)
+{
+    launch_elem(P, 1, gate, vin);
+    launch_gather(P, gate, vout, 0, vout, false);
+}
+
+static int read_sc(tmop_pool *P)
+{
+    PHIP(hipMemcpyAsync(P->h_sc, P->d_sc, sizeof(double) * NSC * P->max_slots, hipMemcpyDeviceToHost, P->s));
+    PHIP(hipStreamSynchronize(P->s));
+    return TMOP_OK;
+}
+
+// one lockstep MINRES iteration for all running slots; ids rotate with k
+static void minres_iter(tmop_pool *P, int k)
+{
+    // ids of (r1, r2, hv) rotate with period 3, (w, w1, w2) likewise; state parity period 2
+    static const int R[3][3] = {{BR1, BR2, BHV}, {BR2, BHV, BR1}, {BHV, BR1, BR2}};
+    static const int W[3][3] = {{BW, BW1, BW2}, {BW1, BW2, BW}, {BW2, BW, BW1}};
+    const int r1 = R[k % 3][0], r2 = R[k % 3][1], hv = R[k % 3][2];
+    const int w = W[k % 3][0], w1 = W[k % 3][1], w2 = W[k % 3][2];
+    const int par = k & 1;
+    launch_elem(P, 3, P->d_run, BV);
+    for (int grp = 0; grp < 4; ++grp) {
+        const int b = P->vt_range[grp][0], n = P->vt_range[grp][1];
+        if (!n) continue;
+        const VTile *vt = P->d_vt + b;
+        double *pp = vpart1(P) + b;
+        if (grp == 0)
+            hipLaunchKernelGGL((kv_mr_gather_l1<3, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+        else if (grp == 1)
+            hipLaunchKernelGGL((kv_mr_gather_l1<3, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+        else if (grp == 2)
+            hipLaunchKernelGGL((kv_mr_gather_l1<2, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+        else
+            hipLaunchKernelGGL((kv_mr_gather_l1<2, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+    }
+    const int n = nvt_all(P);
+    // z goes to the r1 buffer (r1 is dead after gather_l1)
+    hipLaunchKernelGGL(kv_mr_l2, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_jac, P->d_st, par, vpart1(P), hv, r2, r1, vpart2(P));
+    // new w into the old w1 buffer; formula (w1, w2) = (old w2, old w)
+    hipLaunchKernelGGL(kv_mr_update, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_st, par, vpart1(P), vpart2(P), w2, w, w1, r1, P->d_run);
+    (void)w;
+}
+
+static int run_minres(tmop_pool *P, int maxj)
+{
+    const int nv = nvt_all(P);
+    hipLaunchKernelGGL(kv_mr_init, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_jac, vpart1(P));
+    double rtol = 1e-12;
+    for (auto &s : P->slots)
+        if (s.used && s.phase == PH_ITER) rtol = s.sp.minres_rtol;
+    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, rtol, P->d_st, P->d_run);
+    int j = 0;
+    while (j < maxj) {
+        if (P->use_graph && maxj - j >= 6) {
+            if (!P->graph_ok) {
+                PHIP(hipStreamBeginCapture(P->s, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < 6; ++k) minres_iter(P, k);
+                PHIP(hipStreamEndCapture(P->s, &P->graph));
+                PHIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+                P->graph_ok = true;
+            }
+            PHIP(hipGraphLaunch(P->gexec, P->s));
+            j += 6;
+        } else {
+            // the ids/parity of a partial block continue from position j % 6 == 0
+            for (int k = 0; j < maxj && k < 6; ++k, ++j) minres_iter(P, k);
+        }
+        if (j < maxj && j % 12 == 0) {
+            PHIP(hipMemcpyAsync(P->h_int, P->d_run, sizeof(int) * P->max_slots, hipMemcpyDeviceToHost, P->s));
+            PHIP(hipStreamSynchronize(P->s));
+            bool any = false;
+            for (int si = 0; si < P->max_slots; ++si) any = any || (P->slots[si].used && P->h_int[si]);
+            if (!any) break;
+        }
+    }
+    PHIP(hipMemcpyAsync(P->h_st, P->d_st, sizeof(BState) * 2 * P->max_slots, hipMemcpyDeviceToHost, P->s));
+    PHIP(hipStreamSynchronize(P->s));
+    PHIP(hipGetLastError());
+    return TMOP_OK;
+}
+
+static void finish_slot(SlotH &s, int status)
+{
+    s.phase = PH_DONE;
+    s.status = status;
+    s.t_done = now_ms();
+}
+
+// One Newton iteration for every active slot (initial evaluation first for new slots).
+static int pool_step_impl(tmop_pool *P, int *n_active)
+{
+    if (P->dirty) PCHK(pool_rebuild(P));
+    const int M = P->max_slots;
+    // ---- initial evaluation of new slots -------------------------------
+    bool any_new = false;
+    for (int si = 0; si < M; ++si) {
+        SlotH &s = P->slots[si];
+        P->h_gate[0][si] = (s.used && s.phase == PH_NEW) ? 1 : 0;
+        any_new = any_new || P->h_gate[0][si];
+    }
+    if (any_new) {
+        PCHK(upload_gate(P, 0));
+        const int *g0 = P->d_gate[0];
+        dot_to_sc(P, g0, BX, BX, SC_DOT);
+        energy_to_sc(P, g0, BX);
+        gradient_to(P, g0, BX, BG);
+        PCHK(read_sc(P));
+        std::vector<double> xx(M);
+        for (int si = 0; si < M; ++si) xx[si] = P->h_sc[si * NSC + SC_DOT];
+        dot_to_sc(P, g0, BG, BG, SC_DOT);
+        PCHK(read_sc(P));
+        for (int si = 0; si < M; ++si) {
+            SlotH &s = P->slots[si];
+            if (!P->h_gate[0][si]) continue;
+            const double *sc = P->h_sc + si * NSC;
+            if (!std::isfinite(xx[si])) {
+                finish_slot(s, TMOP_ERR_NONFINITE);
+                continue;
+            }
+            if (sc[SC_BAD] > 0.0 || !(sc[SC_MD] > 0.0)) {
+                s.F = INFINITY;
+                finish_slot(s, TMOP_ERR_INVERTED);
+                continue;
+            }
+            s.F = s.F0 = sc[SC_F];
+            s.gn = std::sqrt(sc[SC_DOT]);
+            s.g0 = s.sp.g0_norm > 0.0 ? s.sp.g0_norm : s.gn;
+            s.phase = PH_ITER;
+            if (s.g0 == 0.0 || s.F == 0.0 || s.gn <= s.sp.rel_grad_tol * s.g0) finish_slot(s, TMOP_OK);
+        }
+    }
+    // ---- Newton iteration ---------------------------------------------
+    int maxj = 0, maxh = 0, nit = 0;
+    for (int si = 0; si < M; ++si) {
+        SlotH &s = P->slots[si];
+        if (s.used && s.phase == PH_ITER && s.newton_its >= s.sp.max_newton)
+            finish_slot(s, TMOP_ERR_NOT_CONVERGED);
+        const bool it = s.used && s.phase == PH_ITER;
+        P->h_gate[1][si] = it ? 1 : 0;
+        P->h_int[si] = it && s.sp.jacobi ? 1 : 0;
+        if (it) {
+            nit++;
+            maxj = std::max(maxj, s.sp.max_minres);
+            maxh = std::max(maxh, s.sp.max_halvings);
+        }
+    }
+    if (nit) {
+        PCHK(upload_gate(P, 1));
+        PHIP(hipMemcpyAsync(P->d_jac, P->h_int, sizeof(int) * M, hipMemcpyHostToDevice, P->s));
+        for (int si = 0; si < M; ++si) P->h_gate[4][si] = P->slots[si].sp.max_minres;
+        PHIP(hipMemcpyAsync(P->d_maxit, P->h_gate[4], sizeof(int) * M, hipMemcpyHostToDevice, P->s));
+        const int *g1 = P->d_gate[1];
+        launch_elem(P, 2, g1, BX);   // setup
+        launch_elem(P, 4, g1, BX);   // diagonal
+        launch_gather(P, g1, BDIAG, 1, BDIAG, false);
+        const int nv = nvt_all(P);
+        hipLaunchKernelGGL(kv_absmax, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, BDIAG, vpart1(P));
+        hipLaunchKernelGGL(kr_vec, dim3(M), dim3(VB), 0, P->s, P->d_rg, g1, vpart1(P), 1, SC_DMAX, P->d_sc);
+        hipLaunchKernelGGL(kv_jacobi, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, P->d_sc);
+        PCHK(run_minres(P, maxj));
+        for (int si = 0; si < M; ++si) {
+            SlotH &s = P->slots[si];
+            if (!P->h_gate[1][si]) continue;
+            const BState &a = P->h_st[2 * si], &b = P->h_st[2 * si + 1];
+            const BState &f = a.j >= b.j ? a : b;
+            s.minres_its += f.j;
+            if (f.indefinite) {
+                finish_slot(s, TMOP_ERR_NONFINITE);
+                P->h_gate[1][si] = 0;
+            }
+            s.alpha = 1.0;
+        }
+        // ---- line search rounds -------------------------------------------
+        for (int si = 0; si < M; ++si) P->h_gate[2][si] = P->h_gate[1][si];
+        for (int h = 0; h <= maxh; ++h) {
+            bool any = false;
+            for (int si = 0; si < M; ++si) {
+                any = any || P->h_gate[2][si];
+                P->h_sc[si * NSC + SC_ALPHA] = P->slots[si].alpha;
+            }
+            if (!any) break;
+            PCHK(upload_gate(P, 2));
+            PHIP(hipMemcpyAsync(P->d_sc, P->h_sc, sizeof(double) * NSC * M, hipMemcpyHostToDevice, P->s));
+            const int *g2 = P->d_gate[2];
+            hipLaunchKernelGGL(kv_step, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g2, P->d_sc);
+            energy_to_sc(P, g2, BXT);
+            PCHK(read_sc(P));
+            bool any3 = false;
+            std::vector<double> Ft(M);
+            for (int si = 0; si < M; ++si) {
+                const double *sc = P->h_sc + si * NSC;
+                const bool ok = P->h_gate[2][si] && sc[SC_BAD] == 0.0 && sc[SC_MD] > 0.0 &&
+                                sc[SC_F] < 1.2 * P->slots[si].F;
+                P->h_gate[3][si] = ok ? 1 : 0;
+                Ft[si] = sc[SC_F];
+                any3 = any3 || ok;
+            }
+            if (any3) {
+                PCHK(upload_gate(P, 3));
+                const int *g3 = P->d_gate[3];
+                gradient_to(P, g3, BXT, BGT);
+                dot_to_sc(P, g3, BGT, BGT, SC_DOT);
+                PCHK(read_sc(P));
+                bool anyacc = false;
+                for (int si = 0; si < M; ++si) {
+                    int acc = 0;
+                    if (P->h_gate[3][si]) {
+                        const double gtn = std::sqrt(P->h_sc[si * NSC + SC_DOT]);
+                        SlotH &s = P->slots[si];
+                        if (gtn < 1.2 * s.gn) {
+                            acc = 1;
+                            s.F = Ft[si];
+                            s.gn = gtn;
+                            s.newton_its++;
+                        }
+                    }
+                    P->h_gate[3][si] = acc;
+                    anyacc = anyacc || acc;
+                }
+                if (anyacc) {
+                    PCHK(upload_gate(P, 3));
+                    hipLaunchKernelGGL(kv_copy, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[3], BXT, BX);
+                    hipLaunchKernelGGL(kv_copy, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[3], BGT, BG);
+                    PHIP(hipStreamSynchronize(P->s));
+                }
+            }
+            for (int si = 0; si < M; ++si) {
+                if (!P->h_gate[2][si]) continue;
+                SlotH &s = P->slots[si];
+                if (any3 && P->h_gate[3][si]) {
+                    P->h_gate[2][si] = 0;  // accepted
+                    continue;
+                }
+                s.halvings++;
+                s.alpha *= 0.5;
+                if (h >= s.sp.max_halvings) {
+                    P->h_gate[2][si] = 0;
+                    finish_slot(s, TMOP_ERR_LINESEARCH);
+                }
+            }
+        }
+        // ---- convergence test ---------------------------------------------
+        for (int si = 0; si < M; ++si) {
+            SlotH &s = P->slots[si];
+            if (!s.used || s.phase != PH_ITER) continue;
+            if (s.F == 0.0 || s.gn <= s.sp.rel_grad_tol * s.g0) finish_slot(s, TMOP_OK);
+            else if (s.newton_its >= s.sp.max_newton) finish_slot(s, TMOP_ERR_NOT_CONVERGED);
+        }
+    }
+    int na = 0;
+    for (auto &s : P->slots) na += (s.used && s.phase != PH_DONE) ? 1 : 0;
+    if (n_active) *n_active = na;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_create(tmop_pool **out, size_t budget, int max_slots, void *stream)
+{
+    (void)stream;
+    if (!out || budget == 0 || max_slots <= 0 || max_slots > 65536)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad pool arguments");
+    *out = nullptr;
+    tmop_pool *P = new tmop_pool();
+    P->budget = budget;
+    P->max_slots = max_slots;
+    P->slots.resize(max_slots);
+    hipError_t e = hipStreamCreateWithFlags(&P->s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->arena, budget);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_slots, sizeof(SlotDev) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_rg, sizeof(SlotRange) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_sc, sizeof(double) * NSC * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_st, sizeof(BState) * 2 * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_run, sizeof(int) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_jac, sizeof(int) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_maxit, sizeof(int) * max_slots);
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        e = hipMalloc((void **)&P->d_gate[k], sizeof(int) * max_slots);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_gate[k], sizeof(int) * max_slots, 0);
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_sc, sizeof(double) * NSC * max_slots, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_st, sizeof(BState) * 2 * max_slots, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_int, sizeof(int) * max_slots, 0);
+    if (e != hipSuccess) {
+        tmop_pool_destroy(P);
+        return pfail(e == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,
+                     std::string("pool allocation: ") + hipGetErrorString(e));
+    }
+    P->free_.emplace(0, budget);
+    std::vector<int> z(max_slots, 0);
+    hipMemcpy(P->d_run, z.data(), sizeof(int) * max_slots, hipMemcpyHostToDevice);
+    *out = P;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_destroy(tmop_pool *P)
+{
+    if (!P) return TMOP_OK;
+    if (P->s) hipStreamSynchronize(P->s);
+    invalidate_graph(P);
+    for (auto &kv : P->classes) hipFree(kv.second.d_tiles);
+    hipFree(P->arena);
+    hipFree(P->d_slots);
+    hipFree(P->d_rg);
+    hipFree(P->d_vt);
+    hipFree(P->d_part);
+    hipFree(P->d_sc);
+    hipFree(P->d_st);
+    hipFree(P->d_run);
+    hipFree(P->d_jac);
+    hipFree(P->d_maxit);
+    for (int k = 0; k < 5; ++k) {
+        hipFree(P->d_gate[k]);
+        if (P->h_gate[k]) hipHostFree(P->h_gate[k]);
+    }
+    if (P->h_sc) hipHostFree(P->h_sc);
+    if (P->h_st) hipHostFree(P->h_st);
+    if (P->h_int) hipHostFree(P->h_int);
+    if (P->s) hipStreamDestroy(P->s);
+    delete P;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_request_bytes(const tmop_mesh_desc *m, const tmop_params *prm, size_t *bytes)
+{
+    SlotH s;
+    std::string why;
+    const int r = request_sizes(m, prm, s, why);
+    if (r != TMOP_OK) return pfail(r, why);
+    if (bytes) *bytes = s.bytes;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop_params *prm,
+                               const tmop_solve_params *sp, const double *x_dev, void *src_stream,
+                               int *slot)
+{
+    if (!P || !sp || !x_dev || !slot) return pfail(TMOP_ERR_INVALID_ARG, "null argument");
+    SlotH s;
+    std::string why;
+    int r = request_sizes(m, prm, s, why);
+    if (r != TMOP_OK) return pfail(r, why);
+    BOps probe;
+    if (!find_bops(s.dim, s.p, s.nq, &probe))
+        return pfail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d)");
+    if (s.bytes > P->budget) return pfail(TMOP_ERR_BUDGET, "request larger than the pool budget");
+    int si = -1;
+    for (int k = 0; k < P->max_slots; ++k)
+        if (!P->slots[k].used) {
+            si = k;
+            break;
+        }
+    size_t off = 0;
+    if (si < 0 || !pool_alloc_region(P, s.bytes, &off))
+        return pfail(TMOP_ERR_BUSY, "pool full (slots or HBM budget); retry after a release");
+    Tables tb;
+    Target tg;
+    if (internal_tables(s.p, s.nq, &tb) != TMOP_OK ||
+        internal_target(prm, s.dim, &tg) != TMOP_OK) {
+        pool_free_region(P, off, s.bytes);
+        return pfail(TMOP_ERR_INVALID_ARG, "bad quadrature or target");
+    }
+    s.off = off;
+    s.sp = *sp;
+    s.used = true;
+    s.phase = PH_NEW;
+    s.t_start = now_ms();
+    Geom &g = s.dev.g;
+    g.dim = s.dim;
+    g.p = s.p;
+    g.ne = s.ne;
+    g.nx = s.nx;
+    g.nel[0] = m->nx;
+    g.nel[1] = m->ny;
+    g.nel[2] = s.dim == 3 ? m->nz : 1;
+    for (int k = 0; k < 3; ++k) g.M[k] = g.nel[k] * s.p + 1;
+    if (s.dim == 2) g.M[2] = 1;
+    g.e2n = nullptr;
+    g.ess_mode = m->ess_mode;
+    g.ess = m->ess_mask;
+    s.dev.tg = tg;
+    char *base = P->arena + off;
+    size_t o = 0;
+    for (int k = 0; k < NVEC; ++k) s.dev.vec[k] = nullptr;
+    for (int k = 0; k < BNV; ++k) {
+        s.dev.vec[k] = (double *)(base + o);
+        o += up256((size_t)s.ndof * 8);
+    }
+    s.dev.H = base + o;
+    o += up256((size_t)s.ne * s.nqe * s.S * (s.prec ? 4 : 8));
+    s.dev.eV = base + o;
+    // copy the caller's nodes after the caller's stream has produced them
+    hipEvent_t ev;
+    PHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    PHIP(hipEventRecord(ev, (hipStream_t)src_stream));
+    PHIP(hipStreamWaitEvent(P->s, ev, 0));
+    PHIP(hipMemcpyAsync(s.dev.vec[BX], x_dev, sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s));
+    PHIP(hipMemcpyAsync(P->d_slots + si, &s.dev, sizeof(SlotDev), hipMemcpyHostToDevice, P->s));
+    PHIP(hipStreamSynchronize(P->s));
+    hipEventDestroy(ev);
+    P->slots[si] = s;
+    P->used += s.bytes;
+    P->dirty = true;
+    *slot = si;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_step(tmop_pool *P, int *n_active)
+{
+    if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
+    return pool_step_impl(P, n_active);
+}
+
+extern "C" int tmop_pool_poll(tmop_pool *P, int slot, int *done, tmop_solve_report *rep)
+{
+    if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].used)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad slot");
+    const SlotH &s = P->slots[slot];
+    if (done) *done = s.phase == PH_DONE ? 1 : 0;
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->newton_its = s.newton_its;
+        rep->minres_its_total = s.minres_its;
+        rep->halvings_total = s.halvings;
+        rep->status = s.status;
+        rep->F0 = s.F0;
+        rep->F = s.F;
+        rep->g0_norm = s.g0;
+        rep->g_norm = s.gn;
+        rep->t_total_ms = (s.phase == PH_DONE ? s.t_done : now_ms()) - s.t_start;
+    }
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_result(tmop_pool *P, int slot, double *x_dev, void *dst_stream)
+{
+    if (!P || !x_dev || slot < 0 || slot >= P->max_slots || !P->slots[slot].used)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad slot");
+    const SlotH &s = P->slots[slot];
+    PHIP(hipMemcpyAsync(x_dev, s.dev.vec[BX], sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s));
+    PHIP(hipStreamSynchronize(P->s));
+    (void)dst_stream;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_release(tmop_pool *P, int slot)
+{
+    if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].used)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad slot");
+    PHIP(hipStreamSynchronize(P->s));
+    SlotH &s = P->slots[slot];
+    pool_free_region(P, s.off, s.bytes);
+    P->used -= s.bytes;
+    s = SlotH();
+    P->dirty = true;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_info(tmop_pool *P, size_t *used_bytes, size_t *budget_bytes, int *slots_used)
+{
+    if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
+    if (used_bytes) *used_bytes = P->used;
+    if (budget_bytes) *budget_bytes = P->budget;
+    if (slots_used) {
+        int n = 0;
+        for (auto &s : P->slots) n += s.used ? 1 : 0;
+        *slots_used = n;
+    }
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_set_graph(tmop_pool *P, int enable)
+{
+    if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
+    P->use_graph = enable != 0;
+    invalidate_graph(P);
+    return TMOP_OK;
+}
+
+extern "C" const char *tmop_pool_last_error(void) { return g_perr.c_str(); }
+
+extern "C" int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params *prms,
+                                double *const *x_devs, const tmop_solve_params *sps,
+                                tmop_solve_report *reps, void *stream)
+{
+    if (count <= 0 || !meshes || !prms || !x_devs || !sps || !reps)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad batch arguments");
+    size_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        size_t b = 0;
+        PCHK(tmop_pool_request_bytes(meshes + k, prms + k, &b));
+        total += b;
+    }
+    tmop_pool *P = nullptr;
+    PCHK(tmop_pool_create(&P, total, count, stream));
+    std::vector<int> slot(count, -1);
+    int r = TMOP_OK;
+    for (int k = 0; k < count && r == TMOP_OK; ++k)
+        r = tmop_pool_admit(P, meshes + k, prms + k, sps + k, x_devs[k], stream, &slot[k]);
+    int active = count;
+    while (r == TMOP_OK && active > 0) r = tmop_pool_step(P, &active);
+    for (int k = 0; k < count && r == TMOP_OK; ++k) {
+        int done = 0;
+        r = tmop_pool_poll(P, slot[k], &done, reps + k);
+        if (r == TMOP_OK) r = tmop_pool_result(P, slot[k], x_devs[k], stream);
+    }
+    tmop_pool_destroy(P);
+    return r;
+}

@@ -144,6 +144,60 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
+namespace tmop {
+
+int internal_tables(int p, int nq, Tables *tb)
+{
+    if (p < 1 || p >= MAXNI || nq < 1 || nq > MAXNQ) return TMOP_ERR_INVALID_ARG;
+    double xi[MAXNI], chi[MAXNQ], w[MAXNQ];
+    gll_nodes01(p, xi);
+    gauss_legendre01(nq, chi, w);
+    std::memset(tb, 0, sizeof(*tb));
+    lagrange_tables(p, nq, xi, chi, tb->B, tb->G);
+    for (int q = 0; q < nq; ++q) tb->w[q] = w[q];
+    return TMOP_OK;
+}
+
+int internal_target(const tmop_params *prm, int d, Target *tp)
+{
+    Target &t = *tp;
+    t.metric = prm->metric;
+    t.ideal = prm->has_W ? 0 : 1;
+    t.detW = 1.0;
+    for (int k = 0; k < 9; ++k) t.Winv[k] = 0.0;
+    if (prm->has_W) {
+        const double *W = prm->W;
+        double det, inv[9];
+        if (d == 2) {
+            det = W[0] * W[3] - W[1] * W[2];
+            inv[0] = W[3] / det;
+            inv[1] = -W[1] / det;
+            inv[2] = -W[2] / det;
+            inv[3] = W[0] / det;
+        } else {
+            const double c00 = W[4] * W[8] - W[5] * W[7], c01 = W[5] * W[6] - W[3] * W[8],
+                         c02 = W[3] * W[7] - W[4] * W[6];
+            det = W[0] * c00 + W[1] * c01 + W[2] * c02;
+            // inverse = adj / det, adj = cof^T
+            inv[0] = c00 / det;
+            inv[3] = c01 / det;
+            inv[6] = c02 / det;
+            inv[1] = (W[2] * W[7] - W[1] * W[8]) / det;
+            inv[4] = (W[0] * W[8] - W[2] * W[6]) / det;
+            inv[7] = (W[1] * W[6] - W[0] * W[7]) / det;
+            inv[2] = (W[1] * W[5] - W[2] * W[4]) / det;
+            inv[5] = (W[2] * W[3] - W[0] * W[5]) / det;
+            inv[8] = (W[0] * W[4] - W[1] * W[3]) / det;
+        }
+        if (!(det > 0.0) || !std::isfinite(det)) return TMOP_ERR_INVALID_ARG;
+        t.detW = det;
+        for (int k = 0; k < d * d; ++k) t.Winv[k] = inv[k];
+    }
+    return TMOP_OK;
+}
+
+}  // namespace tmop
+
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
@@ -157,6 +211,7 @@ struct tmop_ctx {
     Ops ops{};
     int dim = 0, p = 0, nq = 0, ni = 0, np = 0, nqe = 0, ne = 0, nx = 0, ndof = 0;
     int precision = TMOP_FP64;
+    int storage = TMOP_HESS_TENSOR;
     int grid = 0;
     hipStream_t s = nullptr;
     void *H = nullptr;
@@ -215,7 +270,8 @@ extern "C" int tmop_workspace_bytes(const tmop_mesh_desc *m, const tmop_params *
     long ne, nx;
     int nqe, np;
     CHK(ctx_sizes(m, prm, ne, nx, nqe, np));
-    const int d = m->dim, S = d * d * (d * d + 1) / 2;
+    const int d = m->dim;
+    const int S = prm->hess_storage == TMOP_HESS_COMPACT ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
     const size_t tb = prm->precision == TMOP_MIXED ? 4 : 8;
     size_t b = align256((size_t)ne * nqe * S * tb);
     b += align256((size_t)ne * d * np * 8);
@@ -274,6 +330,8 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
         return fail(TMOP_ERR_UNSUPPORTED, "metric must be 2 (dim 2) or 303 (dim 3)");
     if (prm->precision != TMOP_FP64 && prm->precision != TMOP_MIXED)
         return fail(TMOP_ERR_INVALID_ARG, "precision must be TMOP_FP64 or TMOP_MIXED");
+    if (prm->hess_storage != TMOP_HESS_TENSOR && prm->hess_storage != TMOP_HESS_COMPACT)
+        return fail(TMOP_ERR_INVALID_ARG, "hess_storage must be TMOP_HESS_TENSOR or _COMPACT");
     if (m->ess_mode == TMOP_ESS_BOUNDARY && m->elem_to_node)
         return fail(TMOP_ERR_INVALID_ARG, "TMOP_ESS_BOUNDARY needs the structured box");
     if (m->ess_mode == TMOP_ESS_MASK && !m->ess_mask)
@@ -295,6 +353,7 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     c->nx = (int)nx;
     c->ndof = (int)(d * nx);
     c->precision = prm->precision;
+    c->storage = prm->hess_storage;
     c->s = (hipStream_t)stream;
     c->grid = (int)((ne + ops.epb - 1) / ops.epb);
 
@@ -314,53 +373,14 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     g.ess_mode = m->ess_mode;
     g.ess = m->ess_mask;
 
-    // tables
-    double xi[MAXNI], chi[MAXNQ], w[MAXNQ];
-    gll_nodes01(p, xi);
-    gauss_legendre01(nq, chi, w);
-    lagrange_tables(p, nq, xi, chi, c->tb.B, c->tb.G);
-    for (int q = 0; q < nq; ++q) c->tb.w[q] = w[q];
-
-    // target
-    Target &t = c->tg;
-    t.metric = prm->metric;
-    t.ideal = prm->has_W ? 0 : 1;
-    t.detW = 1.0;
-    for (int k = 0; k < 9; ++k) t.Winv[k] = 0.0;
-    if (prm->has_W) {
-        const double *W = prm->W;
-        double det, inv[9];
-        if (d == 2) {
-            det = W[0] * W[3] - W[1] * W[2];
-            inv[0] = W[3] / det;
-            inv[1] = -W[1] / det;
-            inv[2] = -W[2] / det;
-            inv[3] = W[0] / det;
-        } else {
-            const double c00 = W[4] * W[8] - W[5] * W[7], c01 = W[5] * W[6] - W[3] * W[8],
-                         c02 = W[3] * W[7] - W[4] * W[6];
-            det = W[0] * c00 + W[1] * c01 + W[2] * c02;
-            // inverse = adj / det, adj = cof^T
-            inv[0] = c00 / det;
-            inv[3] = c01 / det;
-            inv[6] = c02 / det;
-            inv[1] = (W[2] * W[7] - W[1] * W[8]) / det;
-            inv[4] = (W[0] * W[8] - W[2] * W[6]) / det;
-            inv[7] = (W[1] * W[6] - W[0] * W[7]) / det;
-            inv[2] = (W[1] * W[5] - W[2] * W[4]) / det;
-            inv[5] = (W[2] * W[3] - W[0] * W[5]) / det;
-            inv[8] = (W[0] * W[4] - W[1] * W[3]) / det;
-        }
-        if (!(det > 0.0) || !std::isfinite(det)) {
-            delete c;
-            return fail(TMOP_ERR_INVALID_ARG, "target W must have det > 0");
-        }
-        t.detW = det;
-        for (int k = 0; k < d * d; ++k) t.Winv[k] = inv[k];
+    internal_tables(p, nq, &c->tb);
+    if (internal_target(prm, d, &c->tg) != TMOP_OK) {
+        delete c;
+        return fail(TMOP_ERR_INVALID_ARG, "target W must have det > 0");
     }
 
     // workspace
-    const int S = d * d * (d * d + 1) / 2;
+    const int S = c->storage == TMOP_HESS_COMPACT ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
     const size_t tbytes = c->precision == TMOP_MIXED ? 4 : 8;
     c->H_bytes = (size_t)ne * nqe * S * tbytes;
     c->eV_bytes = (size_t)ne * d * np * 8;
@@ -374,10 +394,10 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     ALLOC(c->scal, sizeof(double) * 64);
     ALLOC(c->diag, sizeof(double) * c->ndof);
     ALLOC(c->minv, sizeof(double) * c->ndof);
-    ALLOC(c->mst, sizeof(MinresState));
+    ALLOC(c->mst, 2 * sizeof(MinresState));
 #undef ALLOC
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscal, sizeof(double) * 64, 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmst, sizeof(MinresState), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmst, 2 * sizeof(MinresState), 0);
     if (e != hipSuccess) {
         free_ctx(c);
         return fail(e == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,
@@ -476,7 +496,13 @@ extern "C" int tmop_gradient(tmop_ctx *c, const double *x, double *g)
 
 static void setup_impl(tmop_ctx *c, const double *x)
 {
-    if (c->precision == TMOP_MIXED)
+    const bool mixed = c->precision == TMOP_MIXED;
+    if (c->storage == TMOP_HESS_COMPACT) {
+        if (mixed)
+            c->ops.setupc32(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, c->part);
+        else
+            c->ops.setupc64(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, c->part);
+    } else if (mixed)
         c->ops.setup32(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, c->part);
     else
         c->ops.setup64(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, c->part);
@@ -494,6 +520,13 @@ extern "C" int tmop_hessian_setup(tmop_ctx *c, const double *x)
 
 static void apply_elem(tmop_ctx *c, const double *v)
 {
+    if (c->storage == TMOP_HESS_COMPACT) {
+        if (c->precision == TMOP_MIXED)
+            c->ops.applyc32(c->grid, c->s, c->g, c->tb, c->tg, (const float *)c->H, v, (float *)c->eV);
+        else
+            c->ops.applyc64(c->grid, c->s, c->g, c->tb, c->tg, (const double *)c->H, v, (double *)c->eV);
+        return;
+    }
     if (c->precision == TMOP_MIXED)
         c->ops.apply32(c->grid, c->s, c->g, c->tb, (const float *)c->H, v, (float *)c->eV);
     else
@@ -518,7 +551,12 @@ extern "C" int tmop_hessian_apply(tmop_ctx *c, const double *v, double *y)
 
 static void diag_impl(tmop_ctx *c, double *d)
 {
-    if (c->precision == TMOP_MIXED)
+    if (c->storage == TMOP_HESS_COMPACT) {
+        if (c->precision == TMOP_MIXED)
+            c->ops.diagc32(c->grid, c->s, c->g, c->tb, c->tg, (const float *)c->H, (double *)c->eV);
+        else
+            c->ops.diagc64(c->grid, c->s, c->g, c->tb, c->tg, (const double *)c->H, (double *)c->eV);
+    } else if (c->precision == TMOP_MIXED)
         c->ops.diag32(c->grid, c->s, c->g, c->tb, (const float *)c->H, (double *)c->eV);
     else
         c->ops.diag64(c->grid, c->s, c->g, c->tb, (const double *)c->H, (double *)c->eV);
@@ -592,7 +630,8 @@ static void make_jacobi(tmop_ctx *c)
     c->have_diag = true;
 }
 
-// MINRES on H_c dx = b.  Buffers from the solver pool.
+// MINRES on H_c dx = b.  Buffers from the solver pool; device state
+// double-buffered in c->mst[0..1] (see vec.hip).
 static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
                        bool jacobi, int check_every, int *its_out)
 {
@@ -600,35 +639,37 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
     const long n = c->ndof;
     double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *Y = c->sv[SV_Y], *HV = c->sv[SV_HV];
     double *V = c->sv[SV_V], *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
+    double *part1 = c->part, *part2 = c->part + 1024;
     const double *minv = jacobi ? c->minv : nullptr;
-    mr_init(n, b, minv, R1, R2, Y, dx, W, W1, W2, c->part, c->mst, rtol, c->s);
+    const bool fp32 = c->precision == TMOP_MIXED;
+    mr_init(n, b, minv, R1, R2, Y, V, dx, W, W1, W2, part1, c->mst, rtol, c->s);
     c->tev_used = 0;
     for (int j = 0; j < max_its; ++j) {
-        mr_v(n, j, c->mst, Y, V, c->s);
+        MinresState *sin = c->mst + (j & 1), *sout = c->mst + ((j + 1) & 1);
         const bool rec = c->timing && c->tev_used + 3 <= (int)c->tev.size();
         if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used], c->s));
         apply_elem(c, V);
         if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used + 1], c->s));
-        apply_gather(c, V, HV);
+        // G^T fused with the first Lanczos update
+        mr_gather_l1(c->g, c->csr_ptr, c->csr_ent, c->eV, fp32, j, sin, V, R1, HV, part1, c->s);
         if (rec) {
             HIPCHK(hipEventRecord(c->tev[c->tev_used + 2], c->s));
             c->tev_used += 3;
         }
-        mr_lanczos1(n, j, c->mst, HV, R1, V, c->part, c->s);
-        mr_lanczos2(n, j, c->mst, HV, R2, minv, R1, c->part, c->s);
+        // z goes to the old r1 buffer (r1 is dead after gather_l1)
+        mr_lanczos2(n, j, sin, part1, HV, R2, minv, R1, part2, c->s);
         // new w goes to the old w1 buffer; (w1, w2) of the formula = (old w2, old w)
-        mr_update(n, j, c->mst, V, W2, W, W1, dx, c->s);
-        double *oY = Y, *oR1 = R1, *oR2 = R2, *oHV = HV;
-        Y = oR1;
+        mr_update(n, j, sin, sout, part1, part2, V, W2, W, W1, dx, R1, c->s);
+        double *oR1 = R1, *oR2 = R2, *oHV = HV;
         R1 = oR2;
         R2 = oHV;
-        HV = oY;
+        HV = oR1;
         double *oW = W, *oW1 = W1, *oW2 = W2;
         W1 = oW2;
         W2 = oW;
         W = oW1;
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
-            HIPCHK(hipMemcpyAsync(c->hmst, c->mst, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipMemcpyAsync(c->hmst, sout, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipStreamSynchronize(c->s));
             if (c->hmst->stop != 0x7fffffff) break;
         }
@@ -636,28 +677,27 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
     // keep the rotated pointers consistent for the next call
     c->sv[SV_R1] = R1;
     c->sv[SV_R2] = R2;
-    c->sv[SV_Y] = Y;
     c->sv[SV_HV] = HV;
     c->sv[SV_W] = W;
     c->sv[SV_W1] = W1;
     c->sv[SV_W2] = W2;
-    HIPCHK(hipMemcpyAsync(c->hmst, c->mst, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipMemcpyAsync(c->hmst, c->mst, 2 * sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
     HIPCHK(hipStreamSynchronize(c->s));
     HIPCHK(hipGetLastError());
-    if (its_out) *its_out = c->hmst->its;
-    // applies after convergence are skipped by the kernels' own guards only in
-    // the vector kernels; the element work still ran, so every recorded
-    // action is counted
+    const MinresState &fin = c->hmst[0].its >= c->hmst[1].its ? c->hmst[0] : c->hmst[1];
+    if (its_out) *its_out = fin.its;
+    // every recorded action is counted (the element kernel runs even after
+    // convergence; only the vector kernels skip)
     for (int k = 0; k + 2 < c->tev_used; k += 3) {
-        float a = 0.f, b = 0.f;
+        float a = 0.f, bt = 0.f;
         HIPCHK(hipEventElapsedTime(&a, c->tev[k], c->tev[k + 1]));
-        HIPCHK(hipEventElapsedTime(&b, c->tev[k], c->tev[k + 2]));
+        HIPCHK(hipEventElapsedTime(&bt, c->tev[k], c->tev[k + 2]));
         c->acc_elem_ms += a;
-        c->acc_apply_ms += b;
+        c->acc_apply_ms += bt;
         c->acc_napply += 1;
     }
     c->tev_used = 0;
-    if (c->hmst->indefinite_precond) return fail(TMOP_ERR_NONFINITE, "preconditioner not SPD");
+    if (fin.indefinite_precond) return fail(TMOP_ERR_NONFINITE, "preconditioner not SPD");
     return TMOP_OK;
 }
 

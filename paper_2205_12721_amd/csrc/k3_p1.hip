@@ -14,4 +14,14 @@ bool ops3_p1(int nq, Ops *out)
     }
 }
 
+bool bops3_p1(int nq, BOps *out)
+{
+    switch (nq) {
+    case 1 + 1: TMOP_BOPS_BODY(kb3, S3, 1, 1 + 1)
+    case 1 + 2: TMOP_BOPS_BODY(kb3, S3, 1, 1 + 2)
+    case 1 + 3: TMOP_BOPS_BODY(kb3, S3, 1, 1 + 3)
+    default: return false;
+    }
+}
+
 }  // namespace tmop

@@ -14,4 +14,14 @@ bool ops3_p2(int nq, Ops *out)
     }
 }
 
+bool bops3_p2(int nq, BOps *out)
+{
+    switch (nq) {
+    case 2 + 1: TMOP_BOPS_BODY(kb3, S3, 2, 2 + 1)
+    case 2 + 2: TMOP_BOPS_BODY(kb3, S3, 2, 2 + 2)
+    case 2 + 3: TMOP_BOPS_BODY(kb3, S3, 2, 2 + 3)
+    default: return false;
+    }
+}
+
 }  // namespace tmop

@@ -14,4 +14,14 @@ bool ops3_p3(int nq, Ops *out)
     }
 }
 
+bool bops3_p3(int nq, BOps *out)
+{
+    switch (nq) {
+    case 3 + 1: TMOP_BOPS_BODY(kb3, S3, 3, 3 + 1)
+    case 3 + 2: TMOP_BOPS_BODY(kb3, S3, 3, 3 + 2)
+    case 3 + 3: TMOP_BOPS_BODY(kb3, S3, 3, 3 + 3)
+    default: return false;
+    }
+}
+
 }  // namespace tmop

@@ -14,4 +14,14 @@ bool ops3_p4(int nq, Ops *out)
     }
 }
 
+bool bops3_p4(int nq, BOps *out)
+{
+    switch (nq) {
+    case 4 + 1: TMOP_BOPS_BODY(kb3, S3, 4, 4 + 1)
+    case 4 + 2: TMOP_BOPS_BODY(kb3, S3, 4, 4 + 2)
+    case 4 + 3: TMOP_BOPS_BODY(kb3, S3, 4, 4 + 3)
+    default: return false;
+    }
+}
+
 }  // namespace tmop

@@ -141,15 +141,11 @@ __device__ inline void backward2(Lds2<P, NQ, CT> &L, int nel, OT *__restrict__ o
 }
 
 template <int P, int NQ>
-__global__ __launch_bounds__(BLOCK) void k2_energy(Geom g, Tables tb, Target tg,
-                                                   const double *__restrict__ x,
-                                                   double *__restrict__ part)
+__device__ inline void b2_energy(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ part, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
     double esum = 0.0, dmin = 1.0e300, bad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
@@ -175,16 +171,11 @@ __global__ __launch_bounds__(BLOCK) void k2_energy(Geom g, Tables tb, Target tg,
 }
 
 template <int P, int NQ>
-__global__ __launch_bounds__(BLOCK) void k2_gradient(Geom g, Tables tb, Target tg,
-                                                     const double *__restrict__ x,
-                                                     double *__restrict__ gE,
-                                                     double *__restrict__ bad)
+__device__ inline void b2_gradient(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
@@ -208,15 +199,11 @@ __global__ __launch_bounds__(BLOCK) void k2_gradient(Geom g, Tables tb, Target t
 }
 
 template <int P, int NQ, typename TT>
-__global__ __launch_bounds__(BLOCK) void k2_setup(Geom g, Tables tb, Target tg,
-                                                  const double *__restrict__ x,
-                                                  TT *__restrict__ H, double *__restrict__ bad)
+__device__ inline void b2_setup(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
@@ -239,14 +226,10 @@ __global__ __launch_bounds__(BLOCK) void k2_setup(Geom g, Tables tb, Target tg,
 }
 
 template <int P, int NQ, typename TT, typename CT>
-__global__ __launch_bounds__(BLOCK) void k2_apply(Geom g, Tables tb, const TT *__restrict__ H,
-                                                  const double *__restrict__ v,
-                                                  CT *__restrict__ yE)
+__device__ inline void b2_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, CT> L;
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     prologue2<P, NQ>(g, tb, v, e0, nel, L, true);
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
@@ -269,64 +252,383 @@ __global__ __launch_bounds__(BLOCK) void k2_apply(Geom g, Tables tb, const TT *_
     backward2<P, NQ>(L, nel, yE + (size_t)e0 * 2 * S::NP);
 }
 
+// ------------------------------------------------------------------------
+// Compact quadrature data for quads: T (4) and z c_id, z c_tc, z c_cc, z c_dc,
+// layout [e][8][q].  In 2D C = cof T = [[T11, -T10], [-T01, T00]] and the
+// cofactor derivative is the constant map dC[M] = cof M.
+// ------------------------------------------------------------------------
+constexpr int NC2 = 8;
+
+template <typename CT>
+__device__ inline void compact_action2(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
+{
+    const CT C[4] = {T[3], -T[2], -T[1], T[0]};
+    const CT dC[4] = {M[3], -M[2], -M[1], M[0]};
+    CT tm = 0, cm = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tm += T[k] * M[k];
+        cm += C[k] * M[k];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        Y[r] = ca * M[r] + cb * (T[r] * cm + C[r] * tm) + cc * C[r] * cm + cd * dC[r];
+}
+
+template <typename CT>
+__device__ inline void mul_winv2(const Target &t, const CT *in, CT *out, bool tr)
+{
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            CT s = 0;
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                s += in[a * 2 + n] * (CT)(tr ? t.Winv[k * 2 + n] : t.Winv[n * 2 + k]);
+            out[a * 2 + k] = s;
+        }
+}
+
 template <int P, int NQ, typename TT>
-__global__ __launch_bounds__(BLOCK) void k2_diag(Geom g, Tables tb, const TT *__restrict__ H,
-                                                 double *__restrict__ dE)
+__device__ inline void b2_setupc(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad, int e0, int nel)
+{
+    using S = S2<P, NQ>;
+    __shared__ Lds2<P, NQ, double> L;
+    __shared__ double red[BLOCK / 64];
+    prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
+    double nbad = 0.0;
+    for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
+        const int el = idx / S::NQ2, q = idx % S::NQ2;
+        const int q1 = q % NQ, q2 = q / NQ;
+        double J[4], T[4], C[4], out[NC2];
+        point_grad2<P, NQ>(L, el, q1, q2, J);
+        apply_winv<2>(tg, J, T);
+        const double tau = det_cof<2>(T, C);
+        const double z = tb.w[q1] * tb.w[q2] * tg.detW;
+        if (tau > 0.0) {
+            double I1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) I1 += T[k] * T[k];
+            const MetricCoef m = metric_coef(tg.metric, I1, tau);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[k] = T[k];
+            out[4] = z * m.c_id;
+            out[5] = z * m.c_tc;
+            out[6] = z * m.c_cc;
+            out[7] = z * m.c_dc;
+        } else {
+            nbad += 1.0;
+#pragma unroll
+            for (int k = 0; k < NC2; ++k) out[k] = 0.0;
+        }
+        TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+#pragma unroll
+        for (int k = 0; k < NC2; ++k) h[k * S::NQ2] = (TT)out[k];
+    }
+    const double b = block_sum(nbad, red);
+    if (threadIdx.x == 0) bad[blockIdx.x] = b;
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__device__ inline void b2_applyc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+{
+    using S = S2<P, NQ>;
+    __shared__ Lds2<P, NQ, CT> L;
+    prologue2<P, NQ>(g, tb, v, e0, nel, L, true);
+    for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
+        const int el = idx / S::NQ2, q = idx % S::NQ2;
+        const int q1 = q % NQ, q2 = q / NQ;
+        const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+        CT d[NC2];
+#pragma unroll
+        for (int k = 0; k < NC2; ++k) d[k] = (CT)h[k * S::NQ2];
+        CT J[4], Y[4];
+        point_grad2<P, NQ>(L, el, q1, q2, J);
+        if (tg.ideal) {
+            compact_action2<CT>(d, d[4], d[5], d[6], d[7], J, Y);
+        } else {
+            CT M[4], Yt[4];
+            mul_winv2<CT>(tg, J, M, false);
+            compact_action2<CT>(d, d[4], d[5], d[6], d[7], M, Yt);
+            mul_winv2<CT>(tg, Yt, Y, true);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) L.RY[(el * 4 + r) * S::NQ2 + q] = Y[r];
+    }
+    __syncthreads();
+    backward2<P, NQ>(L, nel, yE + (size_t)e0 * 2 * S::NP);
+}
+
+// Hessian diagonal (Sec. 3.4): 2 components x 3 pairs (n <= p) of planes
+// sQ[el][pair][a][q], then one contraction pass per pair with BB, BG, GG.
+template <int P, int NQ>
+struct DiagLds2 {
+    using S = S2<P, NQ>;
+    double T[3][NQ * S::NI];
+    double sQ[S::EPB * 6 * S::NQ2];
+    double U1[S::EPB * 2 * S::NI * NQ];
+    double sD[S::EPB * 2 * S::NP];
+};
+
+template <int P, int NQ>
+__device__ inline void diag_contract2(const Tables &tb, DiagLds2<P, NQ> &L, int nel,
+                                      double *__restrict__ dE)
 {
     using S = S2<P, NQ>;
     constexpr int NI = S::NI, NQ2 = S::NQ2, NP = S::NP;
-    __shared__ double T[3][NQ * NI];
-    __shared__ double sQ[S::EPB * 2 * NQ2];
-    __shared__ double U1[S::EPB * 2 * NI * NQ];
-    __shared__ double sD[S::EPB * 2 * NP];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
         const double b = tb.B[k], gg = tb.G[k];
-        T[0][k] = b * b;
-        T[1][k] = b * gg;
-        T[2][k] = gg * gg;
+        L.T[0][k] = b * b;
+        L.T[1][k] = b * gg;
+        L.T[2][k] = gg * gg;
     }
-    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) sD[k] = 0.0;
-    const int pn[3] = {0, 0, 1};
-    const int pp[3] = {0, 1, 1};
+    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) L.sD[k] = 0.0;
     for (int pr = 0; pr < 3; ++pr) {
-        const int n = pn[pr], p = pp[pr];
-        const double f = (n == p) ? 1.0 : 2.0;
+        const int n = pr == 2 ? 1 : 0, p = pr == 0 ? 0 : 1;
         const int t1 = (n == 0) + (p == 0), t2 = (n == 1) + (p == 1);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nel * 2 * NQ2; idx += BLOCK) {
-            const int q = idx % NQ2;
-            const int r = idx / NQ2;
-            const int a = r % 2, el = r / 2;
-            const int s = sym_index<4>(a * 2 + n, a * 2 + p);
-            sQ[idx] = f * (double)H[((size_t)(e0 + el) * 10 + s) * NQ2 + q];
-        }
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 2 * NI * NQ; idx += BLOCK) {
             const int q1 = idx % NQ;
             int r = idx / NQ;
             const int i2 = r % NI;
-            r /= NI;
-            const double *y = sQ + r * NQ2 + q1;
+            r /= NI;  // el*2 + a
+            const int el = r / 2, a = r % 2;
+            const double *y = L.sQ + ((el * 3 + pr) * 2 + a) * NQ2 + q1;
             double s = 0.0;
 #pragma unroll
-            for (int q2 = 0; q2 < NQ; ++q2) s += T[t2][q2 * NI + i2] * y[q2 * NQ];
-            U1[(r * NI + i2) * NQ + q1] = s;
+            for (int q2 = 0; q2 < NQ; ++q2) s += L.T[t2][q2 * NI + i2] * y[q2 * NQ];
+            L.U1[(r * NI + i2) * NQ + q1] = s;
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 2 * NP; idx += BLOCK) {
             const int i1 = idx % NI;
             const int rest = idx / NI;
-            const double *y = U1 + rest * NQ;
+            const double *y = L.U1 + rest * NQ;
             double s = 0.0;
 #pragma unroll
-            for (int q1 = 0; q1 < NQ; ++q1) s += T[t1][q1 * NI + i1] * y[q1];
-            sD[idx] += s;
+            for (int q1 = 0; q1 < NQ; ++q1) s += L.T[t1][q1 * NI + i1] * y[q1];
+            L.sD[idx] += s;
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) dE[(size_t)e0 * 2 * NP + k] = sD[k];
+    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) dE[k] = L.sD[k];
+}
+
+template <int P, int NQ, typename TT>
+__device__ inline void b2_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H, double *__restrict__ dE, int e0, int nel)
+{
+    using S = S2<P, NQ>;
+    __shared__ DiagLds2<P, NQ> L;
+    for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
+        const int el = idx / S::NQ2, q = idx % S::NQ2;
+        const TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
+#pragma unroll
+        for (int pr = 0; pr < 3; ++pr) {
+            const int n = pr == 2 ? 1 : 0, p = pr == 0 ? 0 : 1;
+            const double f = (n == p) ? 1.0 : 2.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                L.sQ[((el * 3 + pr) * 2 + a) * S::NQ2 + q] =
+                    f * (double)h[sym_index<4>(a * 2 + n, a * 2 + p) * S::NQ2];
+        }
+    }
+    diag_contract2<P, NQ>(tb, L, nel, dE + (size_t)e0 * 2 * S::NP);
+}
+
+template <int P, int NQ, typename TT>
+__device__ inline void b2_diagc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+{
+    using S = S2<P, NQ>;
+    __shared__ DiagLds2<P, NQ> L;
+    for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
+        const int el = idx / S::NQ2, q = idx % S::NQ2;
+        const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+        double T[4], Tw[4], Cw[4], WW[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) T[k] = (double)h[k * S::NQ2];
+        const double cid = h[4 * S::NQ2], ctc = h[5 * S::NQ2], ccc = h[6 * S::NQ2];
+        const double C[4] = {T[3], -T[2], -T[1], T[0]};
+        if (tg.ideal) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Tw[k] = T[k];
+                Cw[k] = C[k];
+                WW[k] = (k % 3 == 0) ? 1.0 : 0.0;
+            }
+        } else {
+            mul_winv2<double>(tg, T, Tw, true);
+            mul_winv2<double>(tg, C, Cw, true);
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    WW[n * 2 + p] = tg.Winv[n * 2] * tg.Winv[p * 2] + tg.Winv[n * 2 + 1] * tg.Winv[p * 2 + 1];
+        }
+#pragma unroll
+        for (int pr = 0; pr < 3; ++pr) {
+            const int n = pr == 2 ? 1 : 0, p = pr == 0 ? 0 : 1;
+            const double f = (n == p) ? 1.0 : 2.0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double hv = cid * WW[n * 2 + p] +
+                                  ctc * (Tw[a * 2 + n] * Cw[a * 2 + p] + Cw[a * 2 + n] * Tw[a * 2 + p]) +
+                                  ccc * Cw[a * 2 + n] * Cw[a * 2 + p];
+                L.sQ[((el * 3 + pr) * 2 + a) * S::NQ2 + q] = f * hv;
+            }
+        }
+    }
+    diag_contract2<P, NQ>(tb, L, nel, dE + (size_t)e0 * 2 * S::NP);
+}
+
+// ------------------------------------------------------------------------
+// Kernel entry points: single mesh (grid over element blocks) and batched
+// (grid over a tile list of (slot, first element) with per-slot geometry,
+// target and offsets into packed pools).
+// ------------------------------------------------------------------------
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void k2_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_energy<P, NQ>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void k2_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_gradient<P, NQ>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k2_setup(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k2_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_apply<P, NQ, TT, CT>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k2_setupc(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k2_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_applyc<P, NQ, TT, CT>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k2_diag(Geom g, Tables tb, const TT *__restrict__ H, double *__restrict__ dE)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_diag<P, NQ, TT>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k2_diagc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, double *__restrict__ dE)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b2_diagc<P, NQ, TT>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void kb2_energy(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ part)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_energy<P, NQ>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void kb2_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_gradient<P, NQ>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb2_setup(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_setup<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void kb2_apply(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_apply<P, NQ, TT, CT>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb2_setupc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_setupc<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void kb2_applyc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_applyc<P, NQ, TT, CT>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb2_diag(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_diag<P, NQ, TT>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb2_diagc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
+{
+    constexpr int EPB = S2<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b2_diagc<P, NQ, TT>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 }  // namespace tmop

@@ -239,15 +239,11 @@ __device__ inline void backward3(const CT *sB, const CT *sG, const CT *RY, CT *R
 // Energy and minimum det A: per-block partial sums of z mu and minima of det A,
 // count of points with det T <= 0 (Sec. 3.3, eq. D0_expression; Sec. 2.3).
 template <int P, int NQ>
-__global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg,
-                                                   const double *__restrict__ x,
-                                                   double *__restrict__ part)
+__device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ part, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
@@ -280,16 +276,11 @@ __global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg,
 // Gradient E-vector (Sec. 3.3, eq. eq_vm_pa_grad): per point z P, then the
 // transposed contractions.  bad[blockIdx] counts points with det T <= 0.
 template <int P, int NQ>
-__global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg,
-                                                     const double *__restrict__ x,
-                                                     double *__restrict__ gE,
-                                                     double *__restrict__ bad)
+__device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
@@ -318,15 +309,11 @@ __global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target t
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
 // element-major [e][45][NQ^3] so that each entry is one coalesced plane.
 template <int P, int NQ, typename TT>
-__global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg,
-                                                  const double *__restrict__ x,
-                                                  TT *__restrict__ H, double *__restrict__ bad)
+__device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
@@ -358,14 +345,10 @@ __global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg,
 // CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
 // accumulation).
 template <int P, int NQ, typename TT, typename CT>
-__global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *__restrict__ H,
-                                                  const double *__restrict__ v,
-                                                  CT *__restrict__ yE)
+__device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, CT> L;
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, v, e0, nel, L.X, true);
     __syncthreads();
@@ -391,44 +374,179 @@ __global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *_
     backward3<P, NQ>(L.B, L.G, L.RY, L.R2, L.R1, nel, yE + (size_t)e0 * 3 * S::NP);
 }
 
+// ------------------------------------------------------------------------
+// Compact quadrature data: per point T = A W^{-1} (9 values) and the four
+// weighted metric coefficients z c_id, z c_tc, z c_cc, z c_dc (layout
+// [e][13][q]).  The fourth-order tensor is then applied in closed form:
+//   d2mu : M = c_id M + c_tc (T (C:M) + C (T:M)) + c_cc C (C:M) + c_dc dC[M],
+// with C = cof T and dC[M] the derivative of the cofactor at T in direction M
+// (the bilinear part of cof(T + M)).  Same result as the stored tensor,
+// 13 instead of 45 values per point.
+// ------------------------------------------------------------------------
+constexpr int NC3 = 13;
+
+template <typename CT>
+__device__ inline void cof3(const CT *T, CT *C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            C[i * 3 + j] = T[i1 * 3 + j1] * T[i2 * 3 + j2] - T[i1 * 3 + j2] * T[i2 * 3 + j1];
+        }
+}
+
+template <typename CT>
+__device__ inline void compact_action3(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
+{
+    CT C[9];
+    cof3(T, C);
+    CT tm = 0, cm = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        tm += T[k] * M[k];
+        cm += C[k] * M[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const CT dC = T[i1 * 3 + j1] * M[i2 * 3 + j2] + M[i1 * 3 + j1] * T[i2 * 3 + j2] -
+                          T[i1 * 3 + j2] * M[i2 * 3 + j1] - M[i1 * 3 + j2] * T[i2 * 3 + j1];
+            const int r = i * 3 + j;
+            Y[r] = ca * M[r] + cb * (T[r] * cm + C[r] * tm) + cc * C[r] * cm + cd * dC;
+        }
+}
+
+// out = in W^{-1} (tr = false) or in W^{-T} (tr = true), D x D row-major.
+template <int D, typename CT>
+__device__ inline void mul_winv(const Target &t, const CT *in, CT *out, bool tr)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            CT s = 0;
+#pragma unroll
+            for (int n = 0; n < D; ++n)
+                s += in[a * D + n] * (CT)(tr ? t.Winv[k * D + n] : t.Winv[n * D + k]);
+            out[a * D + k] = s;
+        }
+}
+
+template <int P, int NQ, typename TT>
+__device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    __shared__ Lds3<P, NQ, double> L;
+    __shared__ double red[BLOCK / 64];
+    load_tables3<P, NQ>(tb, L.B, L.G);
+    gather3<P, NQ>(g, x, e0, nel, L.X, false);
+    __syncthreads();
+    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    double nbad = 0.0;
+    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
+        double J[9], T[9], C[9], out[NC3];
+        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
+        apply_winv<3>(tg, J, T);
+        const double tau = det_cof<3>(T, C);
+        const double z = tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+        if (tau > 0.0) {
+            double I1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) I1 += T[k] * T[k];
+            const MetricCoef m = metric_coef(tg.metric, I1, tau);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) out[k] = T[k];
+            out[9] = z * m.c_id;
+            out[10] = z * m.c_tc;
+            out[11] = z * m.c_cc;
+            out[12] = z * m.c_dc;
+        } else {
+            nbad += 1.0;
+#pragma unroll
+            for (int k = 0; k < NC3; ++k) out[k] = 0.0;
+        }
+        TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+#pragma unroll
+        for (int k = 0; k < NC3; ++k) h[k * S::NQ3] = (TT)out[k];
+    }
+    const double b = block_sum(nbad, red);
+    if (threadIdx.x == 0) bad[blockIdx.x] = b;
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    __shared__ Lds3<P, NQ, CT> L;
+    load_tables3<P, NQ>(tb, L.B, L.G);
+    gather3<P, NQ>(g, v, e0, nel, L.X, true);
+    __syncthreads();
+    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
+        const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+        CT d[NC3];
+#pragma unroll
+        for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
+        CT J[9], Y[9];
+        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
+        if (tg.ideal) {
+            compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
+        } else {
+            CT M[9], Yt[9];
+            mul_winv<3, CT>(tg, J, M, false);
+            compact_action3<CT>(d, d[9], d[10], d[11], d[12], M, Yt);
+            mul_winv<3, CT>(tg, Yt, Y, true);
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) L.RY[(el * 9 + r) * S::NQ3 + q] = Y[r];
+    }
+    __syncthreads();
+    backward3<P, NQ>(L.B, L.G, L.RY, L.R2, L.R1, nel, yE + (size_t)e0 * 3 * S::NP);
+}
+
 // Hessian diagonal, element part (Sec. 3.4, last paragraph):
 //   d_a(i) = sum_q sum_{n,p} H[an,ap](q) dw_i/dxbar_n dw_i/dxbar_p,
-// contracted per (n,p) pair with the squared 1D tables BB, BG, GG.
-template <int P, int NQ, typename TT>
-__global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__restrict__ H,
-                                                 double *__restrict__ dE)
+// contracted per (n,p) pair with the squared 1D tables BB, BG, GG.  The 18
+// needed entries H[an,ap] (3 components x 6 pairs n <= p, off-diagonal pairs
+// doubled) are first placed in LDS planes sQ[el][pair][a][q].
+template <int P, int NQ>
+struct DiagLds3 {
+    using S = S3<P, NQ>;
+    double T[3][NQ * S::NI];  // BB, BG, GG
+    double sQ[S::EPB * 18 * S::NQ3];
+    double U2[S::EPB * 3 * S::NI * NQ * NQ];
+    double U1[S::EPB * 3 * S::NI * S::NI * NQ];
+    double sD[S::EPB * 3 * S::NP];
+};
+
+__device__ constexpr int diag_pn(int pr) { return pr < 3 ? 0 : (pr < 5 ? 1 : 2); }
+__device__ constexpr int diag_pp(int pr) { return pr < 3 ? pr : (pr < 5 ? pr - 2 : 2); }
+
+template <int P, int NQ>
+__device__ inline void diag_contract3(const Tables &tb, DiagLds3<P, NQ> &L, int nel,
+                                      double *__restrict__ dE)
 {
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NQ3 = S::NQ3, NP = S::NP;
-    __shared__ double T[3][NQ * NI];  // BB, BG, GG
-    __shared__ double sQ[S::EPB * 3 * NQ3];
-    __shared__ double U2[S::EPB * 3 * NI * NQ * NQ];
-    __shared__ double U1[S::EPB * 3 * NI * NI * NQ];
-    __shared__ double sD[S::EPB * 3 * NP];
-    const int e0 = blockIdx.x * S::EPB;
-    const int nel = min(S::EPB, g.ne - e0);
     for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
         const double b = tb.B[k], gg = tb.G[k];
-        T[0][k] = b * b;
-        T[1][k] = b * gg;
-        T[2][k] = gg * gg;
+        L.T[0][k] = b * b;
+        L.T[1][k] = b * gg;
+        L.T[2][k] = gg * gg;
     }
-    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) sD[k] = 0.0;
-    const int pn[6] = {0, 0, 0, 1, 1, 2};
-    const int pp[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) L.sD[k] = 0.0;
     for (int pr = 0; pr < 6; ++pr) {
-        const int n = pn[pr], p = pp[pr];
-        const double f = (n == p) ? 1.0 : 2.0;
+        const int n = diag_pn(pr), p = diag_pp(pr);
         // table index along axis k: number of derivative factors on that axis
         const int t1 = (n == 0) + (p == 0), t2 = (n == 1) + (p == 1), t3 = (n == 2) + (p == 2);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nel * 3 * NQ3; idx += BLOCK) {
-            const int q = idx % NQ3;
-            const int r = idx / NQ3;  // el*3 + a
-            const int a = r % 3, el = r / 3;
-            const int s = sym_index<9>(a * 3 + n, a * 3 + p);
-            sQ[idx] = f * (double)H[((size_t)(e0 + el) * 45 + s) * NQ3 + q];
-        }
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 3 * NI * NQ * NQ; idx += BLOCK) {
             const int q1 = idx % NQ;
@@ -436,12 +554,13 @@ __global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__
             const int q2 = r % NQ;
             r /= NQ;
             const int i3 = r % NI;
-            r /= NI;
-            const double *y = sQ + r * NQ3 + q2 * NQ + q1;
+            r /= NI;  // el*3 + a
+            const int el = r / 3, a = r % 3;
+            const double *y = L.sQ + ((el * 6 + pr) * 3 + a) * NQ3 + q2 * NQ + q1;
             double s = 0.0;
 #pragma unroll
-            for (int q3 = 0; q3 < NQ; ++q3) s += T[t3][q3 * NI + i3] * y[q3 * NQ * NQ];
-            U2[((r * NI + i3) * NQ + q2) * NQ + q1] = s;
+            for (int q3 = 0; q3 < NQ; ++q3) s += L.T[t3][q3 * NI + i3] * y[q3 * NQ * NQ];
+            L.U2[((r * NI + i3) * NQ + q2) * NQ + q1] = s;
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 3 * NI * NI * NQ; idx += BLOCK) {
@@ -451,25 +570,248 @@ __global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__
             r /= NI;
             const int i3 = r % NI;
             r /= NI;
-            const double *y = U2 + (r * NI + i3) * NQ * NQ + q1;
+            const double *y = L.U2 + (r * NI + i3) * NQ * NQ + q1;
             double s = 0.0;
 #pragma unroll
-            for (int q2 = 0; q2 < NQ; ++q2) s += T[t2][q2 * NI + i2] * y[q2 * NQ];
-            U1[((r * NI + i3) * NI + i2) * NQ + q1] = s;
+            for (int q2 = 0; q2 < NQ; ++q2) s += L.T[t2][q2 * NI + i2] * y[q2 * NQ];
+            L.U1[((r * NI + i3) * NI + i2) * NQ + q1] = s;
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 3 * NP; idx += BLOCK) {
             const int i1 = idx % NI;
             const int rest = idx / NI;  // (r*NI + i3)*NI + i2
-            const double *y = U1 + rest * NQ;
+            const double *y = L.U1 + rest * NQ;
             double s = 0.0;
 #pragma unroll
-            for (int q1 = 0; q1 < NQ; ++q1) s += T[t1][q1 * NI + i1] * y[q1];
-            sD[idx] += s;
+            for (int q1 = 0; q1 < NQ; ++q1) s += L.T[t1][q1 * NI + i1] * y[q1];
+            L.sD[idx] += s;
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) dE[(size_t)e0 * 3 * NP + k] = sD[k];
+    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) dE[k] = L.sD[k];
+}
+
+template <int P, int NQ, typename TT>
+__device__ inline void b3_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H, double *__restrict__ dE, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    __shared__ DiagLds3<P, NQ> L;
+    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr) {
+            const int n = diag_pn(pr), p = diag_pp(pr);
+            const double f = (n == p) ? 1.0 : 2.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                L.sQ[((el * 6 + pr) * 3 + a) * S::NQ3 + q] =
+                    f * (double)h[sym_index<9>(a * 3 + n, a * 3 + p) * S::NQ3];
+        }
+    }
+    diag_contract3<P, NQ>(tb, L, nel, dE + (size_t)e0 * 3 * S::NP);
+}
+
+// Diagonal from compact data: within one component a the cofactor-derivative
+// term vanishes, so H[an,ap] = c_id (W^-1 W^-T)_np + c_tc (Tw_an Cw_ap +
+// Cw_an Tw_ap) + c_cc Cw_an Cw_ap with Tw = T W^{-T}, Cw = C W^{-T}.
+template <int P, int NQ, typename TT>
+__device__ inline void b3_diagc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    __shared__ DiagLds3<P, NQ> L;
+    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+        double T[9], C[9], Tw[9], Cw[9], WW[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) T[k] = (double)h[k * S::NQ3];
+        const double cid = h[9 * S::NQ3], ctc = h[10 * S::NQ3], ccc = h[11 * S::NQ3];
+        cof3(T, C);
+        if (tg.ideal) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                Tw[k] = T[k];
+                Cw[k] = C[k];
+                WW[k] = (k % 4 == 0) ? 1.0 : 0.0;
+            }
+        } else {
+            mul_winv<3, double>(tg, T, Tw, true);
+            mul_winv<3, double>(tg, C, Cw, true);
+#pragma unroll
+            for (int n = 0; n < 3; ++n)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) s += tg.Winv[n * 3 + k] * tg.Winv[p * 3 + k];
+                    WW[n * 3 + p] = s;
+                }
+        }
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr) {
+            const int n = diag_pn(pr), p = diag_pp(pr);
+            const double f = (n == p) ? 1.0 : 2.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double hv = cid * WW[n * 3 + p] +
+                                  ctc * (Tw[a * 3 + n] * Cw[a * 3 + p] + Cw[a * 3 + n] * Tw[a * 3 + p]) +
+                                  ccc * Cw[a * 3 + n] * Cw[a * 3 + p];
+                L.sQ[((el * 6 + pr) * 3 + a) * S::NQ3 + q] = f * hv;
+            }
+        }
+    }
+    diag_contract3<P, NQ>(tb, L, nel, dE + (size_t)e0 * 3 * S::NP);
+}
+
+// ------------------------------------------------------------------------
+// Kernel entry points: single mesh (grid over element blocks) and batched
+// (grid over a tile list of (slot, first element) with per-slot geometry,
+// target and offsets into packed pools).
+// ------------------------------------------------------------------------
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_energy<P, NQ>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_gradient<P, NQ>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_apply<P, NQ, TT, CT>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k3_setupc(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void k3_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_applyc<P, NQ, TT, CT>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__restrict__ H, double *__restrict__ dE)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_diag<P, NQ, TT>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void k3_diagc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, double *__restrict__ dE)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = blockIdx.x * EPB;
+    b3_diagc<P, NQ, TT>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void kb3_energy(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ part)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_energy<P, NQ>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ>
+__global__ __launch_bounds__(BLOCK) void kb3_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_gradient<P, NQ>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb3_setup(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_setup<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void kb3_apply(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_apply<P, NQ, TT, CT>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb3_setupc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_setupc<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT, typename CT>
+__global__ __launch_bounds__(BLOCK) void kb3_applyc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_applyc<P, NQ, TT, CT>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb3_diag(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_diag<P, NQ, TT>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+template <int P, int NQ, typename TT>
+__global__ __launch_bounds__(BLOCK) void kb3_diagc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const Tile t = tiles[blockIdx.x];
+    if (gate && !gate[t.slot]) return;
+    const SlotDev &s = slots[t.slot];
+    b3_diagc<P, NQ, TT>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 }  // namespace tmop

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/tmop.h"
 #include "tmop_dev.hpp"
 
 namespace tmop {
@@ -26,10 +27,98 @@ struct Ops {
                    double *dE);
     void (*diag32)(int grid, hipStream_t, const Geom &, const Tables &, const float *H,
                    double *dE);
+    // compact quadrature data (T and four weighted metric coefficients)
+    void (*setupc64)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const double *x, double *Q, double *bad);
+    void (*setupc32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const double *x, float *Q, double *bad);
+    void (*applyc64)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const double *Q, const double *v, double *yE);
+    void (*applyc32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const float *Q, const double *v, float *yE);
+    void (*diagc64)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                    const double *Q, double *dE);
+    void (*diagc32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                    const float *Q, double *dE);
 };
+
+// Batched launchers (grid = number of tiles); every batched element kernel
+// takes the same arguments: 1D tables of its class, tile list, slot table,
+// per-slot gate, input vector id, partial-sum output.
+typedef void (*BLaunch)(int grid, hipStream_t, const Tables &, const Tile *, const SlotDev *,
+                        const int *gate, int vin, double *part);
+
+struct BOps {
+    int epb;
+    BLaunch energy, gradient;
+    BLaunch setup[2][2];  // [storage tensor/compact][fp64/fp32]
+    BLaunch apply[2][2];
+    BLaunch diag[2][2];
+};
+
+// Host-side 1D tables (GLL basis at Gauss-Legendre points) and constant
+// target of a (p, n_q) / params pair; defined in capi.hip.
+int internal_tables(int p, int nq, Tables *tb);
+int internal_target(const tmop_params *prm, int dim, Target *tg);
 
 // Returns false if no kernel was built for this combination.
 bool find_ops(int dim, int p, int nq, Ops *out);
+bool find_bops(int dim, int p, int nq, BOps *out);
+bool bops2(int p, int nq, BOps *out);
+bool bops3_p1(int nq, BOps *out);
+bool bops3_p2(int nq, BOps *out);
+bool bops3_p3(int nq, BOps *out);
+bool bops3_p4(int nq, BOps *out);
+
+#define TMOP_BOPS_BODY(K, SZ, P, NQ)                                                           \
+    {                                                                                          \
+        BOps o;                                                                                \
+        o.epb = SZ<P, NQ>::EPB;                                                                \
+        o.energy = [](int grid, hipStream_t s, const Tables &t, const Tile *tl, const SlotDev *sl, \
+                      const int *gt, int vin, double *part) {                                  \
+            hipLaunchKernelGGL((K##_energy<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, gt, \
+                               vin, part);                                                     \
+        };                                                                                     \
+        o.gradient = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,               \
+                        const SlotDev *sl, const int *gt, int vin, double *part) {             \
+            hipLaunchKernelGGL((K##_gradient<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
+                               gt, vin, part);                                                 \
+        };                                                                                     \
+        TMOP_BOPS_PREC(K, P, NQ, 0, double, double)                                            \
+        TMOP_BOPS_PREC(K, P, NQ, 1, float, float)                                              \
+        *out = o;                                                                              \
+        return true;                                                                           \
+    }
+
+#define TMOP_BOPS_PREC(K, P, NQ, IDX, TT, CT)                                                  \
+    o.setup[0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int vin, double *part) {            \
+        hipLaunchKernelGGL((K##_setup<P, NQ, TT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, gt, \
+                           vin, part);                                                         \
+    };                                                                                         \
+    o.setup[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int vin, double *part) {            \
+        hipLaunchKernelGGL((K##_setupc<P, NQ, TT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl,   \
+                           gt, vin, part);                                                     \
+    };                                                                                         \
+    o.apply[0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int vin, double *) {                \
+        hipLaunchKernelGGL((K##_apply<P, NQ, TT, CT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
+                           gt, vin);                                                           \
+    };                                                                                         \
+    o.apply[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int vin, double *) {                \
+        hipLaunchKernelGGL((K##_applyc<P, NQ, TT, CT>), dim3(grid), dim3(BLOCK), 0, s, t, tl,   \
+                           sl, gt, vin);                                                       \
+    };                                                                                         \
+    o.diag[0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,              \
+                        const SlotDev *sl, const int *gt, int, double *) {                     \
+        hipLaunchKernelGGL((K##_diag<P, NQ, TT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, gt); \
+    };                                                                                         \
+    o.diag[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,              \
+                        const SlotDev *sl, const int *gt, int, double *) {                     \
+        hipLaunchKernelGGL((K##_diagc<P, NQ, TT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, gt); \
+    };
 bool ops2(int p, int nq, Ops *out);
 bool ops3_p1(int nq, Ops *out);
 bool ops3_p2(int nq, Ops *out);
@@ -79,6 +168,36 @@ bool ops3_p4(int nq, Ops *out);
                       double *dE) {                                                              \
             hipLaunchKernelGGL((K##_diag<P, NQ, float>), dim3(grid), dim3(BLOCK), 0, s, g, t,   \
                                H, dE);                                                          \
+        };                                                                                       \
+        o.setupc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
+                        const Target &w, const double *x, double *Q, double *bad) {             \
+            hipLaunchKernelGGL((K##_setupc<P, NQ, double>), dim3(grid), dim3(BLOCK), 0, s, g, t,\
+                               w, x, Q, bad);                                                   \
+        };                                                                                       \
+        o.setupc32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
+                        const Target &w, const double *x, float *Q, double *bad) {              \
+            hipLaunchKernelGGL((K##_setupc<P, NQ, float>), dim3(grid), dim3(BLOCK), 0, s, g, t, \
+                               w, x, Q, bad);                                                   \
+        };                                                                                       \
+        o.applyc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
+                        const Target &w, const double *Q, const double *v, double *yE) {        \
+            hipLaunchKernelGGL((K##_applyc<P, NQ, double, double>), dim3(grid), dim3(BLOCK), 0, \
+                               s, g, t, w, Q, v, yE);                                           \
+        };                                                                                       \
+        o.applyc32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
+                        const Target &w, const float *Q, const double *v, float *yE) {          \
+            hipLaunchKernelGGL((K##_applyc<P, NQ, float, float>), dim3(grid), dim3(BLOCK), 0,   \
+                               s, g, t, w, Q, v, yE);                                           \
+        };                                                                                       \
+        o.diagc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,\
+                       const double *Q, double *dE) {                                            \
+            hipLaunchKernelGGL((K##_diagc<P, NQ, double>), dim3(grid), dim3(BLOCK), 0, s, g, t, \
+                               w, Q, dE);                                                       \
+        };                                                                                       \
+        o.diagc32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,\
+                       const float *Q, double *dE) {                                             \
+            hipLaunchKernelGGL((K##_diagc<P, NQ, float>), dim3(grid), dim3(BLOCK), 0, s, g, t,  \
+                               w, Q, dE);                                                       \
         };                                                                                       \
         *out = o;                                                                                \
         return true;                                                                             \

@@ -44,6 +44,24 @@ struct Target {
     int metric;
 };
 
+// Batched launches: one tile = up to EPB consecutive elements of one slot
+// (mesh); a slot carries its geometry, target and device pointers to its DoF
+// vectors (by vector id), quadrature data and E-vector scratch.
+struct Tile {
+    int slot;
+    int e0;
+};
+
+constexpr int NVEC = 16;
+
+struct SlotDev {
+    Geom g;
+    Target tg;
+    double *vec[NVEC];
+    void *H;
+    void *eV;
+};
+
 // Symmetric packing of a d^2 x d^2 tensor: entry (r, s), r <= s, row-major
 // upper triangle.
 template <int D2>

@@ -30,14 +30,15 @@ void launch_step(long n, const double *x, const double *dx, double alpha, double
 void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hipStream_t s);
 
 void mr_init(long n, const double *b, const double *minv, double *r1, double *r2, double *y,
-             double *x, double *w, double *w1, double *w2, double *part, MinresState *st,
-             double rtol, hipStream_t s);
-void mr_v(long n, int j, const MinresState *st, const double *y, double *v, hipStream_t s);
-void mr_lanczos1(long n, int j, MinresState *st, double *hv, const double *r1, const double *v,
-                 double *part, hipStream_t s);
-void mr_lanczos2(long n, int j, MinresState *st, double *hv, const double *r2, const double *minv,
-                 double *z, double *part, hipStream_t s);
-void mr_update(long n, int j, const MinresState *st, const double *v, const double *w1,
-               const double *w2, double *wout, double *x, hipStream_t s);
+             double *v, double *x, double *w, double *w1, double *w2, double *part,
+             MinresState *st, double rtol, hipStream_t s);
+void mr_gather_l1(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
+                  bool fp32, int j, const MinresState *st, const double *v, const double *r1,
+                  double *hv, double *part, hipStream_t s);
+void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, double *hv,
+                 const double *r2, const double *minv, double *z, double *part2, hipStream_t s);
+void mr_update(long n, int j, const MinresState *sin, MinresState *sout, const double *part1,
+               const double *part2, double *v, const double *w1, const double *w2, double *wout,
+               double *x, const double *z, hipStream_t s);
 
 }  // namespace tmop

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtmop_hip.so")
 
 TMOP_FP64, TMOP_MIXED = 0, 1
+HESS_TENSOR, HESS_COMPACT = 0, 1
 ESS_BOUNDARY, ESS_NONE, ESS_MASK = 0, 1, 2
 
 STATUS = {
@@ -39,7 +40,8 @@ class MeshDesc(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int), ("nq1d", ctypes.c_int), ("has_W", ctypes.c_int),
-                ("W", ctypes.c_double * 9), ("precision", ctypes.c_int)]
+                ("W", ctypes.c_double * 9), ("precision", ctypes.c_int),
+                ("hess_storage", ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -90,6 +92,23 @@ SIGNATURES = {
                     ctypes.POINTER(ctypes.c_int)],
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
+    "tmop_pool_create": [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int, _P],
+    "tmop_pool_destroy": [_P],
+    "tmop_pool_request_bytes": [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
+                                ctypes.POINTER(ctypes.c_size_t)],
+    "tmop_pool_admit": [_P, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
+                        ctypes.POINTER(SolveParams), _P, _P, ctypes.POINTER(ctypes.c_int)],
+    "tmop_pool_step": [_P, ctypes.POINTER(ctypes.c_int)],
+    "tmop_pool_poll": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport)],
+    "tmop_pool_result": [_P, ctypes.c_int, _P, _P],
+    "tmop_pool_release": [_P, ctypes.c_int],
+    "tmop_pool_info": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                       ctypes.POINTER(ctypes.c_int)],
+    "tmop_pool_set_graph": [_P, ctypes.c_int],
+    "tmop_pool_last_error": [],
+    "tmop_batch_solve": [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
+                         ctypes.POINTER(_P), ctypes.POINTER(SolveParams),
+                         ctypes.POINTER(SolveReport), _P],
     "tmop_last_error": [],
     "tmop_version": [],
 }
@@ -105,7 +124,8 @@ def lib():
         for name, args in SIGNATURES.items():
             f = getattr(h, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name in ("tmop_last_error", "tmop_version") else ctypes.c_int
+            f.restype = (ctypes.c_char_p if name in ("tmop_last_error", "tmop_version",
+                                                     "tmop_pool_last_error") else ctypes.c_int)
         _lib_handle = h
     return _lib_handle
 
@@ -143,10 +163,13 @@ class Context:
     (E, (p+1)^dim)) and ``num_nodes``.
     ``ess``: "boundary" (box only), "none", or a uint8 CUDA mask of d*N_x.
     ``precision``: "fp64" or "mixed".
+    ``storage``: "tensor" (packed second-derivative tensor per point) or
+    "compact" (T and four metric coefficients per point).
     """
 
     def __init__(self, dim, n=None, p=1, nq1d=None, metric=None, precision="fp64", W=None,
-                 ess="boundary", elem_to_node=None, num_nodes=None, stream=None):
+                 ess="boundary", elem_to_node=None, num_nodes=None, stream=None,
+                 storage="tensor"):
         import torch
         self._torch = torch
         self.dim, self.p = dim, p
@@ -184,6 +207,8 @@ class Context:
             for k, v in enumerate(Wa.ravel()):
                 prm.W[k] = v
         prm.precision = {"fp64": TMOP_FP64, "mixed": TMOP_MIXED}[precision]
+        prm.hess_storage = {"tensor": HESS_TENSOR, "compact": HESS_COMPACT}[storage]
+        self.storage = storage
         self._md, self._prm = md, prm
         s = stream if stream is not None else torch.cuda.current_stream()
         self._stream = s
@@ -297,3 +322,119 @@ class Context:
                                       ctypes.byref(rep))
         _check(code)
         return rep.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# Batched and served solves
+# ---------------------------------------------------------------------------
+
+def _pcheck(code):
+    if code != 0:
+        raise TmopError(code, lib().tmop_pool_last_error().decode())
+
+
+def request(dim, n, p, nq1d=None, metric=None, precision="fp64", storage="tensor", W=None,
+            ess="boundary"):
+    """(MeshDesc, Params) of a structured-box request."""
+    ns = (n,) * dim if np.isscalar(n) else tuple(n)
+    md = MeshDesc()
+    md.dim, md.order_p = dim, p
+    md.nx, md.ny = ns[0], ns[1]
+    md.nz = ns[2] if dim == 3 else 0
+    md.ess_mode = {"boundary": ESS_BOUNDARY, "none": ESS_NONE}[ess]
+    prm = Params()
+    prm.metric = metric if metric is not None else (2 if dim == 2 else 303)
+    prm.nq1d = nq1d if nq1d is not None else p + 2
+    if W is not None:
+        prm.has_W = 1
+        for k, v in enumerate(np.asarray(W, dtype=np.float64).ravel()):
+            prm.W[k] = v
+    prm.precision = {"fp64": TMOP_FP64, "mixed": TMOP_MIXED}[precision]
+    prm.hess_storage = {"tensor": HESS_TENSOR, "compact": HESS_COMPACT}[storage]
+    return md, prm
+
+
+def solve_params(rel_grad_tol=1e-8, max_newton=200, max_minres=50, minres_rtol=1e-12,
+                 max_halvings=30, jacobi=True, g0_norm=0.0):
+    return SolveParams(rel_grad_tol, max_newton, max_minres, minres_rtol, max_halvings,
+                       int(bool(jacobi)), g0_norm)
+
+
+def request_bytes(md, prm):
+    b = ctypes.c_size_t()
+    _pcheck(lib().tmop_pool_request_bytes(ctypes.byref(md), ctypes.byref(prm), ctypes.byref(b)))
+    return b.value
+
+
+class Pool:
+    """Many solves advanced together (see tmop_pool_* in include/tmop.h)."""
+
+    def __init__(self, hbm_budget, max_slots, graph=True):
+        import torch
+        self._torch = torch
+        h = ctypes.c_void_p()
+        _pcheck(lib().tmop_pool_create(ctypes.byref(h), int(hbm_budget), int(max_slots), None))
+        self._h = h
+        self._keep = {}
+        if not graph:
+            _pcheck(lib().tmop_pool_set_graph(h, 0))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tmop_pool_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, md, prm, sp, x):
+        """Returns the slot index; raises TmopError (code ERR_BUSY / ERR_BUDGET ...)."""
+        slot = ctypes.c_int(-1)
+        s = self._torch.cuda.current_stream().cuda_stream
+        _pcheck(lib().tmop_pool_admit(self._h, ctypes.byref(md), ctypes.byref(prm), ctypes.byref(sp),
+                                      _ptr(x, dtype=self._torch.float64), ctypes.c_void_p(s),
+                                      ctypes.byref(slot)))
+        self._keep[slot.value] = (md, prm, sp)
+        return slot.value
+
+    def step(self):
+        n = ctypes.c_int()
+        _pcheck(lib().tmop_pool_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, slot):
+        done = ctypes.c_int()
+        rep = SolveReport()
+        _pcheck(lib().tmop_pool_poll(self._h, int(slot), ctypes.byref(done), ctypes.byref(rep)))
+        return bool(done.value), rep.as_dict()
+
+    def result(self, slot, out):
+        _pcheck(lib().tmop_pool_result(self._h, int(slot), _ptr(out, dtype=self._torch.float64), None))
+        return out
+
+    def release(self, slot):
+        _pcheck(lib().tmop_pool_release(self._h, int(slot)))
+        self._keep.pop(slot, None)
+
+    def info(self):
+        u, b, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()
+        _pcheck(lib().tmop_pool_info(self._h, ctypes.byref(u), ctypes.byref(b), ctypes.byref(n)))
+        return dict(used=u.value, budget=b.value, slots=n.value)
+
+
+def batch_solve(requests, xs, sps):
+    """Solve meshes together; xs (CUDA float64 tensors) are overwritten.  Returns reports."""
+    import torch
+    n = len(requests)
+    mds = (MeshDesc * n)(*[r[0] for r in requests])
+    prms = (Params * n)(*[r[1] for r in requests])
+    spa = (SolveParams * n)(*sps)
+    reps = (SolveReport * n)()
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(x, dtype=torch.float64).value for x in xs])
+    code = lib().tmop_batch_solve(n, mds, prms, ptrs, spa, reps,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _pcheck(code)
+    return [r.as_dict() for r in reps]

@@ -45,6 +45,7 @@ def test_binding_struct_layouts():
     assert tmop.MeshDesc.ess_mask.offset == 48
     assert tmop.Params.W.offset == 16
     assert ctypes.sizeof(tmop.Params) == 16 + 72 + 8
+    assert tmop.Params.hess_storage.offset == 92
     assert ctypes.sizeof(tmop.SolveParams) == 40
     assert ctypes.sizeof(tmop.SolveReport) == 16 + 10 * 8 + 8
 

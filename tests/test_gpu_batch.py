@@ -1,0 +1,129 @@
+"""Batched and served solves (tmop_pool_* / tmop_batch_solve).
+
+* every mesh of a heterogeneous batch (2D/3D, p = 1..4, FP64/mixed,
+  tensor/compact) reaches the same optimum as the same mesh solved alone with
+  tmop_solve (nodes within 1e-9 relative at the paper's eps = 1e-10);
+* a solve's result is bitwise identical alone in a pool and in a mix, with and
+  without HIP-graph replay of the MINRES iterations;
+* admission: a request above the budget is rejected (ERR_BUDGET), a full pool
+  answers ERR_BUSY until a release; a tangled request fails alone
+  (ERR_INVERTED) without changing the others' results.
+"""
+import numpy as np
+import pytest
+
+from oracle import basis
+from paper_2205_12721_amd import inputs
+from tests.gpu_common import TOLX, log, make_case, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    dict(dim=3, ns=(3, 3, 3), p=2, nq=4, precision="fp64", storage="tensor", seed=71),
+    dict(dim=2, ns=(6, 5), p=3, nq=5, precision="fp64", storage="compact", seed=72),
+    dict(dim=3, ns=(2, 3, 2), p=4, nq=6, precision="mixed", storage="tensor", seed=73),
+    dict(dim=3, ns=(4, 3, 3), p=1, nq=3, precision="fp64", storage="compact", seed=74),
+    dict(dim=2, ns=(5, 5), p=2, nq=4, precision="mixed", storage="compact", seed=75),
+    dict(dim=3, ns=(3, 2, 3), p=3, nq=5, precision="fp64", storage="tensor", seed=76),
+]
+
+
+def _mesh(c):
+    pb, x = make_case(c["dim"], c["ns"], c["p"], c["nq"], seed=c["seed"], amp=0.05,
+                      recipe="smooth" if c["dim"] == 3 else "interior_jitter")
+    return pb, x
+
+
+def _req(c):
+    from paper_2205_12721_amd.tmop import request
+    return request(c["dim"], c["ns"], c["p"], c["nq"], precision=c["precision"], storage=c["storage"])
+
+
+def test_batch_matches_single_solves():
+    from paper_2205_12721_amd.tmop import Context, batch_solve, solve_params
+    meshes = [_mesh(c) for c in MIX]
+    xs = [to_dev(x) for _, x in meshes]
+    sps = [solve_params(rel_grad_tol=1e-10, max_newton=200) for _ in MIX]
+    reps = batch_solve([_req(c) for c in MIX], xs, sps)
+    for c, (pb, x0), xb, rb in zip(MIX, meshes, xs, reps):
+        ctx = Context(c["dim"], c["ns"], c["p"], c["nq"], precision=c["precision"], storage=c["storage"])
+        xa = to_dev(x0)
+        ra = ctx.solve(xa, rel_grad_tol=1e-10, max_newton=200)
+        ctx.close()
+        e = rel(to_host(xb), to_host(xa))
+        log(c, "batch", rb["status"], rb["newton_its"], rb["minres_its_total"], "alone", ra["status"],
+            ra["newton_its"], ra["minres_its_total"], "x rel %.2e" % e)
+        assert rb["status"] == 0 and ra["status"] == 0
+        assert e <= TOLX
+        assert abs(rb["F"] - ra["F"]) <= 1e-10 * ra["F0"]
+
+
+def _pool_run(cases, graph=True, budget=None, extra=None):
+    from paper_2205_12721_amd.tmop import Pool, request_bytes, solve_params
+    reqs = [_req(c) for c in cases]
+    total = sum(request_bytes(*r) for r in reqs)
+    pool = Pool(budget or total, len(cases), graph=graph)
+    xs = [to_dev(_mesh(c)[1]) if extra is None or k not in extra else to_dev(extra[k])
+          for k, c in enumerate(cases)]
+    slots = [pool.admit(md, prm, solve_params(rel_grad_tol=1e-10), x) for (md, prm), x in zip(reqs, xs)]
+    while pool.step() > 0:
+        pass
+    out = []
+    for s, x in zip(slots, xs):
+        done, rep = pool.poll(s)
+        assert done
+        pool.result(s, x)
+        out.append((to_host(x), rep))
+    pool.close()
+    return out
+
+
+def test_pool_alone_equals_mix_bitwise():
+    alone = _pool_run([MIX[0]])[0]
+    alone_nog = _pool_run([MIX[0]], graph=False)[0]
+    mix = _pool_run([MIX[3], MIX[0], MIX[1], MIX[2]])
+    assert np.array_equal(alone[0], mix[1][0])
+    assert np.array_equal(alone[0], alone_nog[0])
+    assert alone[1]["newton_its"] == mix[1][1]["newton_its"]
+    assert alone[1]["minres_its_total"] == mix[1][1]["minres_its_total"]
+    alone2 = _pool_run([MIX[2]])[0]
+    assert np.array_equal(alone2[0], mix[3][0])
+
+
+def test_tangled_request_fails_alone():
+    from paper_2205_12721_amd.tmop import ERR_INVERTED
+    c = MIX[0]
+    ref = _pool_run([MIX[1], c])
+    bad = _mesh(c)[1].copy()
+    # drag an interior node far outside its elements
+    nx = bad.size // 3
+    bad[nx // 2] += 0.9
+    res = _pool_run([MIX[1], c], extra={1: bad})
+    assert res[1][1]["status"] == ERR_INVERTED
+    assert res[0][1]["status"] == 0
+    assert np.array_equal(res[0][0], ref[0][0])
+
+
+def test_admission_budget_and_busy():
+    from paper_2205_12721_amd.tmop import (ERR_BUSY, Pool, TmopError, request, request_bytes,
+                                           solve_params)
+    md, prm = request(3, (3, 3, 3), 2, 4)
+    b = request_bytes(md, prm)
+    big_md, big_prm = request(3, (6, 6, 6), 3, 5)
+    pool = Pool(int(2.5 * b), 8)
+    x = to_dev(_mesh(MIX[0])[1])
+    with pytest.raises(TmopError) as e:
+        pool.admit(big_md, big_prm, solve_params(), to_dev(np.zeros(3 * 19 ** 3)))
+    assert e.value.code == 8  # ERR_BUDGET
+    s0 = pool.admit(md, prm, solve_params(), x)
+    s1 = pool.admit(md, prm, solve_params(), x)
+    with pytest.raises(TmopError) as e:
+        pool.admit(md, prm, solve_params(), x)
+    assert e.value.code == ERR_BUSY
+    assert pool.info()["used"] <= pool.info()["budget"]
+    pool.release(s0)
+    s2 = pool.admit(md, prm, solve_params(), x)
+    assert s2 == s0
+    while pool.step() > 0:
+        pass
+    pool.close()

@@ -26,11 +26,12 @@ def _config(name):
     return c, pb, x, v
 
 
-def test_config2_full_parity():
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
+def test_config2_full_parity(storage):
     from paper_2205_12721_amd.tmop import Context
     c, pb, x, v = _config("c2")
-    log("c2 ndof", pb.ndof)
-    ctx = Context(3, c["n"], c["p"], c["nq"])
+    log("c2 ndof", pb.ndof, storage)
+    ctx = Context(3, c["n"], c["p"], c["nq"], storage=storage)
     xd = to_dev(x)
     F, md = ctx.energy_mindet(xd)
     assert abs(F - pb.energy(x)) <= TOL64 * pb.energy(x)
@@ -41,19 +42,20 @@ def test_config2_full_parity():
     assert rel(to_host(ctx.hessian_apply(to_dev(v))), yo) <= TOL64
     assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= TOL64
     ctx.close()
-    ctx = Context(3, c["n"], c["p"], c["nq"], precision="mixed")
+    ctx = Context(3, c["n"], c["p"], c["nq"], precision="mixed", storage=storage)
     ctx.hessian_setup(xd)
     err = rel(to_host(ctx.hessian_apply(to_dev(v))), yo)
-    log("c2 mixed hvp rel err %.3e" % err)
+    log("c2 mixed hvp rel err %.3e" % err, storage)
     assert err <= 2e-6
     ctx.close()
 
 
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("name", ["c3a", "c3b"])
-def test_config3_sampled_parity(name):
+def test_config3_sampled_parity(name, storage):
     from paper_2205_12721_amd.tmop import Context
     c = inputs.CONFIGS[name]
-    ctx = Context(3, c["n"], c["p"], c["nq"])
+    ctx = Context(3, c["n"], c["p"], c["nq"], storage=storage)
     pb_full = oracle.Problem.box(3, c["n"], c["p"], c["nq"])
     # det check on the GPU path is not used to build oracle inputs: sample the
     # mesh with the oracle's own det test restricted to all elements is too slow
@@ -73,7 +75,7 @@ def test_config3_sampled_parity(name):
     assert rel(to_host(ctx.hessian_apply(to_dev(v)))[idx], yo) <= TOL64
     assert rel(to_host(ctx.hessian_diag())[idx], sub.diag(x)[idx]) <= TOL64
     ctx.close()
-    ctx = Context(3, c["n"], c["p"], c["nq"], precision="mixed")
+    ctx = Context(3, c["n"], c["p"], c["nq"], precision="mixed", storage=storage)
     ctx.hessian_setup(xd)
     err = rel(to_host(ctx.hessian_apply(to_dev(v)))[idx], yo)
     log(name, "mixed hvp rel err (sampled) %.3e" % err)

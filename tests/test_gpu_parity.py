@@ -39,13 +39,14 @@ def _ctx(dim, ns, p, nq, **kw):
     return Context(dim, ns, p, nq, **kw)
 
 
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq", CASES)
-def test_kernels_match_oracle(dim, ns, p, nq):
-    log("case", dim, ns, p, nq)
+def test_kernels_match_oracle(dim, ns, p, nq, storage):
+    log("case", dim, ns, p, nq, storage)
     pb, x = make_case(dim, ns, p, nq, seed=3)
     v = inputs.gaussian_vector(pb.ndof, 11, pb.ess)
     v_raw = inputs.gaussian_vector(pb.ndof, 12)  # nonzero on fixed DoFs too
-    ctx = _ctx(dim, ns, p, nq)
+    ctx = _ctx(dim, ns, p, nq, storage=storage)
     assert ctx.ndof == pb.ndof
     xd = to_dev(x)
     F, md = ctx.energy_mindet(xd)
@@ -63,12 +64,13 @@ def test_kernels_match_oracle(dim, ns, p, nq):
     ctx.close()
 
 
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq", [(2, (5, 4), 2, 4), (3, (3, 2, 3), 3, 5), (3, (2, 2, 2), 2, 4)])
-def test_unconstrained_and_masked(dim, ns, p, nq):
+def test_unconstrained_and_masked(dim, ns, p, nq, storage):
     import torch
     pb, x = make_case(dim, ns, p, nq, seed=4, constrain=None)
     v = inputs.gaussian_vector(pb.ndof, 13)
-    ctx = _ctx(dim, ns, p, nq, ess="none")
+    ctx = _ctx(dim, ns, p, nq, ess="none", storage=storage)
     xd = to_dev(x)
     assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
     ctx.hessian_setup(xd)
@@ -79,7 +81,7 @@ def test_unconstrained_and_masked(dim, ns, p, nq):
     mask = np.random.default_rng(5).uniform(size=pb.ndof) < 0.3
     pbm = oracle.Problem(dim, p, nq, pb.e2n, pb.nx, ess=mask)
     mdev = torch.as_tensor(mask.astype(np.uint8)).cuda()
-    ctx = _ctx(dim, ns, p, nq, ess=mdev)
+    ctx = _ctx(dim, ns, p, nq, ess=mdev, storage=storage)
     assert rel(to_host(ctx.gradient(xd)), pbm.gradient(x)) <= TOL64
     ctx.hessian_setup(xd)
     assert rel(to_host(ctx.hessian_apply(to_dev(v))), pbm.hvp(x, v)) <= TOL64
@@ -87,15 +89,16 @@ def test_unconstrained_and_masked(dim, ns, p, nq):
     ctx.close()
 
 
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq", [(2, (4, 4), 2, 4), (3, (2, 3, 2), 2, 4)])
-def test_constant_target(dim, ns, p, nq):
+def test_constant_target(dim, ns, p, nq, storage):
     rng = np.random.default_rng(7)
     W = np.eye(dim) + 0.2 * rng.standard_normal((dim, dim))
     if np.linalg.det(W) < 0:
         W[:, 0] *= -1
     pb, x = make_case(dim, ns, p, nq, seed=5, W=W)
     v = inputs.gaussian_vector(pb.ndof, 14, pb.ess)
-    ctx = _ctx(dim, ns, p, nq, W=W)
+    ctx = _ctx(dim, ns, p, nq, W=W, storage=storage)
     xd = to_dev(x)
     assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
     assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
@@ -123,19 +126,20 @@ def test_general_mesh_connectivity(dim, ns, p, nq):
     ctx.close()
 
 
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq", [(2, (8, 8), 2, 4), (3, (3, 3, 3), 3, 5), (3, (3, 3, 2), 2, 4)])
-def test_mixed_precision_hvp(dim, ns, p, nq):
-    """FP32 tensor + FP32 action: error vs the FP64 oracle at FP32 level."""
+def test_mixed_precision_hvp(dim, ns, p, nq, storage):
+    """FP32 quadrature data + FP32 action: error vs the FP64 oracle at FP32 level."""
     pb, x = make_case(dim, ns, p, nq, seed=8)
     v = inputs.gaussian_vector(pb.ndof, 16, pb.ess)
-    ctx = _ctx(dim, ns, p, nq, precision="mixed")
+    ctx = _ctx(dim, ns, p, nq, precision="mixed", storage=storage)
     xd = to_dev(x)
     # energy and gradient stay FP64
     assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
     assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
     ctx.hessian_setup(xd)
     err = rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v))
-    log("mixed hvp rel err", err)
+    log("mixed hvp rel err", storage, err)
     assert 0 < err <= 2e-6
     assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= 2e-6
     ctx.close()
