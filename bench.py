@@ -125,6 +125,103 @@ def cpu_baseline(cfg, x, v, seconds):
     }
 
 
+def batch_leg(count):
+    """256 independent hex meshes (log-uniform sizes, p = 1..4, n_q = p+2, mu_303):
+    one batched mixed-precision solve vs one-mesh-at-a-time FP64 solves."""
+    import torch
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes, batch_solve, request, solve_params
+    specs = inputs.batch_specs(count, seed=5)
+    xs = [inputs.perturbed_box(3, s["n"], s["p"], basis_nodes(s["p"]), s["seed"], recipe="smooth",
+                               amp=0.05)[0] for s in specs]
+    ndof = sum(x.size for x in xs)
+    reqs = [request(3, s["n"], s["p"], s["nq"], precision="mixed", storage="compact") for s in specs]
+    sps = [solve_params(rel_grad_tol=1e-8, max_newton=100) for _ in specs]
+    xd = [torch.as_tensor(x).cuda() for x in xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = batch_solve(reqs, xd, sps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = []
+    for s, x in zip(specs, xs):
+        ctx = Context(3, s["n"], s["p"], s["nq"])
+        xs1 = torch.as_tensor(x).cuda()
+        seq.append(ctx.solve(xs1, rel_grad_tol=1e-8, max_newton=100))
+        ctx.close()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    ok = [k for k in range(count) if reps[k]["status"] == 0 and seq[k]["status"] == 0]
+    dF = [abs(reps[k]["F"] - seq[k]["F"]) / max(abs(seq[k]["F"]), 1e-300) for k in ok]
+    return {
+        "meshes": count, "dofs_total": int(ndof),
+        "batched_mixed_s": round(tb, 4), "sequential_fp64_s": round(ts, 4),
+        "speedup": round(ts / tb, 2),
+        "solved_batched": sum(1 for r in reps if r["status"] == 0),
+        "solved_sequential": sum(1 for r in seq if r["status"] == 0),
+        "max_rel_final_energy_diff": float(max(dF)) if dF else None,
+        "newton_its_batched": int(sum(r["newton_its"] for r in reps)),
+        "newton_its_sequential": int(sum(r["newton_its"] for r in seq)),
+    }
+
+
+def serve_leg(rate, nreq):
+    """Poisson stream of mixed 2D/3D requests through the pool vs a sequential FP64 loop."""
+    from paper_2205_12721_amd import inputs, serve
+    reqs = inputs.serving_stream(rate, count=nreq, seed=6)
+    xs = serve.make_inputs(reqs)
+    budget = serve.budget_for(reqs, factor=1.0, cap=64 << 30)
+    s, _ = serve.serve(reqs, xs, budget, max_slots=min(512, nreq))
+    q, _ = serve.sequential(reqs, xs)
+    r3 = lambda v: None if v is None else round(v, 3)  # noqa: E731
+    return {
+        "rate_per_s": rate, "requests": nreq,
+        "p50_ms": r3(s["p50_ms"]), "p99_ms": r3(s["p99_ms"]),
+        "solves_per_s": r3(s["solves_per_s"]), "solved": s["solved"], "budget_bytes": budget,
+        "sequential_fp64": {"p50_ms": r3(q["p50_ms"]), "p99_ms": r3(q["p99_ms"]),
+                            "solves_per_s": r3(q["solves_per_s"]), "solved": q["solved"]},
+    }
+
+
+# Sec. 4.1, Table tab_kershaw_baseline: GPU PA* (Jacobi) on 4 V100s, for context
+KERSHAW_PAPER = {1: (0.4, 11, 203), 2: (0.9, 18, 507), 3: (3.9, 41, 1536), 4: (8.5, 70, 3110)}
+
+
+def kershaw_leg(orders, storage="compact"):
+    """Kershaw benchmark (Sec. 4.1): 24^3 hexes, eps_y = eps_z = 0.3, 9^3 points per
+    element, mu_303, at most 50 Jacobi-MINRES iterations per Newton step, stop at
+    |g|/|g0| <= 1e-10; boundary nodes slide along their faces.  Time to solution on one
+    GPU, FP64, next to the paper's 4-V100 numbers (context, not a like-for-like target)."""
+    import torch
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes
+    ns = (24, 24, 24)
+    res = {}
+    for p in orders:
+        mask = torch.as_tensor(inputs.sliding_mask(ns, p)).cuda()
+        ctx = Context(3, ns, p, 9, ess=mask, storage=storage)
+        x0 = torch.as_tensor(inputs.kershaw_nodes(ns, p, basis_nodes(p), 0.3, 0.3)).cuda()
+        x = x0.clone()
+        ctx.solve(x, rel_grad_tol=1e-10, max_newton=1, max_minres=2)  # warm-up (JIT of modules)
+        x.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.solve(x, rel_grad_tol=1e-10, max_newton=300, max_minres=50)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        pt, pn, pm = KERSHAW_PAPER.get(p, (None, None, None))
+        res["p%d" % p] = {
+            "dofs": 3 * (24 * p + 1) ** 3, "seconds": round(dt, 3), "status": rep["status_name"],
+            "newton_its": rep["newton_its"], "minres_its": rep["minres_its_total"],
+            "F0": rep["F0"], "F": rep["F"], "g_rel": rep["g_norm"] / rep["g0_norm"],
+            "paper_4xV100_seconds": pt, "paper_newton_its": pn, "paper_minres_its": pm,
+        }
+    res["storage"] = storage
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +233,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
+    ap.add_argument("--batch-meshes", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--kershaw-orders", default="1,2,3,4")
+    ap.add_argument("--no-kershaw", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -228,6 +332,17 @@ def main():
             "roofline": roofline(ne, nqe, sv, cv.ndof, 8 if prec == "fp64" else 4, av),
         }
         cv.close()
+
+    if not args.no_batch:
+        out["batch"] = batch_leg(args.batch_meshes)
+        log("[bench] batch leg done")
+    if not args.no_serve:
+        out["serve"] = serve_leg(args.serve_rate, args.serve_requests)
+        log("[bench] serve leg done")
+
+    if not args.no_kershaw:
+        out["kershaw"] = kershaw_leg([int(v) for v in args.kershaw_orders.split(",") if v])
+        log("[bench] kershaw leg done")
 
     if not args.no_copy_bw:
         bw = copy_bandwidth(torch)

@@ -187,3 +187,53 @@ def serving_stream(rate, count=2000, seed=6, max_n3=48):
                          metric=2 if dim == 2 else 303,
                          seed=int(rng.integers(0, 2 ** 31 - 1))))
     return reqs
+
+
+# ---------------------------------------------------------------------------
+# Kershaw meshes (Sec. 4.1 and its appendix): the benchmark's analytic
+# deformation of a uniform hex mesh of [0,1]^3.  x is unchanged; [0,1] in x is
+# cut into six equal layers; in the first and last layers y (and z) are
+# compressed towards opposite corners by the piecewise-linear maps L and R
+# with slopes set by eps, and the middle layers blend between them with a
+# quintic smoothstep.  eps = 1 gives the uniform mesh.  Boundary faces map to
+# themselves, so boundary nodes only move tangentially.
+# ---------------------------------------------------------------------------
+
+def _kershaw_R(eps, t):
+    return np.where(t <= 0.5, (2.0 - eps) * t, 1.0 + eps * (t - 1.0))
+
+
+def _kershaw_L(eps, t):
+    return 1.0 - _kershaw_R(eps, 1.0 - t)
+
+
+def _smoothstep(u):
+    u = np.clip(u, 0.0, 1.0)
+    return u * u * u * (u * (6.0 * u - 15.0) + 10.0)
+
+
+def kershaw_map(x, t, eps):
+    """Image of coordinate t (y or z) at abscissa x for anisotropy eps."""
+    layer = np.floor(6.0 * x).astype(int)
+    lam = 6.0 * x - layer
+    L, R = _kershaw_L(eps, t), _kershaw_R(eps, t)
+    blend = lambda a, b, u: a + (b - a) * _smoothstep(u)  # noqa: E731
+    return np.select([layer <= 0, (layer == 1) | (layer == 4), layer == 2, layer == 3],
+                     [L, blend(L, R, lam), blend(R, L, lam / 2.0), blend(R, L, (1.0 + lam) / 2.0)],
+                     default=R)
+
+
+def kershaw_nodes(ns, p, nodes1d, eps_y=0.3, eps_z=0.3):
+    """Kershaw node vector (3D) of an ns = (n_x, n_y, n_z) box of order p; n_x must be a
+    multiple of 6 and n_y, n_z multiples of 2 for the layers to align with elements."""
+    x = uniform_nodes(ns, p, nodes1d)
+    nx = x.size // 3
+    X, Y, Z = x[:nx], x[nx:2 * nx], x[2 * nx:]
+    return np.concatenate([X, kershaw_map(X, Y, eps_y), kershaw_map(X, Z, eps_z)])
+
+
+def sliding_mask(ns, p):
+    """uint8 mask (dim*N_x): component c of a node is fixed iff the node lies on a face
+    normal to axis c, so boundary nodes slide along their faces (edges: along the edge;
+    corners fixed)."""
+    return boundary_component_mask(ns, p).astype(np.uint8).ravel()

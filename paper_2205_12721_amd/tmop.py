@@ -23,6 +23,7 @@ STATUS = {
     8: "ERR_BUDGET", 9: "ERR_BUSY", 10: "ERR_HIP", 11: "ERR_STATE",
 }
 OK, ERR_INVERTED, ERR_LINESEARCH, ERR_NOT_CONVERGED, ERR_NONFINITE = 0, 3, 4, 5, 6
+ERR_BUDGET, ERR_BUSY = 8, 9
 
 
 class TmopError(RuntimeError):

@@ -1,0 +1,64 @@
+"""Kershaw benchmark meshes (Sec. 4.1): 9^3 Gauss-Legendre points per element,
+mu_303, sliding boundary nodes (component normal to the face fixed).
+
+* every operator matches the oracle on a 6x2x2 Kershaw mesh (eps = 0.3), p = 1..3;
+* the Newton-MINRES solve drives the deformed mesh to the uniform grid (the
+  optimum: every element the same affine image of the reference cube) as the
+  paper's benchmark does, and matches the oracle's solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import basis
+from paper_2205_12721_amd import inputs
+from tests.gpu_common import TOL64, TOLX, log, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NS = (6, 2, 2)
+
+
+def _problem(p):
+    mask = inputs.sliding_mask(NS, p)
+    e2n, nx = oracle.mesh.box_topology(3, NS, p)
+    pb = oracle.Problem(3, p, 9, e2n, nx, ess=mask.astype(bool))
+    x = inputs.kershaw_nodes(NS, p, basis.gll_nodes(p), 0.3, 0.3)
+    assert pb.min_det(x) > 0
+    return pb, x, mask
+
+
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_kershaw_operators(p, storage):
+    import torch
+    from paper_2205_12721_amd.tmop import Context
+    pb, x, mask = _problem(p)
+    v = inputs.gaussian_vector(pb.ndof, 5, pb.ess)
+    ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda(), storage=storage)
+    xd = to_dev(x)
+    assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
+    assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
+    ctx.hessian_setup(xd)
+    assert rel(to_host(ctx.hessian_apply(to_dev(v))), pb.hvp(x, v)) <= TOL64
+    assert rel(to_host(ctx.hessian_diag()), pb.diag(x)) <= TOL64
+    ctx.close()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_kershaw_solve_reaches_uniform_grid(p):
+    import torch
+    from paper_2205_12721_amd.tmop import Context
+    pb, x, mask = _problem(p)
+    xo, ro = oracle.newton_solve(pb, x, rel_grad_tol=1e-10, max_newton=200)
+    ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda())
+    xd = to_dev(x)
+    rg = ctx.solve(xd, rel_grad_tol=1e-10, max_newton=200)
+    ctx.close()
+    xu = inputs.uniform_nodes(NS, p, basis.gll_nodes(p))
+    log("kershaw p=%d oracle its %d F %.3e | gpu its %d F %.3e" % (p, ro["newton_its"], ro["F"],
+                                                                   rg["newton_its"], rg["F"]))
+    assert rg["status"] == 0 and ro["status"] == 0
+    assert rel(to_host(xd), xo) <= TOLX
+    assert np.abs(to_host(xd) - xu).max() < 1e-6
+    assert abs(rg["F"] - pb.energy(xu)) <= 1e-10 * rg["F0"]

@@ -165,7 +165,7 @@ def test_error_paths():
     import torch
     from paper_2205_12721_amd.tmop import TmopError, ERR_INVERTED
     with pytest.raises(TmopError) as e:
-        _ctx(3, (2, 2, 2), 3, 9)
+        _ctx(3, (2, 2, 2), 3, 8)  # n_q = p+5: no kernel
     assert e.value.code == 2
     ctx = _ctx(2, (2, 2), 1, 2, ess="none")
     with pytest.raises(TmopError) as e:
