@@ -155,6 +155,10 @@ int internal_tables(int p, int nq, Tables *tb)
     std::memset(tb, 0, sizeof(*tb));
     lagrange_tables(p, nq, xi, chi, tb->B, tb->G);
     for (int q = 0; q < nq; ++q) tb->w[q] = w[q];
+    for (int k = 0; k < MAXNQ * MAXNI; ++k) {
+        tb->Bf[k] = (float)tb->B[k];
+        tb->Gf[k] = (float)tb->G[k];
+    }
     return TMOP_OK;
 }
 

@@ -7,8 +7,13 @@
 namespace tmop {
 
 // ------------------------------------------------------------------------
-// G^T: sum of the (up to 2^dim) element-local copies of global node `node`,
-// component c, in a fixed order (deterministic, no atomics).
+// G^T on the structured box: sum of the (up to 2^dim) element-local copies of
+// global node `node`, component c, in a fixed order (deterministic, no
+// atomics).  The box E-vector is the exploded grid: along axis k, element e
+// owns positions e*(p+1) .. e*(p+1)+p, so grid coordinate gk = e*p + j lands
+// at position gk + e (owner e < nel) and, for a vertex shared with element
+// e-1 (j = 0, e > 0), also at gk + e - 1.  The copies of one node are thus
+// neighbours in x, and the lanes of a wave read runs of consecutive words.
 // ------------------------------------------------------------------------
 template <int DIM, typename ET>
 __device__ inline ET gather_box_node(const Geom &g, const ET *__restrict__ eV, int c, int node,
@@ -16,45 +21,41 @@ __device__ inline ET gather_box_node(const Geom &g, const ET *__restrict__ eV, i
 {
     const int p = g.p, ni = p + 1;
     const int np = DIM == 3 ? ni * ni * ni : ni * ni;
-    int ce[3][2], cj[3][2], nc[3];
+    // per axis: position of the copy owned by the lower element (slot 0) and
+    // by the upper element (slot 1), and whether each exists
+    int pos[3][2];
+    bool has[3][2];
+#pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const int gk = gc[k];
-        if (gk == g.M[k] - 1) {
-            ce[k][0] = g.nel[k] - 1;
-            cj[k][0] = p;
-            nc[k] = 1;
-        } else {
-            const int e = gk / p, j = gk - e * p;
-            if (j == 0 && e > 0) {
-                ce[k][0] = e - 1;
-                cj[k][0] = p;
-                ce[k][1] = e;
-                cj[k][1] = 0;
-                nc[k] = 2;
-            } else {
-                ce[k][0] = e;
-                cj[k][0] = j;
-                nc[k] = 1;
-            }
+        const int e = gk / p, j = gk - e * p;
+        has[k][0] = j == 0 && e > 0;
+        has[k][1] = e < g.nel[k];
+        pos[k][0] = gk + e - 1;
+        pos[k][1] = gk + e;
+    }
+    const int EX = g.nel[0] * ni;
+    const ET *base = eV + (size_t)c * g.ne * np;
+    // every load is issued unconditionally (a missing copy reads entry 0 and
+    // is then dropped), so they are all in flight together; the sum runs in
+    // a fixed order
+    constexpr int NC = DIM == 3 ? 8 : 4;
+    ET val[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        const int d = t & 1, b = (t >> 1) & 1, a = t >> 2;
+        bool ok = has[0][d] && has[1][b];
+        int off = pos[1][b] * EX + pos[0][d];
+        if (DIM == 3) {
+            ok = ok && has[2][a];
+            off += pos[2][a] * (g.nel[1] * ni) * EX;
         }
+        val[t] = base[ok ? off : 0];
+        if (!ok) val[t] = 0;
     }
-    ET s = 0;
-    if constexpr (DIM == 3) {
-        for (int a = 0; a < nc[2]; ++a)
-            for (int b = 0; b < nc[1]; ++b)
-                for (int d = 0; d < nc[0]; ++d) {
-                    const long e = ce[0][d] + (long)g.nel[0] * (ce[1][b] + (long)g.nel[1] * ce[2][a]);
-                    const int i = cj[0][d] + ni * (cj[1][b] + ni * cj[2][a]);
-                    s += eV[(e * DIM + c) * np + i];
-                }
-    } else {
-        for (int b = 0; b < nc[1]; ++b)
-            for (int d = 0; d < nc[0]; ++d) {
-                const long e = ce[0][d] + (long)g.nel[0] * ce[1][b];
-                const int i = cj[0][d] + ni * cj[1][b];
-                s += eV[(e * DIM + c) * np + i];
-            }
-    }
+    ET s = val[0];
+#pragma unroll
+    for (int t = 1; t < NC; ++t) s += val[t];
     return s;
 }
 
@@ -80,17 +81,17 @@ __device__ inline ET gather_csr_node(const Geom &g, const int32_t *__restrict__ 
 template <int DIM, typename ET>
 __device__ inline double gather_entry(const Geom &g, const int32_t *__restrict__ ptr,
                                       const int32_t *__restrict__ ent, const ET *__restrict__ eV,
-                                      long idx, bool *fixed)
+                                      int idx, bool *fixed)
 {
-    const int c = (int)(idx / g.nx);
-    const int node = (int)(idx % g.nx);
+    const int c = idx / g.nx;
+    const int node = idx - c * g.nx;
     if (ptr) {
         *fixed = is_fixed(g, c, node, -1, -1, -1);
         return *fixed ? 0.0 : (double)gather_csr_node<DIM, ET>(g, ptr, ent, eV, c, node);
     }
     int gc[3];
-    gc[0] = node % g.M[0];
     const int t = node / g.M[0];
+    gc[0] = node - t * g.M[0];
     gc[1] = DIM == 3 ? t % g.M[1] : t;
     gc[2] = DIM == 3 ? t / g.M[1] : 0;
     *fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);

@@ -105,8 +105,22 @@ __device__ inline void point_grad2(const Lds2<P, NQ, CT> &L, int el, int q1, int
     }
 }
 
+// E-vector index of (element e, component c, local node i1,i2): element-major
+// [e][c][i] on general meshes, the exploded grid [c][ey*NI+i2][ex*NI+i1] on
+// the structured box (the layout the node gather expects).
+template <int P>
+__device__ inline long ev_index2(const Geom &g, int e, int c, int i1, int i2)
+{
+    constexpr int NI = P + 1, NP = NI * NI;
+    if (g.e2n) return ((long)e * 2 + c) * NP + i1 + NI * i2;
+    const int ex = e % g.nel[0], ey = e / g.nel[0];
+    const long EX = (long)g.nel[0] * NI;
+    return (long)c * g.ne * NP + (long)(ey * NI + i2) * EX + ex * NI + i1;
+}
+
 template <int P, int NQ, typename CT, typename OT>
-__device__ inline void backward2(Lds2<P, NQ, CT> &L, int nel, OT *__restrict__ out)
+__device__ inline void backward2(Lds2<P, NQ, CT> &L, const Geom &g, int e0, int nel,
+                                 OT *__restrict__ out)
 {
     using S = S2<P, NQ>;
     constexpr int NI = S::NI, NQ2 = S::NQ2;
@@ -136,7 +150,7 @@ __device__ inline void backward2(Lds2<P, NQ, CT> &L, int nel, OT *__restrict__ o
 #pragma unroll
         for (int q1 = 0; q1 < NQ; ++q1)
             s += L.G[q1 * NI + i1] * t[q1] + L.B[q1 * NI + i1] * t[S::L1 + q1];
-        out[idx] = (OT)s;
+        out[ev_index2<P>(g, e0 + rc / 2, rc % 2, i1, i2)] = (OT)s;
     }
 }
 
@@ -193,7 +207,7 @@ __device__ inline void b2_gradient(const Geom &g, const Tables &tb, const Target
         for (int k = 0; k < 4; ++k) L.RY[(el * 4 + k) * S::NQ2 + q] = Pm[k];
     }
     __syncthreads();
-    backward2<P, NQ>(L, nel, gE + (size_t)e0 * 2 * S::NP);
+    backward2<P, NQ>(L, g, e0, nel, gE);
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
@@ -249,7 +263,7 @@ __device__ inline void b2_apply(const Geom &g, const Tables &tb, const TT *__res
         }
     }
     __syncthreads();
-    backward2<P, NQ>(L, nel, yE + (size_t)e0 * 2 * S::NP);
+    backward2<P, NQ>(L, g, e0, nel, yE);
 }
 
 // ------------------------------------------------------------------------
@@ -357,7 +371,7 @@ __device__ inline void b2_applyc(const Geom &g, const Tables &tb, const Target &
         for (int r = 0; r < 4; ++r) L.RY[(el * 4 + r) * S::NQ2 + q] = Y[r];
     }
     __syncthreads();
-    backward2<P, NQ>(L, nel, yE + (size_t)e0 * 2 * S::NP);
+    backward2<P, NQ>(L, g, e0, nel, yE);
 }
 
 // Hessian diagonal (Sec. 3.4): 2 components x 3 pairs (n <= p) of planes
@@ -372,8 +386,8 @@ struct DiagLds2 {
 };
 
 template <int P, int NQ>
-__device__ inline void diag_contract2(const Tables &tb, DiagLds2<P, NQ> &L, int nel,
-                                      double *__restrict__ dE)
+__device__ inline void diag_contract2(const Tables &tb, const Geom &g, int e0, DiagLds2<P, NQ> &L,
+                                      int nel, double *__restrict__ dE)
 {
     using S = S2<P, NQ>;
     constexpr int NI = S::NI, NQ2 = S::NQ2, NP = S::NP;
@@ -412,7 +426,10 @@ __device__ inline void diag_contract2(const Tables &tb, DiagLds2<P, NQ> &L, int 
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) dE[k] = L.sD[k];
+    for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) {
+        const int i = k % NP, r = k / NP;
+        dE[ev_index2<P>(g, e0 + r / 2, r % 2, i % NI, i / NI)] = L.sD[k];
+    }
 }
 
 template <int P, int NQ, typename TT>
@@ -433,7 +450,7 @@ __device__ inline void b2_diag(const Geom &g, const Tables &tb, const TT *__rest
                     f * (double)h[sym_index<4>(a * 2 + n, a * 2 + p) * S::NQ2];
         }
     }
-    diag_contract2<P, NQ>(tb, L, nel, dE + (size_t)e0 * 2 * S::NP);
+    diag_contract2<P, NQ>(tb, g, e0, L, nel, dE);
 }
 
 template <int P, int NQ, typename TT>
@@ -478,7 +495,7 @@ __device__ inline void b2_diagc(const Geom &g, const Tables &tb, const Target &t
             }
         }
     }
-    diag_contract2<P, NQ>(tb, L, nel, dE + (size_t)e0 * 2 * S::NP);
+    diag_contract2<P, NQ>(tb, g, e0, L, nel, dE);
 }
 
 // ------------------------------------------------------------------------

@@ -5,13 +5,20 @@
 //   A_a1(q) = sum_i1 G[q1][i1] sum_i2 B[q2][i2] sum_i3 B[q3][i3] x_a(i1,i2,i3)
 // and the transposed contractions map quadrature values back to nodes.
 //
-// LDS layout per workgroup (CT = compute type, double or float):
-//   sB, sG   [NQ][NI]                 1D tables
-//   sX       [EPB][3][NI^3]           element nodes (or v_E)
-//   R1       [EPB][3][2][NI][NI][NQ]  after the axis-1 contraction (B, G variants)
-//   R2       [EPB][3][3][NI][NQ][NQ]  after the axis-2 contraction (GB, BG, BB)
-//   RY       [EPB][9][NQ^3]           per-point 3x3 values (Y = H : grad v, or P)
-// Forward:  sX -> R1 -> R2 -> (points) ; backward: RY -> R2 -> R1 -> E-vector.
+// Each contraction stage is a loop over "pencils": one work item loads one 1D
+// line of its input from LDS once and produces the whole 1D line of outputs.
+// The 1D tables are indexed with compile-time constants in the kernel
+// arguments, so they are read into scalar registers instead of from LDS.
+//
+// LDS per workgroup (CT = compute type, double or float):
+//   X   [EPB][3][NI^3]            element nodes (or v_E)
+//   R1  [EPB][3][2][NI][NI][NQ]   after the axis-1 contraction (B, G variants)
+//   R2  [EPB][3][3][NI][NQ][NQ]   after the axis-2 contraction (GB, BG, BB)
+//   RY  [EPB][9][NQ^3]            per-point 3x3 values: J = dx/dxbar after
+//                                 the forward sweeps, then Y (H : grad v, or P)
+// with X/R2 and R1/RY overlaid.
+// Forward:  X -> R1 -> R2 -> RY(J);  point stage RY(J) -> RY(Y) in place;
+// backward: RY(Y) -> R2 -> R1 -> E-vector.
 #pragma once
 #include "tmop_dev.hpp"
 
@@ -29,26 +36,21 @@ struct S3 {
     static constexpr int NS = 45;            // packed tensor entries
 };
 
+// X and R2 share storage, and so do R1 and RY: each stage reads one of the
+// two buffers and writes the other, so a buffer is overwritten only after the
+// barrier that ends the last read of its previous contents.
 template <int P, int NQ, typename CT>
 struct Lds3 {
     using S = S3<P, NQ>;
-    CT B[NQ * S::NI];
-    CT G[NQ * S::NI];
-    CT X[S::EPB * 3 * S::NP];
-    CT R1[S::EPB * 6 * S::L1];
-    CT R2[S::EPB * 9 * S::L2];
-    CT RY[S::EPB * 9 * S::NQ3];
+    union {
+        CT X[S::EPB * 3 * S::NP];
+        CT R2[S::EPB * 9 * S::L2];
+    };
+    union {
+        CT R1[S::EPB * 6 * S::L1];
+        CT RY[S::EPB * 9 * S::NQ3];
+    };
 };
-
-template <int P, int NQ, typename CT>
-__device__ inline void load_tables3(const Tables &t, CT *sB, CT *sG)
-{
-    constexpr int NI = P + 1;
-    for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
-        sB[k] = (CT)t.B[k];
-        sG[k] = (CT)t.G[k];
-    }
-}
 
 // Global node of local node (i1,i2,i3) of element e, and its grid coordinates.
 template <int P>
@@ -70,7 +72,7 @@ __device__ inline int node3(const Geom &g, int e, int i1, int i2, int i3, int &g
     return gx + g.M[0] * (gy + g.M[1] * gz);
 }
 
-// Gather d components of a global vector into sX for the block's elements.
+// Gather 3 components of a global vector into X for the block's elements.
 // masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)).
 template <int P, int NQ, typename CT>
 __device__ inline void gather3(const Geom &g, const double *__restrict__ vec, int e0, int nel,
@@ -91,172 +93,232 @@ __device__ inline void gather3(const Geom &g, const double *__restrict__ vec, in
     }
 }
 
-// Axis-1 and axis-2 contractions: sX -> R1 -> R2.
+// Forward sweeps X -> R1 -> R2 -> RY (J at every point, plane el*9 + c*3 + b).
 template <int P, int NQ, typename CT>
-__device__ inline void forward12(const CT *sB, const CT *sG, const CT *sX, CT *R1, CT *R2, int nel)
+__device__ inline void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, CT *RY, int nel)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2;
-    for (int idx = threadIdx.x; idx < nel * 3 * NI * NI * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int i2 = r % NI;
-        r /= NI;
-        const int i3 = r % NI;
-        r /= NI;  // el*3 + c
-        const CT *x = sX + r * S::NP + (i3 * NI + i2) * NI;
-        CT b = 0, gg = 0;
+    constexpr int NI = S::NI, NP = S::NP, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    // axis 1: pencils (r, i3, i2), r = el*3 + c
+    for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
+        const int i23 = pen % (NI * NI), r = pen / (NI * NI);
+        const CT *x = X + r * NP + i23 * NI;
+        CT xv[NI];
 #pragma unroll
-        for (int i1 = 0; i1 < NI; ++i1) {
-            const CT xv = x[i1];
-            b += sB[q1 * NI + i1] * xv;
-            gg += sG[q1 * NI + i1] * xv;
+        for (int k = 0; k < NI; ++k) xv[k] = x[k];
+        CT *o = R1 + r * 2 * L1 + i23 * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT b = 0, d = 0;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                b += tabB<CT>(tb, q * NI + k) * xv[k];
+                d += tabG<CT>(tb, q * NI + k) * xv[k];
+            }
+            o[q] = b;
+            o[L1 + q] = d;
         }
-        CT *o = R1 + r * 2 * L1 + (i3 * NI + i2) * NQ + q1;
-        o[0] = b;
-        o[L1] = gg;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nel * 3 * NI * NQ * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int q2 = r % NQ;
-        r /= NQ;
-        const int i3 = r % NI;
-        r /= NI;
-        const CT *tb = R1 + r * 2 * L1 + i3 * NI * NQ + q1;  // B variant, [i2] stride NQ
-        const CT *tg = tb + L1;                             // G variant
-        CT gb = 0, bg = 0, bb = 0;
+    // axis 2: pencils (r, i3, q1)
+    for (int pen = threadIdx.x; pen < nel * 3 * NI * NQ; pen += BLOCK) {
+        const int q1 = pen % NQ, i3 = (pen / NQ) % NI, r = pen / (NQ * NI);
+        const CT *t = R1 + r * 2 * L1 + i3 * NI * NQ + q1;  // [i2] stride NQ
+        CT xb[NI], xg[NI];
 #pragma unroll
-        for (int i2 = 0; i2 < NI; ++i2) {
-            const CT B2 = sB[q2 * NI + i2], G2 = sG[q2 * NI + i2];
-            const CT xb = tb[i2 * NQ], xg = tg[i2 * NQ];
-            gb += B2 * xg;
-            bg += G2 * xb;
-            bb += B2 * xb;
+        for (int k = 0; k < NI; ++k) {
+            xb[k] = t[k * NQ];
+            xg[k] = t[L1 + k * NQ];
         }
-        CT *o = R2 + r * 3 * L2 + (i3 * NQ + q2) * NQ + q1;
-        o[0] = gb;
-        o[L2] = bg;
-        o[2 * L2] = bb;
+        CT *o = R2 + r * 3 * L2 + i3 * NQ2 + q1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT gb = 0, bg = 0, bb = 0;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const CT b2 = tabB<CT>(tb, q * NI + k), g2 = tabG<CT>(tb, q * NI + k);
+                gb += b2 * xg[k];
+                bg += g2 * xb[k];
+                bb += b2 * xb[k];
+            }
+            o[q * NQ] = gb;
+            o[L2 + q * NQ] = bg;
+            o[2 * L2 + q * NQ] = bb;
+        }
+    }
+    __syncthreads();
+    // axis 3: pencils (r, q2, q1) -> J at the NQ points of the pencil
+    for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
+        const int q12 = pen % NQ2, r = pen / NQ2;
+        const CT *t = R2 + r * 3 * L2 + q12;  // [i3] stride NQ^2
+        CT t0[NI], t1[NI], t2[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            t0[k] = t[k * NQ2];
+            t1[k] = t[L2 + k * NQ2];
+            t2[k] = t[2 * L2 + k * NQ2];
+        }
+        CT *o = RY + r * 3 * NQ3 + q12;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
+                a0 += b3 * t0[k];
+                a1 += b3 * t1[k];
+                a2 += g3 * t2[k];
+            }
+            o[q * NQ2] = a0;
+            o[NQ3 + q * NQ2] = a1;
+            o[2 * NQ3 + q * NQ2] = a2;
+        }
     }
     __syncthreads();
 }
 
-// Axis-3 contraction at one point: J[c*3+b] = d x_c / d xbar_b.
-template <int P, int NQ, typename CT>
-__device__ inline void point_grad3(const CT *sB, const CT *sG, const CT *R2, int el, int q1,
-                                   int q2, int q3, CT *J)
+// E-vector index of (element e, component c, local node i1,i2,i3).  General
+// meshes: element-major [e][c][i].  Structured box: the exploded grid
+// [c][ez*NI+i3][ey*NI+i2][ex*NI+i1], in which the node gather reads runs of
+// neighbouring addresses.
+template <int P>
+__device__ inline long ev_index3(const Geom &g, int e, int c, int i1, int i2, int i3)
 {
-    using S = S3<P, NQ>;
-    constexpr int NI = S::NI, L2 = S::L2;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const CT *t = R2 + (el * 3 + c) * 3 * L2 + q2 * NQ + q1;  // [i3] stride NQ^2
-        CT a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-        for (int i3 = 0; i3 < NI; ++i3) {
-            const CT B3 = sB[q3 * NI + i3], G3 = sG[q3 * NI + i3];
-            a0 += B3 * t[i3 * NQ * NQ];
-            a1 += B3 * t[L2 + i3 * NQ * NQ];
-            a2 += G3 * t[2 * L2 + i3 * NQ * NQ];
-        }
-        J[c * 3 + 0] = a0;
-        J[c * 3 + 1] = a1;
-        J[c * 3 + 2] = a2;
-    }
+    constexpr int NI = P + 1, NP = NI * NI * NI;
+    if (g.e2n) return ((long)e * 3 + c) * NP + i1 + NI * (i2 + NI * i3);
+    const int ex = e % g.nel[0];
+    const int t = e / g.nel[0];
+    const int ey = t % g.nel[1];
+    const int ez = t / g.nel[1];
+    const long EX = (long)g.nel[0] * NI, EY = (long)g.nel[1] * NI;
+    return (long)c * g.ne * NP + ((long)(ez * NI + i3) * EY + (ey * NI + i2)) * EX + ex * NI + i1;
 }
 
-// Transposed contractions RY -> R2 -> R1 -> out (E-vector, element-major
-// [e][c][i]).  y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q).
+// Backward (transposed) sweeps RY -> R2 -> R1 -> E-vector:
+//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q).
 template <int P, int NQ, typename CT, typename OT>
-__device__ inline void backward3(const CT *sB, const CT *sG, const CT *RY, CT *R2, CT *R1, int nel,
-                                 OT *__restrict__ out)
+__device__ inline void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
+                                 CT *R1, int nel, OT *__restrict__ out)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2, NQ3 = S::NQ3;
-    for (int idx = threadIdx.x; idx < nel * 3 * NI * NQ * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int q2 = r % NQ;
-        r /= NQ;
-        const int i3 = r % NI;
-        r /= NI;  // el*3 + c
-        const CT *y = RY + r * 3 * NQ3 + q2 * NQ + q1;  // [b] stride NQ3, [q3] stride NQ^2
-        CT t0 = 0, t1 = 0, t2 = 0;
+    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    // axis 3: pencils (r, q2, q1)
+    for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
+        const int q12 = pen % NQ2, r = pen / NQ2;
+        const CT *y = RY + r * 3 * NQ3 + q12;  // [b] stride NQ^3, [q3] stride NQ^2
+        CT y0[NQ], y1[NQ], y2[NQ];
 #pragma unroll
-        for (int q3 = 0; q3 < NQ; ++q3) {
-            const CT B3 = sB[q3 * NI + i3], G3 = sG[q3 * NI + i3];
-            t0 += B3 * y[q3 * NQ * NQ];
-            t1 += B3 * y[NQ3 + q3 * NQ * NQ];
-            t2 += G3 * y[2 * NQ3 + q3 * NQ * NQ];
+        for (int q = 0; q < NQ; ++q) {
+            y0[q] = y[q * NQ2];
+            y1[q] = y[NQ3 + q * NQ2];
+            y2[q] = y[2 * NQ3 + q * NQ2];
         }
-        CT *o = R2 + r * 3 * L2 + (i3 * NQ + q2) * NQ + q1;
-        o[0] = t0;
-        o[L2] = t1;
-        o[2 * L2] = t2;
+        CT *o = R2 + r * 3 * L2 + q12;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
+                t0 += b3 * y0[q];
+                t1 += b3 * y1[q];
+                t2 += g3 * y2[q];
+            }
+            o[k * NQ2] = t0;
+            o[L2 + k * NQ2] = t1;
+            o[2 * L2 + k * NQ2] = t2;
+        }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nel * 3 * NI * NI * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int i2 = r % NI;
-        r /= NI;
-        const int i3 = r % NI;
-        r /= NI;
-        const CT *t = R2 + r * 3 * L2 + i3 * NQ * NQ + q1;  // [q2] stride NQ
-        CT u0 = 0, u1 = 0;
+    // axis 2: pencils (r, i3, q1)
+    for (int pen = threadIdx.x; pen < nel * 3 * NI * NQ; pen += BLOCK) {
+        const int q1 = pen % NQ, i3 = (pen / NQ) % NI, r = pen / (NQ * NI);
+        const CT *t = R2 + r * 3 * L2 + i3 * NQ2 + q1;  // [q2] stride NQ
+        CT t0[NQ], t1[NQ], t2[NQ];
 #pragma unroll
-        for (int q2 = 0; q2 < NQ; ++q2) {
-            const CT B2 = sB[q2 * NI + i2], G2 = sG[q2 * NI + i2];
-            u0 += B2 * t[q2 * NQ];
-            u1 += G2 * t[L2 + q2 * NQ] + B2 * t[2 * L2 + q2 * NQ];
+        for (int q = 0; q < NQ; ++q) {
+            t0[q] = t[q * NQ];
+            t1[q] = t[L2 + q * NQ];
+            t2[q] = t[2 * L2 + q * NQ];
         }
-        CT *o = R1 + r * 2 * L1 + (i3 * NI + i2) * NQ + q1;
-        o[0] = u0;   // still needs G along axis 1
-        o[L1] = u1;  // still needs B along axis 1
+        CT *o = R1 + r * 2 * L1 + i3 * NI * NQ + q1;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT u0 = 0, u1 = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const CT b2 = tabB<CT>(tb, q * NI + k), g2 = tabG<CT>(tb, q * NI + k);
+                u0 += b2 * t0[q];
+                u1 += g2 * t1[q] + b2 * t2[q];
+            }
+            o[k * NQ] = u0;       // G along axis 1 still to apply
+            o[L1 + k * NQ] = u1;  // B along axis 1 still to apply
+        }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nel * 3 * S::NP; idx += BLOCK) {
-        const int i1 = idx % NI;
-        int r = idx / NI;
-        const int i2 = r % NI;
-        r /= NI;
-        const int i3 = r % NI;
-        r /= NI;
+    // axis 1: pencils (r, i3, i2) -> NI consecutive outputs
+    for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
+        const int i2 = pen % NI, i3 = (pen / NI) % NI, r = pen / (NI * NI);
+        const int c = r % 3, el = r / 3;
         const CT *t = R1 + r * 2 * L1 + (i3 * NI + i2) * NQ;
-        CT s = 0;
+        CT u0[NQ], u1[NQ];
 #pragma unroll
-        for (int q1 = 0; q1 < NQ; ++q1) s += sG[q1 * NI + i1] * t[q1] + sB[q1 * NI + i1] * t[L1 + q1];
-        out[idx] = (OT)s;
+        for (int q = 0; q < NQ; ++q) {
+            u0[q] = t[q];
+            u1[q] = t[L1 + q];
+        }
+        OT *o = out + ev_index3<P>(g, e0 + el, c, 0, i2, i3);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT s = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                s += tabG<CT>(tb, q * NI + k) * u0[q] + tabB<CT>(tb, q * NI + k) * u1[q];
+            o[k] = (OT)s;
+        }
     }
+}
+
+// J[c*3+b] = d x_c / d xbar_b at point q of element el, left in RY by forward3.
+template <int P, int NQ, typename CT>
+__device__ inline void point_J3(const CT *RY, int el, int q, CT *J)
+{
+    constexpr int NQ3 = S3<P, NQ>::NQ3;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) J[k] = RY[(el * 9 + k) * NQ3 + q];
+}
+
+template <int NQ>
+__device__ inline double point_weight3(const Tables &tb, const Target &tg, int q)
+{
+    const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / (NQ * NQ);
+    return tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
 }
 
 // ------------------------------------------------------------------------
-// Kernels
+// Element bodies
 // ------------------------------------------------------------------------
 
 // Energy and minimum det A: per-block partial sums of z mu and minima of det A,
 // count of points with det T <= 0 (Sec. 3.3, eq. D0_expression; Sec. 2.3).
 template <int P, int NQ>
-__device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ part, int e0, int nel)
+__device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &tg,
+                                 const double *__restrict__ x, double *__restrict__ part, int e0,
+                                 int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double esum = 0.0, dmin = 1.0e300, bad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
         double J[9];
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
-        const double dA = det_only<3>(J);
-        dmin = fmin(dmin, dA);
-        const double z = tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+        point_J3<P, NQ>(L.RY, el, q, J);
+        dmin = fmin(dmin, det_only<3>(J));
+        const double z = point_weight3<NQ>(tb, tg, q);
         double mu, Pm[9];
         if (metric_first<3>(tg, J, z, &mu, Pm))
             esum += z * mu;
@@ -276,22 +338,22 @@ __device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &
 // Gradient E-vector (Sec. 3.3, eq. eq_vm_pa_grad): per point z P, then the
 // transposed contractions.  bad[blockIdx] counts points with det T <= 0.
 template <int P, int NQ>
-__device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad, int e0, int nel)
+__device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
+                                   const double *__restrict__ x, double *__restrict__ gE,
+                                   double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
         double J[9], Pm[9], mu;
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
-        const double z = tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+        point_J3<P, NQ>(L.RY, el, q, J);
+        const double z = point_weight3<NQ>(tb, tg, q);
         if (!metric_first<3>(tg, J, z, &mu, Pm)) {
             nbad += 1.0;
 #pragma unroll
@@ -301,7 +363,7 @@ __device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target
         for (int k = 0; k < 9; ++k) L.RY[(el * 9 + k) * S::NQ3 + q] = Pm[k];
     }
     __syncthreads();
-    backward3<P, NQ>(L.B, L.G, L.RY, L.R2, L.R1, nel, gE + (size_t)e0 * 3 * S::NP);
+    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, gE);
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
@@ -309,22 +371,22 @@ __device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
 // element-major [e][45][NQ^3] so that each entry is one coalesced plane.
 template <int P, int NQ, typename TT>
-__device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad, int e0, int nel)
+__device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &tg,
+                                const double *__restrict__ x, TT *__restrict__ H,
+                                double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
         double J[9], Hp[45];
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
-        const double z = tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+        point_J3<P, NQ>(L.RY, el, q, J);
+        const double z = point_weight3<NQ>(tb, tg, q);
         if (!metric_second<3>(tg, J, z, Hp)) {
             nbad += 1.0;
 #pragma unroll
@@ -341,27 +403,38 @@ __device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &t
 // Hessian action, element part (Sec. 3.4, eq. eq_vm_pa_hess):
 //   grad v at the points (forward contractions of P v),
 //   Y_an = sum_bp H[an,bp] (grad v)_bp  with the stored tensor,
-//   transposed contractions -> E-vector yE[e][c][i].
+//   transposed contractions -> E-vector.
 // CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
 // accumulation).
 template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+__device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+                                const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ>;
+    // at most one quadrature point per lane: its tensor is loaded before the
+    // sweeps and stays in flight behind them (barriers wait on LDS only)
+    constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;
     __shared__ Lds3<P, NQ, CT> L;
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, v, e0, nel, L.X, true);
-    __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
-    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
-        const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
+    const int npts = nel * S::NQ3;
+    CT hv[45];
+    if (ONE && threadIdx.x < npts) {
+        const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
         const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
-        CT hv[45];
 #pragma unroll
         for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
+    }
+    __syncthreads();
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        if (!ONE) {
+            const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
+#pragma unroll
+            for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
+        }
         CT J[9];
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
+        point_J3<P, NQ>(L.RY, el, q, J);
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
             CT s = 0;
@@ -371,7 +444,7 @@ __device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__res
         }
     }
     __syncthreads();
-    backward3<P, NQ>(L.B, L.G, L.RY, L.R2, L.R1, nel, yE + (size_t)e0 * 3 * S::NP);
+    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
 }
 
 // ------------------------------------------------------------------------
@@ -437,24 +510,24 @@ __device__ inline void mul_winv(const Target &t, const CT *in, CT *out, bool tr)
 }
 
 template <int P, int NQ, typename TT>
-__device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad, int e0, int nel)
+__device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
+                                 const double *__restrict__ x, TT *__restrict__ Q,
+                                 double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
         double J[9], T[9], C[9], out[NC3];
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
+        point_J3<P, NQ>(L.RY, el, q, J);
         apply_winv<3>(tg, J, T);
         const double tau = det_cof<3>(T, C);
-        const double z = tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+        const double z = point_weight3<NQ>(tb, tg, q);
         if (tau > 0.0) {
             double I1 = 0.0;
 #pragma unroll
@@ -480,23 +553,33 @@ __device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &
 }
 
 template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+__device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
+                                 const TT *__restrict__ Q, const double *__restrict__ v,
+                                 CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ>;
+    constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;  // as in b3_apply
     __shared__ Lds3<P, NQ, CT> L;
-    load_tables3<P, NQ>(tb, L.B, L.G);
     gather3<P, NQ>(g, v, e0, nel, L.X, true);
-    __syncthreads();
-    forward12<P, NQ>(L.B, L.G, L.X, L.R1, L.R2, nel);
-    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
-        const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / S::NQ2;
+    const int npts = nel * S::NQ3;
+    CT d[NC3];
+    if (ONE && threadIdx.x < npts) {
+        const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
         const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
-        CT d[NC3];
 #pragma unroll
         for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
+    }
+    __syncthreads();
+    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        if (!ONE) {
+            const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+#pragma unroll
+            for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
+        }
         CT J[9], Y[9];
-        point_grad3<P, NQ>(L.B, L.G, L.R2, el, q1, q2, q3, J);
+        point_J3<P, NQ>(L.RY, el, q, J);
         if (tg.ideal) {
             compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
         } else {
@@ -509,7 +592,7 @@ __device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &
         for (int r = 0; r < 9; ++r) L.RY[(el * 9 + r) * S::NQ3 + q] = Y[r];
     }
     __syncthreads();
-    backward3<P, NQ>(L.B, L.G, L.RY, L.R2, L.R1, nel, yE + (size_t)e0 * 3 * S::NP);
+    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
 }
 
 // Hessian diagonal, element part (Sec. 3.4, last paragraph):
@@ -531,8 +614,8 @@ __device__ constexpr int diag_pn(int pr) { return pr < 3 ? 0 : (pr < 5 ? 1 : 2);
 __device__ constexpr int diag_pp(int pr) { return pr < 3 ? pr : (pr < 5 ? pr - 2 : 2); }
 
 template <int P, int NQ>
-__device__ inline void diag_contract3(const Tables &tb, DiagLds3<P, NQ> &L, int nel,
-                                      double *__restrict__ dE)
+__device__ inline void diag_contract3(const Tables &tb, const Geom &g, int e0, DiagLds3<P, NQ> &L,
+                                      int nel, double *__restrict__ dE)
 {
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NQ3 = S::NQ3, NP = S::NP;
@@ -588,7 +671,10 @@ __device__ inline void diag_contract3(const Tables &tb, DiagLds3<P, NQ> &L, int 
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) dE[k] = L.sD[k];
+    for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) {
+        const int i = k % NP, r = k / NP;
+        dE[ev_index3<P>(g, e0 + r / 3, r % 3, i % NI, (i / NI) % NI, i / (NI * NI))] = L.sD[k];
+    }
 }
 
 template <int P, int NQ, typename TT>
@@ -609,7 +695,7 @@ __device__ inline void b3_diag(const Geom &g, const Tables &tb, const TT *__rest
                     f * (double)h[sym_index<9>(a * 3 + n, a * 3 + p) * S::NQ3];
         }
     }
-    diag_contract3<P, NQ>(tb, L, nel, dE + (size_t)e0 * 3 * S::NP);
+    diag_contract3<P, NQ>(tb, g, e0, L, nel, dE);
 }
 
 // Diagonal from compact data: within one component a the cofactor-derivative
@@ -661,8 +747,9 @@ __device__ inline void b3_diagc(const Geom &g, const Tables &tb, const Target &t
             }
         }
     }
-    diag_contract3<P, NQ>(tb, L, nel, dE + (size_t)e0 * 3 * S::NP);
+    diag_contract3<P, NQ>(tb, g, e0, L, nel, dE);
 }
+
 
 // ------------------------------------------------------------------------
 // Kernel entry points: single mesh (grid over element blocks) and batched

@@ -30,11 +30,29 @@ struct Geom {
 };
 
 // 1D tables: B[q][i] = l_i(chi_q), G[q][i] = l_i'(chi_q), w[q] (Sec. 3.1, eq. eq_B_G_1D).
+// Bf, Gf: the same tables rounded to FP32 for the mixed-precision action.
+// Kernels take Tables by value, so the entries they index with compile-time
+// constants are read from the kernel arguments into scalar registers.
 struct Tables {
     double B[MAXNQ * MAXNI];
     double G[MAXNQ * MAXNI];
     double w[MAXNQ];
+    float Bf[MAXNQ * MAXNI];
+    float Gf[MAXNQ * MAXNI];
 };
+
+template <typename CT>
+__device__ inline CT tabB(const Tables &t, int k);
+template <>
+__device__ inline double tabB<double>(const Tables &t, int k) { return t.B[k]; }
+template <>
+__device__ inline float tabB<float>(const Tables &t, int k) { return t.Bf[k]; }
+template <typename CT>
+__device__ inline CT tabG(const Tables &t, int k);
+template <>
+__device__ inline double tabG<double>(const Tables &t, int k) { return t.G[k]; }
+template <>
+__device__ inline float tabG<float>(const Tables &t, int k) { return t.Gf[k]; }
 
 // Constant target: W^{-1} (row-major) and det W; ideal != 0 means W = I.
 struct Target {
@@ -305,7 +323,16 @@ __device__ inline bool metric_second(const Target &t, const double *A, double z,
         return true;
     }
     // general constant W: each entry H_A[an][bp] = sum_kl d2mu[ak][bl] Winv_nk Winv_pl,
-    // with d2mu evaluated entry by entry (keeps register use low)
+    // with d2mu evaluated entry by entry (keeps register use low).  The loops
+    // index at run time, so they work on copies (Tg, Cg, Hg): the arrays of
+    // the ideal-target path above then stay in registers.
+    constexpr int NS = D2 * (D2 + 1) / 2;
+    double Tg[D2], Cg[D2], Hg[NS];
+#pragma unroll
+    for (int k = 0; k < D2; ++k) {
+        Tg[k] = T[k];
+        Cg[k] = C[k];
+    }
     for (int r = 0; r < D2; ++r)
         for (int s = r; s < D2; ++s) {
             const int a = r / D, n = r % D, b = s / D, p = s % D;
@@ -313,13 +340,15 @@ __device__ inline bool metric_second(const Target &t, const double *A, double z,
             for (int k = 0; k < D; ++k)
                 for (int l = 0; l < D; ++l) {
                     const int rr = a * D + k, ss = b * D + l;
-                    double v = m.c_tc * (T[rr] * C[ss] + C[rr] * T[ss]) + m.c_cc * C[rr] * C[ss] +
-                               m.c_dc * dcof<D>(T, rr, ss);
+                    double v = m.c_tc * (Tg[rr] * Cg[ss] + Cg[rr] * Tg[ss]) +
+                               m.c_cc * Cg[rr] * Cg[ss] + m.c_dc * dcof<D>(Tg, rr, ss);
                     if (rr == ss) v += m.c_id;
                     acc += v * t.Winv[n * D + k] * t.Winv[p * D + l];
                 }
-            Hp[sym_index<D2>(r, s)] = z * acc;
+            Hg[sym_index<D2>(r, s)] = z * acc;
         }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Hp[k] = Hg[k];
     return true;
 }
 

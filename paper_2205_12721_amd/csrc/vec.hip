@@ -19,9 +19,8 @@ __global__ __launch_bounds__(VBLOCK) void k_gather(Geom g, const int32_t *__rest
                                                    double *__restrict__ out, int fix_mode,
                                                    const double *__restrict__ src)
 {
-    const long total = (long)DIM * g.nx;
-    for (long idx = blockIdx.x * (long)VBLOCK + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * VBLOCK) {
+    const int total = DIM * g.nx;
+    for (int idx = blockIdx.x * VBLOCK + threadIdx.x; idx < total; idx += gridDim.x * VBLOCK) {
         bool fixed;
         const double v = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
         out[idx] = fixed ? (fix_mode == 0 ? 0.0 : (fix_mode == 1 ? 1.0 : src[idx])) : v;
@@ -304,10 +303,9 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_l1(Geom g, const int32_t *
     if (j > st->stop) return;
     __shared__ double red[VBLOCK / 64];
     const double cr = j >= 1 ? st->beta / st->oldb : 0.0;
-    const long total = (long)DIM * g.nx;
+    const int total = DIM * g.nx;
     double s = 0.0;
-    for (long idx = blockIdx.x * (long)VBLOCK + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * VBLOCK) {
+    for (int idx = blockIdx.x * VBLOCK + threadIdx.x; idx < total; idx += gridDim.x * VBLOCK) {
         bool fixed;
         const double a = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
         const double vi = v[idx];
