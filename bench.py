@@ -107,7 +107,7 @@ def cpu_baseline(cfg, x, v, seconds):
     import oracle
     _, dim, n, p, nq = cfg
     pb = oracle.Problem.box(dim, n, p, nq)
-    pb.hvp(x, v)  # warm up
+    y = pb.hvp(x, v)  # warm up; the action is kept for the precision leg
     reps, t0 = 0, time.perf_counter()
     while True:
         pb.hvp(x, v)
@@ -122,7 +122,49 @@ def cpu_baseline(cfg, x, v, seconds):
         "kind": "oracle",
         "sample": "%d Hessian actions of the FP64 oracle (direct, not sum-factorized) on the "
                   "same mesh and vector, %.1f s" % (reps, el),
-    }
+    }, y
+
+
+def precision_leg(cfg, x0, v_host, y_oracle, max_newton=100):
+    """Error of each Hessian-action variant against the FP64 oracle's action (same mesh
+    and vector), and FP64 vs mixed full solves to |g|/|g0| <= 1e-8 on the same mesh:
+    time, Newton/MINRES counts and the relative final-energy difference."""
+    import numpy as np
+    import torch
+    from paper_2205_12721_amd.tmop import Context
+    _, dim, n, p, nq = cfg
+    v = torch.as_tensor(v_host).cuda()
+    yo = np.asarray(y_oracle)
+    out = {"hvp_rel_err_vs_oracle": {}}
+    for storage in ("tensor", "compact"):
+        for prec in ("fp64", "mixed"):
+            c = Context(dim, n, p, nq, precision=prec, storage=storage)
+            c.hessian_setup(x0)
+            y = c.hessian_apply(v).cpu().numpy()
+            c.close()
+            out["hvp_rel_err_vs_oracle"]["%s_%s" % (storage, prec)] = float(
+                np.linalg.norm(y - yo) / np.linalg.norm(yo))
+    sol = {}
+    for storage, prec in (("tensor", "fp64"), ("compact", "fp64"), ("compact", "mixed")):
+        c = Context(dim, n, p, nq, precision=prec, storage=storage)
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = c.solve(x, rel_grad_tol=1e-8, max_newton=max_newton)
+        torch.cuda.synchronize()
+        sol["%s_%s" % (storage, prec)] = {
+            "seconds": round(time.perf_counter() - t0, 4), "status": rep["status_name"],
+            "newton_its": rep["newton_its"], "minres_its": rep["minres_its_total"],
+            "F0": rep["F0"], "F": rep["F"], "x": x}
+        c.close()
+    ref = sol["tensor_fp64"]
+    for k, r in sol.items():
+        r["rel_final_energy_diff_vs_tensor_fp64"] = abs(r["F"] - ref["F"]) / abs(ref["F"])
+        r["rel_node_diff_vs_tensor_fp64"] = float((r["x"] - ref["x"]).norm() / ref["x"].norm())
+    for r in sol.values():
+        del r["x"]
+    out["solve_to_1e-8"] = sol
+    return out
 
 
 def batch_leg(count):
@@ -231,6 +273,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256)
@@ -351,8 +394,11 @@ def main():
 
     if not args.no_cpu_baseline:
         v = inputs.gaussian_vector(ctx.ndof, inputs.CONFIGS[cname]["vec_seed"])
-        out["cpu_baseline"] = cpu_baseline(cfg, xh, v, args.cpu_seconds)
+        out["cpu_baseline"], y_oracle = cpu_baseline(cfg, xh, v, args.cpu_seconds)
         log("[bench] cpu baseline done")
+        if not args.no_precision:
+            out["precision"] = precision_leg(cfg, x0, v, y_oracle)
+            log("[bench] precision leg done")
 
     ctx.close()
     print(json.dumps(out), flush=True)

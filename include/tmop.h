@@ -8,8 +8,10 @@
  *
  *   Mesh nodes           x (Sec. 2.1, eq. eq_x): a global vector of d x N_x
  *                        coordinates, the element map x = sum_i x_{E,i} w_i.
- *   Target / metric      T = A W^{-1} (Sec. 2.2, eqs. eq_A, eq_T); mu_2 for
- *                        quads, mu_303 for hexes (Sec. 2.2, Sec. 4.1).
+ *   Target / metric      T = A W^{-1} (Sec. 2.2, eqs. eq_A, eq_T); shape
+ *                        metrics mu_2 (quads) and mu_303 (hexes), size metric
+ *                        mu_55, shape+size metrics mu_7 and mu_9 (quads)
+ *                        (Sec. 2.2, Sec. 4.1).
  *   Objective            F(x) = sum_E int mu(T) (Sec. 2.2, eq. eq_F_full, first
  *                        term, spatial weight 1; Sec. 3.3, eq. D0_expression).
  *   Gradient             Sec. 3.3, eq. eq_vm_pa_grad.
@@ -90,7 +92,10 @@ typedef struct {
 
 /* Discretisation, target and precision. */
 typedef struct {
-    int metric;     /* 2 (mu_2, dim 2) or 303 (mu_303, dim 3) */
+    int metric;     /* dim 2: 2 (mu_2 = |T|^2/(2 tau) - 1), 7 (mu_7 = |T - T^{-t}|^2),
+                       9 (mu_9 = tau mu_7) or 55 (mu_55 = (tau - 1)^2);
+                       dim 3: 303 (mu_303 = |T|^2/(3 tau^{2/3}) - 1) or 55.
+                       Others: TMOP_ERR_UNSUPPORTED */
     int nq1d;       /* quadrature points per direction, p+1 .. p+3 */
     int has_W;      /* 0: ideal target W = I; 1: use the constant W below */
     double W[9];    /* constant target matrix, row-major dim x dim, det > 0 */

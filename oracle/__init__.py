@@ -50,6 +50,10 @@ class _Problem(ctypes.Structure):
         ("dphi", ctypes.POINTER(ctypes.c_double)),
         ("Winv", ctypes.c_double * 9),
         ("detW", ctypes.c_double),
+        ("phi", ctypes.POINTER(ctypes.c_double)),
+        ("x0", ctypes.POINTER(ctypes.c_double)),
+        ("lim_coef", ctypes.c_double),
+        ("lim_delta", ctypes.c_double),
     ]
 
 
@@ -123,8 +127,9 @@ class Problem:
         self.ne, self.npe = self.e2n.shape
         self.nx = int(nx)
         self.ndof = dim * self.nx
-        self.wq, dphi = _dense_tables(dim, p, nq1d)
+        self.wq, dphi, phi = _dense_tables(dim, p, nq1d)
         self.dphi = np.ascontiguousarray(dphi)
+        self.phi = np.ascontiguousarray(phi)
         self.nqe = len(self.wq)
         self.W = np.eye(dim) if W is None else np.asarray(W, dtype=np.float64).reshape(dim, dim)
         Winv = np.linalg.inv(self.W)
@@ -143,9 +148,29 @@ class Problem:
         for k in range(9):
             self._pb.Winv[k] = wi[k]
         self._pb.detW = float(np.linalg.det(self.W))
+        self._pb.phi = _dp(self.phi)
+        self.lim_x0 = None
+        self._pb.x0 = None
+        self._pb.lim_coef = 0.0
+        self._pb.lim_delta = 1.0
         self.ess = None if ess is None else np.asarray(ess, dtype=bool).ravel()
         if self.npe != (p + 1) ** dim:
             raise ValueError("e2n width does not match (p+1)^dim")
+
+    def set_limiting(self, x0, coef=1.0, delta=1.0):
+        """Add the limiting term coef * sum_E int |x - x0|^2 / delta^2 of eq.
+        eq_F_full (xi(y, delta) = |y|^2 / delta^2); x0=None removes it."""
+        if x0 is None:
+            self.lim_x0 = None
+            self._pb.x0 = None
+            self._pb.lim_coef = 0.0
+            return
+        if not delta > 0:
+            raise ValueError("delta must be positive")
+        self.lim_x0 = np.array(self._x(x0), dtype=np.float64, copy=True)
+        self._pb.x0 = _dp(self.lim_x0)
+        self._pb.lim_coef = float(coef)
+        self._pb.lim_delta = float(delta)
 
     @classmethod
     def box(cls, dim, n, p, nq1d, metric_id=None, W=None, constrain="boundary"):
@@ -252,9 +277,10 @@ class Problem:
 @functools.lru_cache(maxsize=32)
 def _dense_tables(dim, p, nq1d):
     wq, dphi = basis.dense_tables(dim, p, nq1d)
-    wq.setflags(write=False)
-    dphi.setflags(write=False)
-    return wq, dphi
+    phi = basis.dense_values(dim, p, nq1d)
+    for a in (wq, dphi, phi):
+        a.setflags(write=False)
+    return wq, dphi, phi
 
 
 from .solver import minres, newton_solve  # noqa: E402,F401
@@ -271,4 +297,6 @@ def restrict_to_nodes(pb, nodes):
     keep = np.isin(pb.e2n, nodes).any(axis=1)
     sub = Problem(pb.dim, pb.p, pb.nq1d, pb.e2n[keep], pb.nx, metric_id=pb.metric, W=pb.W,
                   ess=pb.ess)
+    if pb.lim_x0 is not None:
+        sub.set_limiting(pb.lim_x0, pb._pb.lim_coef, pb._pb.lim_delta)
     return sub

@@ -107,3 +107,20 @@ def dense_tables(dim, p, nq):
                     val *= (G if k == b else B)[qs[k], iis[k]]
                 dphi[b, q, i] = val
     return wq, dphi
+
+
+def dense_values(dim, p, nq):
+    """phi[q, i] = wbar_i(xbar_q) (N_q x N_p), same orderings as dense_tables."""
+    ni = p + 1
+    chi, _ = gl_rule(nq)
+    B, _ = lagrange(gll_nodes(p), chi)
+    NQ = nq ** dim
+    NP = ni ** dim
+    phi = np.ones((NQ, NP))
+    for q in range(NQ):
+        qs = [(q // nq ** k) % nq for k in range(dim)]
+        for i in range(NP):
+            iis = [(i // ni ** k) % ni for k in range(dim)]
+            for k in range(dim):
+                phi[q, i] *= B[qs[k], iis[k]]
+    return phi

@@ -61,6 +61,12 @@ typedef struct {
     const double *dphi; /* dim*nq*np: d wbar_i/d xbar_b at chi_q, index [b][q][i] */
     double Winv[9];     /* constant target inverse W^{-1}, row-major dim x dim */
     double detW;        /* det W */
+    /* Limiting term of eq. eq_F_full, xi(y, delta) = |y|^2 / delta^2 with
+     * y = x - x0 at the point, weighted by lim_coef; off when x0 is NULL. */
+    const double *phi;  /* nq*np: wbar_i(chi_q), index [q][i] */
+    const double *x0;   /* dim*nx reference node positions, or NULL */
+    double lim_coef;    /* weight of the limiting integral */
+    double lim_delta;   /* limiting distance delta (> 0) */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -154,7 +160,9 @@ int oracle_metric(int dim, int metric, const double *T, double *mu, double *dmu,
                   double *d2mu)
 {
     int d = dim, d2 = dim * dim;
-    if (!((dim == 2 && metric == 2) || (dim == 3 && metric == 303))) return -1;
+    int known = (dim == 2 && (metric == 2 || metric == 7 || metric == 9 || metric == 55)) ||
+                (dim == 3 && (metric == 303 || metric == 55));
+    if (!known) return -1;
     double tau = det_mat(d, T);
     if (!(tau > 0.0)) return 0;
     double I1 = 0.0;
@@ -162,6 +170,10 @@ int oracle_metric(int dim, int metric, const double *T, double *mu, double *dmu,
     double C[9];
     cofactor(d, T, C);
 
+    /* Every metric here is f(I1, tau), linear in I1, so that
+     *   dmu    = 2 f_1 T + f_tau C,
+     *   d2mu   = 2 f_1 Id + 2 f_1tau (T x C + C x T) + f_tautau C x C + f_tau dC/dT
+     * (no T x T term since f_11 = 0). */
     double c_id, c_tc, c_cc, c_dc; /* coefficients of Id, (TxC+CxT), CxC, dC/dT */
     double c_T, c_C;               /* coefficients of T and C in dmu */
     if (metric == 2) {
@@ -172,7 +184,7 @@ int oracle_metric(int dim, int metric, const double *T, double *mu, double *dmu,
         c_tc = -1.0 / (tau * tau);
         c_cc = I1 / (tau * tau * tau);
         c_dc = -I1 / (2.0 * tau * tau);
-    } else {
+    } else if (metric == 303) {
         double t13 = cbrt(tau);     /* tau^{1/3} */
         double t23 = t13 * t13;     /* tau^{2/3} */
         double t53 = tau * t23;     /* tau^{5/3} */
@@ -184,6 +196,43 @@ int oracle_metric(int dim, int metric, const double *T, double *mu, double *dmu,
         c_tc = -4.0 / (9.0 * t53);
         c_cc = 10.0 * I1 / (27.0 * t83);
         c_dc = -2.0 * I1 / (9.0 * t53);
+    } else if (metric == 55) {
+        /* mu_55 = (tau - 1)^2: f_1 = 0, f_tau = 2 (tau - 1), f_tautau = 2 */
+        *mu = (tau - 1.0) * (tau - 1.0);
+        c_T = 0.0;
+        c_C = 2.0 * (tau - 1.0);
+        c_id = 0.0;
+        c_tc = 0.0;
+        c_cc = 2.0;
+        c_dc = 2.0 * (tau - 1.0);
+    } else {
+        /* mu_7 = |T - T^{-t}|^2 and mu_9 = tau |T - T^{-t}|^2 (2D), evaluated from
+         * the definition with T^{-t} = C / tau.  In 2D |C| = |T| and T : C = 2 tau,
+         * so mu_7 = I1 (1 + tau^-2) - 4 and mu_9 = I1 (tau + 1/tau) - 4 tau give the
+         * derivative coefficients. */
+        double m7 = 0.0;
+        for (int k = 0; k < d2; k++) {
+            double e = T[k] - C[k] / tau;
+            m7 += e * e;
+        }
+        double it = 1.0 / tau, it2 = it * it, it3 = it2 * it;
+        if (metric == 7) {
+            *mu = m7;
+            c_T = 2.0 * (1.0 + it2);       /* 2 f_1 */
+            c_C = -2.0 * I1 * it3;         /* f_tau */
+            c_id = 2.0 * (1.0 + it2);
+            c_tc = -4.0 * it3;             /* 2 f_1tau */
+            c_cc = 6.0 * I1 * it2 * it2;   /* f_tautau */
+            c_dc = -2.0 * I1 * it3;
+        } else {
+            *mu = tau * m7;
+            c_T = 2.0 * (tau + it);
+            c_C = I1 * (1.0 - it2) - 4.0;
+            c_id = 2.0 * (tau + it);
+            c_tc = 2.0 * (1.0 - it2);
+            c_cc = 2.0 * I1 * it3;
+            c_dc = I1 * (1.0 - it2) - 4.0;
+        }
     }
     if (dmu)
         for (int k = 0; k < d2; k++) dmu[k] = c_T * T[k] + c_C * C[k];
@@ -225,6 +274,26 @@ static void gather_elem(const oracle_problem *pb, const double *x, int e, double
     const int32_t *map = pb->e2n + (size_t)e * np;
     for (int a = 0; a < d; a++)
         for (int i = 0; i < np; i++) xE[a * np + i] = x[(size_t)a * pb->nx + map[i]];
+}
+
+/* u_a = sum_i uE[a][i] wbar_i(chi_q): the FE function of element values uE at q. */
+static void value_at(const oracle_problem *pb, const double *uE, int q, double *u)
+{
+    int d = pb->dim, np = pb->np;
+    const double *ph = pb->phi + (size_t)q * np;
+    for (int a = 0; a < d; a++) {
+        double s = 0.0;
+        for (int i = 0; i < np; i++) s += uE[a * np + i] * ph[i];
+        u[a] = s;
+    }
+}
+
+/* lim_coef / delta^2: the limiting integrand is this times |x - x0|^2; its
+ * gradient with respect to x(q) is twice this times (x - x0), and its second
+ * derivative twice this times the identity. */
+static double lim_scale(const oracle_problem *pb)
+{
+    return pb->x0 ? pb->lim_coef / (pb->lim_delta * pb->lim_delta) : 0.0;
 }
 
 static void t_from_a(const oracle_problem *pb, const double *A, double *T)
@@ -291,8 +360,10 @@ static void elem_energies(const oracle_problem *pb, const double *x, double *eE,
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int e = 0; e < pb->ne; e++) {
-        double xE[3 * 729], A[9], T[9], mu;
+        double xE[3 * 729], x0E[3 * 729], A[9], T[9], mu, u[3], u0[3];
+        double ls = lim_scale(pb);
         gather_elem(pb, x, e, xE);
+        if (ls != 0.0) gather_elem(pb, pb->x0, e, x0E);
         double s = 0.0;
         for (int q = 0; q < pb->nq; q++) {
             jacobian_at(pb, xE, q, A);
@@ -302,6 +373,13 @@ static void elem_energies(const oracle_problem *pb, const double *x, double *eE,
                 continue;
             }
             s += pb->wq[q] * pb->detW * mu;
+            if (ls != 0.0) {
+                value_at(pb, xE, q, u);
+                value_at(pb, x0E, q, u0);
+                double y2 = 0.0;
+                for (int a = 0; a < pb->dim; a++) y2 += (u[a] - u0[a]) * (u[a] - u0[a]);
+                s += pb->wq[q] * pb->detW * ls * y2;
+            }
         }
         eE[e] = s;
     }
@@ -329,9 +407,11 @@ int oracle_gradient(const oracle_problem *pb, const double *x, double *g)
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int e = 0; e < pb->ne; e++) {
-        double xE[3 * 729], A[9], T[9], mu, dmu[9], PA[9];
+        double xE[3 * 729], x0E[3 * 729], A[9], T[9], mu, dmu[9], PA[9], u[3], u0[3];
         double *ee = ev + (size_t)e * d * np;
+        double ls = lim_scale(pb);
         gather_elem(pb, x, e, xE);
+        if (ls != 0.0) gather_elem(pb, pb->x0, e, x0E);
         for (int q = 0; q < nq; q++) {
             jacobian_at(pb, xE, q, A);
             t_from_a(pb, A, T);
@@ -354,6 +434,14 @@ int oracle_gradient(const oracle_problem *pb, const double *x, double *g)
                         s += PA[a * d + n] * pb->dphi[((size_t)n * nq + q) * np + i];
                     ee[a * np + i] += z * s;
                 }
+            if (ls != 0.0) {
+                /* d/dx_{a,i} of z ls |x(q) - x0(q)|^2 = 2 z ls (x - x0)_a(q) wbar_i(q) */
+                value_at(pb, xE, q, u);
+                value_at(pb, x0E, q, u0);
+                for (int a = 0; a < d; a++)
+                    for (int i = 0; i < np; i++)
+                        ee[a * np + i] += 2.0 * z * ls * (u[a] - u0[a]) * pb->phi[(size_t)q * np + i];
+            }
         }
         (void)d2;
     }
@@ -393,6 +481,7 @@ int oracle_hessian_apply(const oracle_problem *pb, const double *x, const double
     for (int e = 0; e < pb->ne; e++) {
         double xE[3 * 729], vE[3 * 729], A[9], GV[9], HA[81], Y[9];
         double *ee = ev + (size_t)e * d * np;
+        double ls = lim_scale(pb);
         gather_elem(pb, x, e, xE);
         gather_elem(pb, v, e, vE);
         for (int q = 0; q < nq; q++) {
@@ -415,6 +504,14 @@ int oracle_hessian_apply(const oracle_problem *pb, const double *x, const double
                         s += Y[a * d + n] * pb->dphi[((size_t)n * nq + q) * np + i];
                     ee[a * np + i] += z * s;
                 }
+            if (ls != 0.0) {
+                /* limiting: the mass-like term 2 z ls v_a(q) wbar_i(q) (eq. eq_pa_limiting) */
+                double vq[3];
+                value_at(pb, vE, q, vq);
+                for (int a = 0; a < d; a++)
+                    for (int i = 0; i < np; i++)
+                        ee[a * np + i] += 2.0 * z * ls * vq[a] * pb->phi[(size_t)q * np + i];
+            }
         }
     }
     scatter_add(pb, ev, y);
@@ -448,7 +545,8 @@ int oracle_hessian_diag(const oracle_problem *pb, const double *x, double *dg)
                             s += HA[(a * d + n) * d2 + (a * d + p)] *
                                  pb->dphi[((size_t)n * nq + q) * np + i] *
                                  pb->dphi[((size_t)p * nq + q) * np + i];
-                    ee[a * np + i] += z * s;
+                    double ph = pb->phi[(size_t)q * np + i];
+                    ee[a * np + i] += z * (s + 2.0 * lim_scale(pb) * ph * ph);
                 }
         }
     }
@@ -483,6 +581,9 @@ int oracle_element_hessian(const oracle_problem *pb, const double *x, int e, dou
                                 s += HA[(a * d + nn) * d2 + (b * d + p)] *
                                      pb->dphi[((size_t)nn * nq + q) * np + i] *
                                      pb->dphi[((size_t)p * nq + q) * np + j];
+                        if (a == b) /* limiting: mass-like block (eq. eq_pa_limiting) */
+                            s += 2.0 * lim_scale(pb) * pb->phi[(size_t)q * np + i] *
+                                 pb->phi[(size_t)q * np + j];
                         H[(size_t)(a * np + i) * n + (b * np + j)] += z * s;
                     }
     }

@@ -521,8 +521,8 @@ static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH 
         why = "dim must be 2 or 3";
         return TMOP_ERR_INVALID_ARG;
     }
-    if (!((m->dim == 2 && prm->metric == 2) || (m->dim == 3 && prm->metric == 303))) {
-        why = "metric must be 2 (dim 2) or 303 (dim 3)";
+    if (!metric_supported(m->dim, prm->metric)) {
+        why = "metric must be 2, 7, 9 or 55 (dim 2) or 303 or 55 (dim 3)";
         return TMOP_ERR_UNSUPPORTED;
     }
     if (m->ess_mode == TMOP_ESS_MASK && !m->ess_mask) {

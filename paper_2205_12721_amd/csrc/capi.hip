@@ -330,8 +330,8 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     int nqe, np;
     CHK(ctx_sizes(m, prm, ne, nx, nqe, np));
     const int d = m->dim, p = m->order_p, nq = prm->nq1d;
-    if (!((d == 2 && prm->metric == 2) || (d == 3 && prm->metric == 303)))
-        return fail(TMOP_ERR_UNSUPPORTED, "metric must be 2 (dim 2) or 303 (dim 3)");
+    if (!metric_supported(d, prm->metric))
+        return fail(TMOP_ERR_UNSUPPORTED, "metric must be 2, 7, 9 or 55 (dim 2) or 303 or 55 (dim 3)");
     if (prm->precision != TMOP_FP64 && prm->precision != TMOP_MIXED)
         return fail(TMOP_ERR_INVALID_ARG, "precision must be TMOP_FP64 or TMOP_MIXED");
     if (prm->hess_storage != TMOP_HESS_TENSOR && prm->hess_storage != TMOP_HESS_COMPACT)

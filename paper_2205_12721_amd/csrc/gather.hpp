@@ -36,26 +36,32 @@ __device__ inline ET gather_box_node(const Geom &g, const ET *__restrict__ eV, i
     }
     const int EX = g.nel[0] * ni;
     const ET *base = eV + (size_t)c * g.ne * np;
-    // every load is issued unconditionally (a missing copy reads entry 0 and
-    // is then dropped), so they are all in flight together; the sum runs in
-    // a fixed order
-    constexpr int NC = DIM == 3 ? 8 : 4;
-    ET val[NC];
+    // Rows (y, z copies) that do not exist are skipped; the test is uniform
+    // along a row of nodes, so it rarely diverges within a wave.  Within a
+    // row both x copies are loaded (a missing one reads the row's first entry
+    // and is dropped afterwards).  No loaded value is used before the last
+    // load is issued, so all are in flight together; the sum runs in a fixed
+    // order.
+    constexpr int NR = DIM == 3 ? 4 : 2;
+    ET lo[NR], hi[NR];
+    bool rok[NR];
 #pragma unroll
-    for (int t = 0; t < NC; ++t) {
-        const int d = t & 1, b = (t >> 1) & 1, a = t >> 2;
-        bool ok = has[0][d] && has[1][b];
-        int off = pos[1][b] * EX + pos[0][d];
-        if (DIM == 3) {
-            ok = ok && has[2][a];
-            off += pos[2][a] * (g.nel[1] * ni) * EX;
+    for (int t = 0; t < NR; ++t) {
+        const int b = t & 1, a = t >> 1;
+        rok[t] = has[1][b] && (DIM == 2 || has[2][a]);
+        const int off = pos[1][b] * EX + (DIM == 3 ? pos[2][a] * (g.nel[1] * ni) * EX : 0);
+        lo[t] = hi[t] = 0;
+        if (rok[t]) {
+            lo[t] = base[off + (has[0][0] ? pos[0][0] : 0)];
+            hi[t] = base[off + (has[0][1] ? pos[0][1] : 0)];
         }
-        val[t] = base[ok ? off : 0];
-        if (!ok) val[t] = 0;
     }
-    ET s = val[0];
+    ET s = 0;
 #pragma unroll
-    for (int t = 1; t < NC; ++t) s += val[t];
+    for (int t = 0; t < NR; ++t) {
+        s += (rok[t] && has[0][0]) ? lo[t] : (ET)0;
+        s += (rok[t] && has[0][1]) ? hi[t] : (ET)0;
+    }
     return s;
 }
 

@@ -73,23 +73,39 @@ __device__ inline int node3(const Geom &g, int e, int i1, int i2, int i3, int &g
 }
 
 // Gather 3 components of a global vector into X for the block's elements.
-// masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)).
+// masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)).  The
+// loop has a compile-time trip count so that all of a lane's loads are
+// issued before the first one is waited for.
 template <int P, int NQ, typename CT>
 __device__ inline void gather3(const Geom &g, const double *__restrict__ vec, int e0, int nel,
                                CT *sX, bool masked)
 {
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NP = S::NP;
-    for (int idx = threadIdx.x; idx < nel * 3 * NP; idx += BLOCK) {
-        const int i = idx % NP;
-        const int r = idx / NP;  // el*3 + c
-        const int c = r % 3, el = r / 3;
-        const int i1 = i % NI, i2 = (i / NI) % NI, i3 = i / (NI * NI);
-        int gx, gy, gz;
-        const int node = node3<P>(g, e0 + el, i1, i2, i3, gx, gy, gz);
-        double v = vec[(size_t)c * g.nx + node];
-        if (masked && is_fixed(g, c, node, gx, gy, gz)) v = 0.0;
-        sX[idx] = (CT)v;
+    constexpr int NIT = (S::EPB * 3 * NP + BLOCK - 1) / BLOCK;
+    const int n = nel * 3 * NP;
+    double val[NIT];
+    bool fix[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * BLOCK;
+        val[it] = 0.0;
+        fix[it] = false;
+        if (idx < n) {
+            const int i = idx % NP;
+            const int r = idx / NP;  // el*3 + c
+            const int c = r % 3, el = r / 3;
+            const int i1 = i % NI, i2 = (i / NI) % NI, i3 = i / (NI * NI);
+            int gx, gy, gz;
+            const int node = node3<P>(g, e0 + el, i1, i2, i3, gx, gy, gz);
+            val[it] = vec[(size_t)c * g.nx + node];
+            fix[it] = masked && is_fixed(g, c, node, gx, gy, gz);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * BLOCK;
+        if (idx < n) sX[idx] = fix[it] ? (CT)0 : (CT)val[it];
     }
 }
 

@@ -162,10 +162,29 @@ __device__ inline double block_min(double v, double *red)
 //   d2mu  = c_id Id + c_tc (T (x) C + C (x) T) + c_cc C (x) C + c_dc dC/dT
 // ------------------------------------------------------------------------
 
+// Metrics with kernels: 2, 7, 9, 55 in 2D; 303, 55 in 3D.
+inline __host__ __device__ bool metric_supported(int dim, int metric)
+{
+    if (dim == 2) return metric == 2 || metric == 7 || metric == 9 || metric == 55;
+    return dim == 3 && (metric == 303 || metric == 55);
+}
+
 struct MetricCoef {
     double mu, cT, cC, c_id, c_tc, c_cc, c_dc;
 };
 
+// Quality metrics of Sec. 2.2 / 4.1, each a function f(I1, tau) of I1 = |T|^2 and
+// tau = det T that is linear in I1, so that
+//   dmu/dT   = cT T + cC C                       (cT = 2 f_1, cC = f_tau)
+//   d2mu/dT2 = c_id Id + c_tc (T x C + C x T) + c_cc C x C + c_dc dC/dT
+// with c_id = 2 f_1, c_tc = 2 f_1tau, c_cc = f_tautau, c_dc = f_tau.
+//   2   mu_2   = I1 / (2 tau) - 1                 (2D shape)
+//   303 mu_303 = I1 / (3 tau^{2/3}) - 1           (3D shape)
+//   55  mu_55  = (tau - 1)^2                      (size, 2D and 3D)
+//   7   mu_7   = |T - T^{-t}|^2 = I1 (1 + tau^-2) - 4          (2D shape+size)
+//   9   mu_9   = tau |T - T^{-t}|^2 = I1 (tau + 1/tau) - 4 tau (2D shape+size)
+// (the 2D forms of mu_7, mu_9 use |C| = |T| and T : C = 2 tau; metric_value
+// evaluates them from their definition instead, which is exact at T = I).
 __device__ inline MetricCoef metric_coef(int metric, double I1, double tau)
 {
     MetricCoef m;
@@ -178,7 +197,7 @@ __device__ inline MetricCoef metric_coef(int metric, double I1, double tau)
         m.c_tc = -it * it;
         m.c_cc = I1 * it * it * it;
         m.c_dc = -0.5 * I1 * it * it;
-    } else {
+    } else if (metric == 303) {
         const double r = 1.0 / cbrt(tau);  // tau^{-1/3}
         const double r2 = r * r;           // tau^{-2/3}
         const double r5 = r2 * r2 * r;     // tau^{-5/3}
@@ -190,8 +209,53 @@ __device__ inline MetricCoef metric_coef(int metric, double I1, double tau)
         m.c_tc = -4.0 * r5 / 9.0;
         m.c_cc = 10.0 * I1 * r8 / 27.0;
         m.c_dc = -2.0 * I1 * r5 / 9.0;
+    } else if (metric == 55) {
+        const double dm = tau - 1.0;
+        m.mu = dm * dm;
+        m.cT = 0.0;
+        m.cC = 2.0 * dm;
+        m.c_id = 0.0;
+        m.c_tc = 0.0;
+        m.c_cc = 2.0;
+        m.c_dc = 2.0 * dm;
+    } else if (metric == 7) {
+        const double it = 1.0 / tau, it2 = it * it, it3 = it2 * it;
+        m.mu = I1 * (1.0 + it2) - 4.0;
+        m.cT = 2.0 * (1.0 + it2);
+        m.cC = -2.0 * I1 * it3;
+        m.c_id = m.cT;
+        m.c_tc = -4.0 * it3;
+        m.c_cc = 6.0 * I1 * it2 * it2;
+        m.c_dc = m.cC;
+    } else {  // 9
+        const double it = 1.0 / tau, it2 = it * it;
+        m.mu = I1 * (tau + it) - 4.0 * tau;
+        m.cT = 2.0 * (tau + it);
+        m.cC = I1 * (1.0 - it2) - 4.0;
+        m.c_id = m.cT;
+        m.c_tc = 2.0 * (1.0 - it2);
+        m.c_cc = 2.0 * I1 * it2 * it;
+        m.c_dc = m.cC;
     }
     return m;
+}
+
+// mu at T (C = cof T, tau = det T > 0) for the energy: mu_7 and mu_9 from their
+// definition |T - C / tau|^2 (no cancellation near T = I), the others from
+// metric_coef.
+template <int D>
+__device__ inline double metric_value(int metric, const double *T, const double *C, double I1,
+                                      double tau, const MetricCoef &m)
+{
+    if (metric != 7 && metric != 9) return m.mu;
+    const double it = 1.0 / tau;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+        const double e = T[k] - C[k] * it;
+        s += e * e;
+    }
+    return metric == 7 ? s : tau * s;
 }
 
 template <int D>
@@ -275,7 +339,7 @@ __device__ inline bool metric_first(const Target &t, const double *A, double z, 
 #pragma unroll
     for (int k = 0; k < D * D; ++k) I1 += T[k] * T[k];
     const MetricCoef m = metric_coef(t.metric, I1, tau);
-    *mu = m.mu;
+    *mu = metric_value<D>(t.metric, T, C, I1, tau, m);
     double dmu[D * D];
 #pragma unroll
     for (int k = 0; k < D * D; ++k) dmu[k] = m.cT * T[k] + m.cC * C[k];
