@@ -293,6 +293,15 @@ int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params 
 int tmop_time_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev, int n, double *elem_ms,
                     double *total_ms);
 
+/* Limiting term (Sec. 2.2, eq. eq_F_full, second integral; Sec. 3.5, eq.
+ * eq_pa_limiting): adds coef * sum_E int_{E_t} |x - x0|^2 / delta^2 to F, with
+ * its gradient and its mass-like Hessian, to every later evaluation and solve
+ * of the context.  x0_dev: device [dim*N_x] reference node positions (SoA),
+ * copied into the context on its stream (the caller may free it afterwards);
+ * NULL removes the term.  coef >= 0 and delta > 0, else TMOP_ERR_INVALID_ARG.
+ * The Jacobi diagonal is recomputed on its next use. */
+int tmop_set_limiting(tmop_ctx *ctx, const double *x0_dev, double coef, double delta);
+
 /* Enable (1) or disable (0) HIP-event timing of the Hessian actions inside
  * MINRES; results land in tmop_solve_report.t_apply_ms / n_apply. */
 int tmop_set_timing(tmop_ctx *ctx, int enable);

@@ -1166,6 +1166,8 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     g.e2n = nullptr;
     g.ess_mode = m->ess_mode;
     g.ess = m->ess_mask;
+    g.x0 = nullptr;  // pooled solves have no limiting term
+    g.lim = 0.0;
     s.dev.tg = tg;
     char *base = P->arena + off;
     size_t o = 0;

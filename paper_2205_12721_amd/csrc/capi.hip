@@ -209,6 +209,7 @@ int internal_target(const tmop_params *prm, int d, Target *tp)
 enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_HV, SV_V, SV_W, SV_W1, SV_W2, SV_COUNT };
 
 struct tmop_ctx {
+    double *x0buf = nullptr;  // reference nodes of the limiting term (library copy)
     Geom g{};
     Tables tb{};
     Target tg{};
@@ -315,6 +316,7 @@ static void free_ctx(tmop_ctx *c)
     hipFree(c->csr_ent);
     hipFree(c->diag);
     hipFree(c->minv);
+    hipFree(c->x0buf);
     for (auto &v : c->sv) hipFree(v);
     hipFree(c->mst);
     if (c->hmst) hipHostFree(c->hmst);
@@ -848,6 +850,31 @@ extern "C" int tmop_newton_step(tmop_ctx *c, double *x, int n_minres, int jacobi
     rep->status = r;
     rep->t_total_ms = now_ms() - t0;
     return r;
+}
+
+extern "C" int tmop_set_limiting(tmop_ctx *c, const double *x0, double coef, double delta)
+{
+    if (!c) return fail(TMOP_ERR_INVALID_ARG, "null context");
+    c->have_diag = false;
+    if (!x0) {
+        c->g.x0 = nullptr;
+        c->g.lim = 0.0;
+        return TMOP_OK;
+    }
+    if (!(delta > 0.0) || !(coef >= 0.0) || !std::isfinite(coef) || !std::isfinite(delta))
+        return fail(TMOP_ERR_INVALID_ARG, "limiting term needs coef >= 0 and delta > 0");
+    if (!c->x0buf) {
+        const hipError_t e = hipMalloc((void **)&c->x0buf, sizeof(double) * c->ndof);
+        if (e != hipSuccess) {
+            c->x0buf = nullptr;
+            return fail(e == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,
+                        "limiting term reference nodes");
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->x0buf, x0, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->s));
+    c->g.x0 = c->x0buf;
+    c->g.lim = coef * c->tg.detW / (delta * delta);
+    return TMOP_OK;
 }
 
 extern "C" int tmop_set_timing(tmop_ctx *c, int enable)

@@ -3,8 +3,14 @@
 // (Sec. 3.2):
 //   A_a1(q) = sum_i1 G[q1][i1] sum_i2 B[q2][i2] x_a(i1,i2),
 //   A_a2(q) = sum_i1 B[q1][i1] sum_i2 G[q2][i2] x_a(i1,i2).
-// LDS per workgroup: sB, sG [NQ][NI]; sX [EPB][2][NI^2];
-// R1 [EPB][2][2][NI][NQ] (axis-1 B and G variants); RY [EPB][4][NQ^2].
+// Pencil sweeps with the 1D tables read from the kernel arguments (scalar
+// operands).  LDS per workgroup:
+//   X   [EPB][2][NI^2]          element nodes (or v_E)
+//   R1  [EPB][2][2][NI][NQ]     after the axis-1 contraction (B, G variants)
+//   RY  [EPB][NR][NQ^2]         J (planes c*2+b), then Y or P; with the
+//                               limiting term (NR = 6) the values of
+//                               component c in plane 4+c
+// with X and RY overlaid (X is dead once the axis-1 sweep has read it).
 #pragma once
 #include "tmop_dev.hpp"
 
@@ -20,18 +26,23 @@ struct S2 {
     static constexpr int NS = 10;
 };
 
-template <int P, int NQ, typename CT>
+template <int P, int NQ, typename CT, int NR = 4>
 struct Lds2 {
     using S = S2<P, NQ>;
-    CT B[NQ * S::NI];
-    CT G[NQ * S::NI];
-    CT X[S::EPB * 2 * S::NP];
+    union {
+        CT X[S::EPB * 2 * S::NP];
+        CT RY[S::EPB * NR * S::NQ2];
+    };
     CT R1[S::EPB * 4 * S::L1];
-    CT RY[S::EPB * 4 * S::NQ2];
+};
+
+template <bool LIM>
+struct Planes2 {
+    static constexpr int NR = LIM ? 6 : 4;
 };
 
 template <int P>
-__device__ inline int node2(const Geom &g, int e, int i1, int i2, int &gx, int &gy)
+__device__ __forceinline__ int node2(const Geom &g, int e, int i1, int i2, int &gx, int &gy)
 {
     constexpr int NI = P + 1;
     if (g.e2n) {
@@ -45,71 +56,11 @@ __device__ inline int node2(const Geom &g, int e, int i1, int i2, int &gx, int &
     return gx + g.M[0] * gy;
 }
 
-template <int P, int NQ, typename CT>
-__device__ inline void prologue2(const Geom &g, const Tables &t, const double *__restrict__ vec,
-                                 int e0, int nel, Lds2<P, NQ, CT> &L, bool masked)
-{
-    using S = S2<P, NQ>;
-    constexpr int NI = S::NI, NP = S::NP;
-    for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
-        L.B[k] = (CT)t.B[k];
-        L.G[k] = (CT)t.G[k];
-    }
-    for (int idx = threadIdx.x; idx < nel * 2 * NP; idx += BLOCK) {
-        const int i = idx % NP;
-        const int r = idx / NP;
-        const int c = r % 2, el = r / 2;
-        int gx, gy;
-        const int node = node2<P>(g, e0 + el, i % NI, i / NI, gx, gy);
-        double v = vec[(size_t)c * g.nx + node];
-        if (masked && is_fixed(g, c, node, gx, gy, 0)) v = 0.0;
-        L.X[idx] = (CT)v;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nel * 2 * NI * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int i2 = r % NI;
-        r /= NI;  // el*2 + c
-        const CT *x = L.X + r * NP + i2 * NI;
-        CT b = 0, gg = 0;
-#pragma unroll
-        for (int i1 = 0; i1 < NI; ++i1) {
-            b += L.B[q1 * NI + i1] * x[i1];
-            gg += L.G[q1 * NI + i1] * x[i1];
-        }
-        CT *o = L.R1 + r * 2 * S::L1 + i2 * NQ + q1;
-        o[0] = b;
-        o[S::L1] = gg;
-    }
-    __syncthreads();
-}
-
-template <int P, int NQ, typename CT>
-__device__ inline void point_grad2(const Lds2<P, NQ, CT> &L, int el, int q1, int q2, CT *J)
-{
-    using S = S2<P, NQ>;
-    constexpr int NI = S::NI;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const CT *tb = L.R1 + (el * 2 + c) * 2 * S::L1 + q1;  // [i2] stride NQ
-        const CT *tg = tb + S::L1;
-        CT a0 = 0, a1 = 0;
-#pragma unroll
-        for (int i2 = 0; i2 < NI; ++i2) {
-            a0 += L.B[q2 * NI + i2] * tg[i2 * NQ];
-            a1 += L.G[q2 * NI + i2] * tb[i2 * NQ];
-        }
-        J[c * 2 + 0] = a0;
-        J[c * 2 + 1] = a1;
-    }
-}
-
 // E-vector index of (element e, component c, local node i1,i2): element-major
 // [e][c][i] on general meshes, the exploded grid [c][ey*NI+i2][ex*NI+i1] on
 // the structured box (the layout the node gather expects).
 template <int P>
-__device__ inline long ev_index2(const Geom &g, int e, int c, int i1, int i2)
+__device__ __forceinline__ long ev_index2(const Geom &g, int e, int c, int i1, int i2)
 {
     constexpr int NI = P + 1, NP = NI * NI;
     if (g.e2n) return ((long)e * 2 + c) * NP + i1 + NI * i2;
@@ -118,61 +69,233 @@ __device__ inline long ev_index2(const Geom &g, int e, int c, int i1, int i2)
     return (long)c * g.ne * NP + (long)(ey * NI + i2) * EX + ex * NI + i1;
 }
 
-template <int P, int NQ, typename CT, typename OT>
-__device__ inline void backward2(Lds2<P, NQ, CT> &L, const Geom &g, int e0, int nel,
-                                 OT *__restrict__ out)
+// Gather 2 components of a global vector into X (masked: fixed DoFs as zero;
+// sub: a vector subtracted entry by entry).
+template <int P, int NQ, typename CT>
+__device__ __forceinline__ void gather2(const Geom &g, const double *__restrict__ vec, int e0, int nel,
+                               CT *sX, bool masked, const double *__restrict__ sub = nullptr)
 {
     using S = S2<P, NQ>;
-    constexpr int NI = S::NI, NQ2 = S::NQ2;
-    for (int idx = threadIdx.x; idx < nel * 2 * NI * NQ; idx += BLOCK) {
-        const int q1 = idx % NQ;
-        int r = idx / NQ;
-        const int i2 = r % NI;
-        r /= NI;  // el*2 + c
-        const CT *y = L.RY + r * 2 * NQ2 + q1;  // [b] stride NQ2, [q2] stride NQ
-        CT u0 = 0, u1 = 0;
+    constexpr int NI = S::NI, NP = S::NP;
+    constexpr int NIT = (S::EPB * 2 * NP + BLOCK - 1) / BLOCK;
+    const int n = nel * 2 * NP;
+    double val[NIT];
+    bool fix[NIT];
 #pragma unroll
-        for (int q2 = 0; q2 < NQ; ++q2) {
-            u0 += L.B[q2 * NI + i2] * y[q2 * NQ];
-            u1 += L.G[q2 * NI + i2] * y[NQ2 + q2 * NQ];
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * BLOCK;
+        val[it] = 0.0;
+        fix[it] = false;
+        if (idx < n) {
+            const int i = idx % NP;
+            const int r = idx / NP;  // el*2 + c
+            const int c = r % 2, el = r / 2;
+            int gx, gy;
+            const int node = node2<P>(g, e0 + el, i % NI, i / NI, gx, gy);
+            val[it] = vec[(size_t)c * g.nx + node];
+            if (sub) val[it] -= sub[(size_t)c * g.nx + node];
+            fix[it] = masked && is_fixed(g, c, node, gx, gy, 0);
         }
-        CT *o = L.R1 + r * 2 * S::L1 + i2 * NQ + q1;
-        o[0] = u0;
-        o[S::L1] = u1;
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nel * 2 * S::NP; idx += BLOCK) {
-        const int i1 = idx % NI;
-        const int r = idx / NI;  // (el*2+c)*NI + i2
-        const int rc = r / NI, i2 = r % NI;
-        const CT *t = L.R1 + rc * 2 * S::L1 + i2 * NQ;
-        CT s = 0;
 #pragma unroll
-        for (int q1 = 0; q1 < NQ; ++q1)
-            s += L.G[q1 * NI + i1] * t[q1] + L.B[q1 * NI + i1] * t[S::L1 + q1];
-        out[ev_index2<P>(g, e0 + rc / 2, rc % 2, i1, i2)] = (OT)s;
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * BLOCK;
+        if (idx < n) sX[idx] = fix[it] ? (CT)0 : (CT)val[it];
     }
 }
 
-template <int P, int NQ>
-__device__ inline void b2_energy(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ part, int e0, int nel)
+// Forward sweeps X -> R1 -> RY: J (plane el*NR + c*2 + b), with VAL also the
+// value of component c (plane el*NR + 4 + c).
+template <int P, int NQ, typename CT, int NR = 4, bool VAL = false>
+__device__ __forceinline__ void forward2(const Tables &tb, const CT *X, CT *R1, CT *RY, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ Lds2<P, NQ, double> L;
+    constexpr int NI = S::NI, NP = S::NP, L1 = S::L1, NQ2 = S::NQ2;
+    // axis 1: pencils (r, i2), r = el*2 + c
+    for (int pen = threadIdx.x; pen < nel * 2 * NI; pen += BLOCK) {
+        const int i2 = pen % NI, r = pen / NI;
+        const CT *x = X + r * NP + i2 * NI;
+        CT xv[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) xv[k] = x[k];
+        CT *o = R1 + r * 2 * L1 + i2 * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT b = 0, d = 0;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                b += tabB<CT>(tb, q * NI + k) * xv[k];
+                d += tabG<CT>(tb, q * NI + k) * xv[k];
+            }
+            o[q] = b;
+            o[L1 + q] = d;
+        }
+    }
+    __syncthreads();
+    // axis 2: pencils (r, q1)
+    for (int pen = threadIdx.x; pen < nel * 2 * NQ; pen += BLOCK) {
+        const int q1 = pen % NQ, r = pen / NQ;
+        const int el = r / 2, c = r % 2;
+        const CT *t = R1 + r * 2 * L1 + q1;  // [i2] stride NQ
+        CT xb[NI], xg[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            xb[k] = t[k * NQ];
+            xg[k] = t[L1 + k * NQ];
+        }
+        CT *o = RY + (el * NR + c * 2) * NQ2 + q1;
+        CT *ov = RY + (el * NR + 4 + c) * NQ2 + q1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const CT b2 = tabB<CT>(tb, q * NI + k), g2 = tabG<CT>(tb, q * NI + k);
+                a0 += b2 * xg[k];
+                a1 += g2 * xb[k];
+                if (VAL) a2 += b2 * xb[k];
+            }
+            o[q * NQ] = a0;
+            o[NQ2 + q * NQ] = a1;
+            if (VAL) ov[q * NQ] = a2;
+        }
+    }
+    __syncthreads();
+}
+
+// Backward (transposed) sweeps RY -> R1 -> E-vector:
+//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q)  (+ RY[4+c](q) w_i(q) with VAL).
+template <int P, int NQ, typename CT, typename OT, int NR = 4, bool VAL = false>
+__device__ __forceinline__ void backward2(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R1,
+                                 int nel, OT *__restrict__ out)
+{
+    using S = S2<P, NQ>;
+    constexpr int NI = S::NI, L1 = S::L1, NQ2 = S::NQ2;
+    // axis 2: pencils (r, q1)
+    for (int pen = threadIdx.x; pen < nel * 2 * NQ; pen += BLOCK) {
+        const int q1 = pen % NQ, r = pen / NQ;
+        const int el = r / 2, c = r % 2;
+        const CT *y = RY + (el * NR + c * 2) * NQ2 + q1;  // [b] stride NQ^2, [q2] stride NQ
+        const CT *yv = RY + (el * NR + 4 + c) * NQ2 + q1;
+        CT y0[NQ], y1[NQ], ym[VAL ? NQ : 1];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            y0[q] = y[q * NQ];
+            y1[q] = y[NQ2 + q * NQ];
+            if (VAL) ym[q] = yv[q * NQ];
+        }
+        CT *o = R1 + r * 2 * L1 + q1;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT u0 = 0, u1 = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const CT b2 = tabB<CT>(tb, q * NI + k), g2 = tabG<CT>(tb, q * NI + k);
+                u0 += b2 * y0[q];
+                u1 += g2 * y1[q];
+                if (VAL) u1 += b2 * ym[q];
+            }
+            o[k * NQ] = u0;       // G along axis 1 still to apply
+            o[L1 + k * NQ] = u1;  // B along axis 1 still to apply
+        }
+    }
+    __syncthreads();
+    // axis 1: pencils (r, i2) -> NI consecutive outputs
+    for (int pen = threadIdx.x; pen < nel * 2 * NI; pen += BLOCK) {
+        const int i2 = pen % NI, r = pen / NI;
+        const int c = r % 2, el = r / 2;
+        const CT *t = R1 + r * 2 * L1 + i2 * NQ;
+        CT u0[NQ], u1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            u0[q] = t[q];
+            u1[q] = t[L1 + q];
+        }
+        OT *o = out + ev_index2<P>(g, e0 + el, c, 0, i2);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT s = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                s += tabG<CT>(tb, q * NI + k) * u0[q] + tabB<CT>(tb, q * NI + k) * u1[q];
+            o[k] = (OT)s;
+        }
+    }
+}
+
+template <int P, int NQ, typename CT, int NR = 4>
+__device__ __forceinline__ void point_J2(const CT *RY, int el, int q, CT *J)
+{
+    constexpr int NQ2 = NQ * NQ;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) J[k] = RY[(el * NR + k) * NQ2 + q];
+}
+
+template <int NQ>
+__device__ __forceinline__ double qweight2(const Tables &tb, int q)
+{
+    return tab_w<NQ>(tb, q % NQ) * tab_w<NQ>(tb, q / NQ);
+}
+
+// Values of x - x0 at the points into U[el][c][q] (limiting term).
+template <int P, int NQ, typename L2>
+__device__ __forceinline__ void lim_values2(const Geom &g, const Tables &tb, const double *__restrict__ x,
+                                   int e0, int nel, L2 &L, double *U)
+{
+    using S = S2<P, NQ>;
+    gather2<P, NQ>(g, x, e0, nel, L.X, false, g.x0);
+    __syncthreads();
+    forward2<P, NQ, double, 6, true>(tb, L.X, L.R1, L.RY, nel);
+    for (int idx = threadIdx.x; idx < nel * 2 * S::NQ2; idx += BLOCK) {
+        const int q = idx % S::NQ2, r = idx / S::NQ2;  // r = el*2 + c
+        U[idx] = L.RY[((r / 2) * 6 + 4 + r % 2) * S::NQ2 + q];
+    }
+    __syncthreads();
+}
+
+// Limiting term in the Hessian action: value planes v_c(q) -> 2 w_q lim v_c(q).
+template <int NQ, typename CT, int NR>
+__device__ __forceinline__ void lim_point2(const Tables &tb, const Geom &g, int el, int q, CT *RY)
+{
+    constexpr int NQ2 = NQ * NQ;
+    const CT f = (CT)(2.0 * g.lim * qweight2<NQ>(tb, q));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) RY[(el * NR + 4 + c) * NQ2 + q] *= f;
+}
+
+// ------------------------------------------------------------------------
+// Element bodies (see the hex kernels for the description of each)
+// ------------------------------------------------------------------------
+
+template <int P, int NQ, bool LIM = false>
+__device__ __forceinline__ void b2_energy(const Geom &g, const Tables &tb, const Target &tg,
+                                 const double *__restrict__ x, double *__restrict__ part, int e0,
+                                 int nel)
+{
+    using S = S2<P, NQ>;
+    constexpr int NR = Planes2<LIM>::NR;
+    __shared__ Lds2<P, NQ, double, NR> L;
+    __shared__ double U[LIM ? S::EPB * 2 * S::NQ2 : 1];
     __shared__ double red[BLOCK / 64];
-    prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
+    if (LIM) lim_values2<P, NQ>(g, tb, x, e0, nel, L, U);
+    gather2<P, NQ>(g, x, e0, nel, L.X, false);
+    __syncthreads();
+    forward2<P, NQ, double, NR>(tb, L.X, L.R1, L.RY, nel);
     double esum = 0.0, dmin = 1.0e300, bad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         double J[4], Pm[4], mu;
-        point_grad2<P, NQ>(L, el, q1, q2, J);
+        point_J2<P, NQ, double, NR>(L.RY, el, q, J);
         dmin = fmin(dmin, det_only<2>(J));
-        const double z = tb.w[q1] * tb.w[q2] * tg.detW;
+        const double z = qweight2<NQ>(tb, q) * tg.detW;
         if (metric_first<2>(tg, J, z, &mu, Pm))
             esum += z * mu;
         else
             bad += 1.0;
+        if (LIM) {
+            const double u0 = U[(el * 2) * S::NQ2 + q], u1 = U[(el * 2 + 1) * S::NQ2 + q];
+            esum += qweight2<NQ>(tb, q) * g.lim * (u0 * u0 + u1 * u1);
+        }
     }
     const double s = block_sum(esum, red);
     const double m = block_min(dmin, red);
@@ -184,48 +307,63 @@ __device__ inline void b2_energy(const Geom &g, const Tables &tb, const Target &
     }
 }
 
-template <int P, int NQ>
-__device__ inline void b2_gradient(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad, int e0, int nel)
+template <int P, int NQ, bool LIM = false>
+__device__ __forceinline__ void b2_gradient(const Geom &g, const Tables &tb, const Target &tg,
+                                   const double *__restrict__ x, double *__restrict__ gE,
+                                   double *__restrict__ bad, int e0, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ Lds2<P, NQ, double> L;
+    constexpr int NR = Planes2<LIM>::NR;
+    __shared__ Lds2<P, NQ, double, NR> L;
+    __shared__ double U[LIM ? S::EPB * 2 * S::NQ2 : 1];
     __shared__ double red[BLOCK / 64];
-    prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
+    if (LIM) lim_values2<P, NQ>(g, tb, x, e0, nel, L, U);
+    gather2<P, NQ>(g, x, e0, nel, L.X, false);
+    __syncthreads();
+    forward2<P, NQ, double, NR>(tb, L.X, L.R1, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         double J[4], Pm[4], mu;
-        point_grad2<P, NQ>(L, el, q1, q2, J);
-        const double z = tb.w[q1] * tb.w[q2] * tg.detW;
+        point_J2<P, NQ, double, NR>(L.RY, el, q, J);
+        const double z = qweight2<NQ>(tb, q) * tg.detW;
         if (!metric_first<2>(tg, J, z, &mu, Pm)) {
             nbad += 1.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) Pm[k] = 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) L.RY[(el * 4 + k) * S::NQ2 + q] = Pm[k];
+        for (int k = 0; k < 4; ++k) L.RY[(el * NR + k) * S::NQ2 + q] = Pm[k];
+        if (LIM) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                L.RY[(el * NR + 4 + c) * S::NQ2 + q] =
+                    2.0 * qweight2<NQ>(tb, q) * g.lim * U[(el * 2 + c) * S::NQ2 + q];
+        }
     }
     __syncthreads();
-    backward2<P, NQ>(L, g, e0, nel, gE);
+    backward2<P, NQ, double, double, NR, LIM>(tb, g, e0, L.RY, L.R1, nel, gE);
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
 template <int P, int NQ, typename TT>
-__device__ inline void b2_setup(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad, int e0, int nel)
+__device__ __forceinline__ void b2_setup(const Geom &g, const Tables &tb, const Target &tg,
+                                const double *__restrict__ x, TT *__restrict__ H,
+                                double *__restrict__ bad, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
+    gather2<P, NQ>(g, x, e0, nel, L.X, false);
+    __syncthreads();
+    forward2<P, NQ, double>(tb, L.X, L.R1, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         double J[4], Hp[10];
-        point_grad2<P, NQ>(L, el, q1, q2, J);
-        const double z = tb.w[q1] * tb.w[q2] * tg.detW;
+        point_J2<P, NQ>(L.RY, el, q, J);
+        const double z = qweight2<NQ>(tb, q) * tg.detW;
         if (!metric_second<2>(tg, J, z, Hp)) {
             nbad += 1.0;
 #pragma unroll
@@ -239,31 +377,35 @@ __device__ inline void b2_setup(const Geom &g, const Tables &tb, const Target &t
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
-template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b2_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+__device__ __forceinline__ void b2_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+                                const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ Lds2<P, NQ, CT> L;
-    prologue2<P, NQ>(g, tb, v, e0, nel, L, true);
+    constexpr int NR = Planes2<LIM>::NR;
+    __shared__ Lds2<P, NQ, CT, NR> L;
+    gather2<P, NQ>(g, v, e0, nel, L.X, true);
+    __syncthreads();
+    forward2<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.RY, nel);
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         const TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
         CT hv[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) hv[k] = (CT)h[k * S::NQ2];
         CT J[4];
-        point_grad2<P, NQ>(L, el, q1, q2, J);
+        point_J2<P, NQ, CT, NR>(L.RY, el, q, J);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             CT s = 0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) s += hv[sym_index<4>(r, c)] * J[c];
-            L.RY[(el * 4 + r) * S::NQ2 + q] = s;
+            L.RY[(el * NR + r) * S::NQ2 + q] = s;
         }
+        if (LIM) lim_point2<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
-    backward2<P, NQ>(L, g, e0, nel, yE);
+    backward2<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R1, nel, yE);
 }
 
 // ------------------------------------------------------------------------
@@ -274,7 +416,7 @@ __device__ inline void b2_apply(const Geom &g, const Tables &tb, const TT *__res
 constexpr int NC2 = 8;
 
 template <typename CT>
-__device__ inline void compact_action2(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
+__device__ __forceinline__ void compact_action2(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
 {
     const CT C[4] = {T[3], -T[2], -T[1], T[0]};
     const CT dC[4] = {M[3], -M[2], -M[1], M[0]};
@@ -290,7 +432,7 @@ __device__ inline void compact_action2(const CT *T, CT ca, CT cb, CT cc, CT cd, 
 }
 
 template <typename CT>
-__device__ inline void mul_winv2(const Target &t, const CT *in, CT *out, bool tr)
+__device__ __forceinline__ void mul_winv2(const Target &t, const CT *in, CT *out, bool tr)
 {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -304,22 +446,26 @@ __device__ inline void mul_winv2(const Target &t, const CT *in, CT *out, bool tr
         }
 }
 
+
 template <int P, int NQ, typename TT>
-__device__ inline void b2_setupc(const Geom &g, const Tables &tb, const Target &tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad, int e0, int nel)
+__device__ __forceinline__ void b2_setupc(const Geom &g, const Tables &tb, const Target &tg,
+                                 const double *__restrict__ x, TT *__restrict__ Q,
+                                 double *__restrict__ bad, int e0, int nel)
 {
     using S = S2<P, NQ>;
     __shared__ Lds2<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
-    prologue2<P, NQ>(g, tb, x, e0, nel, L, false);
+    gather2<P, NQ>(g, x, e0, nel, L.X, false);
+    __syncthreads();
+    forward2<P, NQ, double>(tb, L.X, L.R1, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         double J[4], T[4], C[4], out[NC2];
-        point_grad2<P, NQ>(L, el, q1, q2, J);
+        point_J2<P, NQ>(L.RY, el, q, J);
         apply_winv<2>(tg, J, T);
         const double tau = det_cof<2>(T, C);
-        const double z = tb.w[q1] * tb.w[q2] * tg.detW;
+        const double z = qweight2<NQ>(tb, q) * tg.detW;
         if (tau > 0.0) {
             double I1 = 0.0;
 #pragma unroll
@@ -344,21 +490,25 @@ __device__ inline void b2_setupc(const Geom &g, const Tables &tb, const Target &
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
-template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b2_applyc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+__device__ __forceinline__ void b2_applyc(const Geom &g, const Tables &tb, const Target &tg,
+                                 const TT *__restrict__ Q, const double *__restrict__ v,
+                                 CT *__restrict__ yE, int e0, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ Lds2<P, NQ, CT> L;
-    prologue2<P, NQ>(g, tb, v, e0, nel, L, true);
+    constexpr int NR = Planes2<LIM>::NR;
+    __shared__ Lds2<P, NQ, CT, NR> L;
+    gather2<P, NQ>(g, v, e0, nel, L.X, true);
+    __syncthreads();
+    forward2<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.RY, nel);
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const int q1 = q % NQ, q2 = q / NQ;
         const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
         CT d[NC2];
 #pragma unroll
         for (int k = 0; k < NC2; ++k) d[k] = (CT)h[k * S::NQ2];
         CT J[4], Y[4];
-        point_grad2<P, NQ>(L, el, q1, q2, J);
+        point_J2<P, NQ, CT, NR>(L.RY, el, q, J);
         if (tg.ideal) {
             compact_action2<CT>(d, d[4], d[5], d[6], d[7], J, Y);
         } else {
@@ -368,29 +518,32 @@ __device__ inline void b2_applyc(const Geom &g, const Tables &tb, const Target &
             mul_winv2<CT>(tg, Yt, Y, true);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) L.RY[(el * 4 + r) * S::NQ2 + q] = Y[r];
+        for (int r = 0; r < 4; ++r) L.RY[(el * NR + r) * S::NQ2 + q] = Y[r];
+        if (LIM) lim_point2<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
-    backward2<P, NQ>(L, g, e0, nel, yE);
+    backward2<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R1, nel, yE);
 }
 
 // Hessian diagonal (Sec. 3.4): 2 components x 3 pairs (n <= p) of planes
-// sQ[el][pair][a][q], then one contraction pass per pair with BB, BG, GG.
-template <int P, int NQ>
+// sQ[el][pair][a][q], then one contraction pass per pair with BB, BG, GG; with
+// the limiting term a fourth pair 2 w_q lim contracted with BB on both axes.
+template <int P, int NQ, bool LIM = false>
 struct DiagLds2 {
     using S = S2<P, NQ>;
+    static constexpr int NPR = LIM ? 4 : 3;
     double T[3][NQ * S::NI];
-    double sQ[S::EPB * 6 * S::NQ2];
+    double sQ[S::EPB * NPR * 2 * S::NQ2];
     double U1[S::EPB * 2 * S::NI * NQ];
     double sD[S::EPB * 2 * S::NP];
 };
 
-template <int P, int NQ>
-__device__ inline void diag_contract2(const Tables &tb, const Geom &g, int e0, DiagLds2<P, NQ> &L,
-                                      int nel, double *__restrict__ dE)
+template <int P, int NQ, bool LIM>
+__device__ __forceinline__ void diag_contract2(const Tables &tb, const Geom &g, int e0,
+                                      DiagLds2<P, NQ, LIM> &L, int nel, double *__restrict__ dE)
 {
     using S = S2<P, NQ>;
-    constexpr int NI = S::NI, NQ2 = S::NQ2, NP = S::NP;
+    constexpr int NI = S::NI, NQ2 = S::NQ2, NP = S::NP, NPR = DiagLds2<P, NQ, LIM>::NPR;
     for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
         const double b = tb.B[k], gg = tb.G[k];
         L.T[0][k] = b * b;
@@ -398,9 +551,10 @@ __device__ inline void diag_contract2(const Tables &tb, const Geom &g, int e0, D
         L.T[2][k] = gg * gg;
     }
     for (int k = threadIdx.x; k < nel * 2 * NP; k += BLOCK) L.sD[k] = 0.0;
-    for (int pr = 0; pr < 3; ++pr) {
+    for (int pr = 0; pr < NPR; ++pr) {
         const int n = pr == 2 ? 1 : 0, p = pr == 0 ? 0 : 1;
-        const int t1 = (n == 0) + (p == 0), t2 = (n == 1) + (p == 1);
+        const bool val = pr == 3;
+        const int t1 = val ? 0 : (n == 0) + (p == 0), t2 = val ? 0 : (n == 1) + (p == 1);
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 2 * NI * NQ; idx += BLOCK) {
             const int q1 = idx % NQ;
@@ -408,7 +562,7 @@ __device__ inline void diag_contract2(const Tables &tb, const Geom &g, int e0, D
             const int i2 = r % NI;
             r /= NI;  // el*2 + a
             const int el = r / 2, a = r % 2;
-            const double *y = L.sQ + ((el * 3 + pr) * 2 + a) * NQ2 + q1;
+            const double *y = L.sQ + ((el * NPR + pr) * 2 + a) * NQ2 + q1;
             double s = 0.0;
 #pragma unroll
             for (int q2 = 0; q2 < NQ; ++q2) s += L.T[t2][q2 * NI + i2] * y[q2 * NQ];
@@ -432,11 +586,24 @@ __device__ inline void diag_contract2(const Tables &tb, const Geom &g, int e0, D
     }
 }
 
-template <int P, int NQ, typename TT>
-__device__ inline void b2_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H, double *__restrict__ dE, int e0, int nel)
+template <int P, int NQ, bool LIM>
+__device__ __forceinline__ void diag_lim2(const Tables &tb, const Geom &g, DiagLds2<P, NQ, LIM> &L, int el,
+                                 int q)
+{
+    if (!LIM) return;
+    constexpr int NQ2 = NQ * NQ, NPR = DiagLds2<P, NQ, LIM>::NPR;
+    const double f = 2.0 * g.lim * qweight2<NQ>(tb, q);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) L.sQ[((el * NPR + 3) * 2 + a) * NQ2 + q] = f;
+}
+
+template <int P, int NQ, typename TT, bool LIM = false>
+__device__ __forceinline__ void b2_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+                               double *__restrict__ dE, int e0, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ DiagLds2<P, NQ> L;
+    constexpr int NPR = DiagLds2<P, NQ, LIM>::NPR;
+    __shared__ DiagLds2<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
         const TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
@@ -446,18 +613,21 @@ __device__ inline void b2_diag(const Geom &g, const Tables &tb, const TT *__rest
             const double f = (n == p) ? 1.0 : 2.0;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
-                L.sQ[((el * 3 + pr) * 2 + a) * S::NQ2 + q] =
+                L.sQ[((el * NPR + pr) * 2 + a) * S::NQ2 + q] =
                     f * (double)h[sym_index<4>(a * 2 + n, a * 2 + p) * S::NQ2];
         }
+        diag_lim2<P, NQ, LIM>(tb, g, L, el, q);
     }
-    diag_contract2<P, NQ>(tb, g, e0, L, nel, dE);
+    diag_contract2<P, NQ, LIM>(tb, g, e0, L, nel, dE);
 }
 
-template <int P, int NQ, typename TT>
-__device__ inline void b2_diagc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+template <int P, int NQ, typename TT, bool LIM = false>
+__device__ __forceinline__ void b2_diagc(const Geom &g, const Tables &tb, const Target &tg,
+                                const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
 {
     using S = S2<P, NQ>;
-    __shared__ DiagLds2<P, NQ> L;
+    constexpr int NPR = DiagLds2<P, NQ, LIM>::NPR;
+    __shared__ DiagLds2<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
         const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
@@ -491,33 +661,35 @@ __device__ inline void b2_diagc(const Geom &g, const Tables &tb, const Target &t
                 const double hv = cid * WW[n * 2 + p] +
                                   ctc * (Tw[a * 2 + n] * Cw[a * 2 + p] + Cw[a * 2 + n] * Tw[a * 2 + p]) +
                                   ccc * Cw[a * 2 + n] * Cw[a * 2 + p];
-                L.sQ[((el * 3 + pr) * 2 + a) * S::NQ2 + q] = f * hv;
+                L.sQ[((el * NPR + pr) * 2 + a) * S::NQ2 + q] = f * hv;
             }
         }
+        diag_lim2<P, NQ, LIM>(tb, g, L, el, q);
     }
-    diag_contract2<P, NQ>(tb, g, e0, L, nel, dE);
+    diag_contract2<P, NQ, LIM>(tb, g, e0, L, nel, dE);
 }
 
 // ------------------------------------------------------------------------
-// Kernel entry points: single mesh (grid over element blocks) and batched
-// (grid over a tile list of (slot, first element) with per-slot geometry,
-// target and offsets into packed pools).
+// Kernel entry points: single mesh (grid over element blocks; LIM selects the
+// variant with the limiting term) and batched (grid over a tile list of
+// (slot, first element) with per-slot geometry, target and offsets into
+// packed pools; no limiting term).
 // ------------------------------------------------------------------------
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_energy<P, NQ>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
+    b2_energy<P, NQ, LIM>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_gradient<P, NQ>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+    b2_gradient<P, NQ, LIM>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -528,12 +700,12 @@ __global__ __launch_bounds__(BLOCK) void k2_setup(Geom g, Tables tb, Target tg, 
     b2_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_apply<P, NQ, TT, CT>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
+    b2_apply<P, NQ, TT, CT, LIM>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -544,28 +716,28 @@ __global__ __launch_bounds__(BLOCK) void k2_setupc(Geom g, Tables tb, Target tg,
     b2_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_applyc<P, NQ, TT, CT>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
+    b2_applyc<P, NQ, TT, CT, LIM>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_diag(Geom g, Tables tb, const TT *__restrict__ H, double *__restrict__ dE)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_diag<P, NQ, TT>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
+    b2_diag<P, NQ, TT, LIM>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k2_diagc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, double *__restrict__ dE)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_diagc<P, NQ, TT>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
+    b2_diagc<P, NQ, TT, LIM>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ>

@@ -14,8 +14,11 @@
 //   X   [EPB][3][NI^3]            element nodes (or v_E)
 //   R1  [EPB][3][2][NI][NI][NQ]   after the axis-1 contraction (B, G variants)
 //   R2  [EPB][3][3][NI][NQ][NQ]   after the axis-2 contraction (GB, BG, BB)
-//   RY  [EPB][9][NQ^3]            per-point 3x3 values: J = dx/dxbar after
-//                                 the forward sweeps, then Y (H : grad v, or P)
+//   RY  [EPB][NR][NQ^3]           per-point 3x3 values: J = dx/dxbar after
+//                                 the forward sweeps, then Y (H : grad v, or P);
+//                                 with the limiting term (NR = 12) also the
+//                                 vector's values at the points, then the
+//                                 limiting term's point values
 // with X/R2 and R1/RY overlaid.
 // Forward:  X -> R1 -> R2 -> RY(J);  point stage RY(J) -> RY(Y) in place;
 // backward: RY(Y) -> R2 -> R1 -> E-vector.
@@ -39,7 +42,9 @@ struct S3 {
 // X and R2 share storage, and so do R1 and RY: each stage reads one of the
 // two buffers and writes the other, so a buffer is overwritten only after the
 // barrier that ends the last read of its previous contents.
-template <int P, int NQ, typename CT>
+// NR = planes of RY per element: 9 (J or Y), or 12 when the three value
+// planes of the limiting term (the vector itself at the points) follow.
+template <int P, int NQ, typename CT, int NR = 9>
 struct Lds3 {
     using S = S3<P, NQ>;
     union {
@@ -48,13 +53,19 @@ struct Lds3 {
     };
     union {
         CT R1[S::EPB * 6 * S::L1];
-        CT RY[S::EPB * 9 * S::NQ3];
+        CT RY[S::EPB * NR * S::NQ3];
     };
+};
+
+// RY planes per element for a body with (LIM) or without the limiting term.
+template <bool LIM>
+struct Planes3 {
+    static constexpr int NR = LIM ? 12 : 9;
 };
 
 // Global node of local node (i1,i2,i3) of element e, and its grid coordinates.
 template <int P>
-__device__ inline int node3(const Geom &g, int e, int i1, int i2, int i3, int &gx, int &gy,
+__device__ __forceinline__ int node3(const Geom &g, int e, int i1, int i2, int i3, int &gx, int &gy,
                             int &gz)
 {
     constexpr int NI = P + 1;
@@ -73,12 +84,13 @@ __device__ inline int node3(const Geom &g, int e, int i1, int i2, int i3, int &g
 }
 
 // Gather 3 components of a global vector into X for the block's elements.
-// masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)).  The
+// masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)); sub:
+// a vector subtracted entry by entry (x - x0 of the limiting term).  The
 // loop has a compile-time trip count so that all of a lane's loads are
 // issued before the first one is waited for.
 template <int P, int NQ, typename CT>
-__device__ inline void gather3(const Geom &g, const double *__restrict__ vec, int e0, int nel,
-                               CT *sX, bool masked)
+__device__ __forceinline__ void gather3(const Geom &g, const double *__restrict__ vec, int e0, int nel,
+                               CT *sX, bool masked, const double *__restrict__ sub = nullptr)
 {
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NP = S::NP;
@@ -99,6 +111,7 @@ __device__ inline void gather3(const Geom &g, const double *__restrict__ vec, in
             int gx, gy, gz;
             const int node = node3<P>(g, e0 + el, i1, i2, i3, gx, gy, gz);
             val[it] = vec[(size_t)c * g.nx + node];
+            if (sub) val[it] -= sub[(size_t)c * g.nx + node];
             fix[it] = masked && is_fixed(g, c, node, gx, gy, gz);
         }
     }
@@ -109,9 +122,10 @@ __device__ inline void gather3(const Geom &g, const double *__restrict__ vec, in
     }
 }
 
-// Forward sweeps X -> R1 -> R2 -> RY (J at every point, plane el*9 + c*3 + b).
-template <int P, int NQ, typename CT>
-__device__ inline void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, CT *RY, int nel)
+// Forward sweeps X -> R1 -> R2 -> RY (J at every point, plane el*NR + c*3 + b;
+// with VAL also the value of component c, plane el*NR + 9 + c).
+template <int P, int NQ, typename CT, int NR = 9, bool VAL = false>
+__device__ __forceinline__ void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, CT *RY, int nel)
 {
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NP = S::NP, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
@@ -174,20 +188,24 @@ __device__ inline void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, C
             t1[k] = t[L2 + k * NQ2];
             t2[k] = t[2 * L2 + k * NQ2];
         }
-        CT *o = RY + r * 3 * NQ3 + q12;
+        const int el = r / 3, c = r % 3;
+        CT *o = RY + (el * NR + c * 3) * NQ3 + q12;
+        CT *ov = RY + (el * NR + 9 + c) * NQ3 + q12;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            CT a0 = 0, a1 = 0, a2 = 0;
+            CT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
                 a0 += b3 * t0[k];
                 a1 += b3 * t1[k];
                 a2 += g3 * t2[k];
+                if (VAL) a3 += b3 * t2[k];
             }
             o[q * NQ2] = a0;
             o[NQ3 + q * NQ2] = a1;
             o[2 * NQ3 + q * NQ2] = a2;
+            if (VAL) ov[q * NQ2] = a3;
         }
     }
     __syncthreads();
@@ -198,7 +216,7 @@ __device__ inline void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, C
 // [c][ez*NI+i3][ey*NI+i2][ex*NI+i1], in which the node gather reads runs of
 // neighbouring addresses.
 template <int P>
-__device__ inline long ev_index3(const Geom &g, int e, int c, int i1, int i2, int i3)
+__device__ __forceinline__ long ev_index3(const Geom &g, int e, int c, int i1, int i2, int i3)
 {
     constexpr int NI = P + 1, NP = NI * NI * NI;
     if (g.e2n) return ((long)e * 3 + c) * NP + i1 + NI * (i2 + NI * i3);
@@ -211,9 +229,9 @@ __device__ inline long ev_index3(const Geom &g, int e, int c, int i1, int i2, in
 }
 
 // Backward (transposed) sweeps RY -> R2 -> R1 -> E-vector:
-//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q).
-template <int P, int NQ, typename CT, typename OT>
-__device__ inline void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
+//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q)  (+ RY[9+c](q) w_i(q) with VAL).
+template <int P, int NQ, typename CT, typename OT, int NR = 9, bool VAL = false>
+__device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
                                  CT *R1, int nel, OT *__restrict__ out)
 {
     using S = S3<P, NQ>;
@@ -221,13 +239,16 @@ __device__ inline void backward3(const Tables &tb, const Geom &g, int e0, const 
     // axis 3: pencils (r, q2, q1)
     for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
         const int q12 = pen % NQ2, r = pen / NQ2;
-        const CT *y = RY + r * 3 * NQ3 + q12;  // [b] stride NQ^3, [q3] stride NQ^2
-        CT y0[NQ], y1[NQ], y2[NQ];
+        const int el = r / 3, c = r % 3;
+        const CT *y = RY + (el * NR + c * 3) * NQ3 + q12;  // [b] stride NQ^3, [q3] stride NQ^2
+        const CT *yv = RY + (el * NR + 9 + c) * NQ3 + q12;
+        CT y0[NQ], y1[NQ], y2[NQ], ym[VAL ? NQ : 1];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             y0[q] = y[q * NQ2];
             y1[q] = y[NQ3 + q * NQ2];
             y2[q] = y[2 * NQ3 + q * NQ2];
+            if (VAL) ym[q] = yv[q * NQ2];
         }
         CT *o = R2 + r * 3 * L2 + q12;
 #pragma unroll
@@ -239,6 +260,8 @@ __device__ inline void backward3(const Tables &tb, const Geom &g, int e0, const 
                 t0 += b3 * y0[q];
                 t1 += b3 * y1[q];
                 t2 += g3 * y2[q];
+                // the value term follows the B B path of plane 2 on axes 1, 2
+                if (VAL) t2 += b3 * ym[q];
             }
             o[k * NQ2] = t0;
             o[L2 + k * NQ2] = t1;
@@ -296,43 +319,85 @@ __device__ inline void backward3(const Tables &tb, const Geom &g, int e0, const 
 }
 
 // J[c*3+b] = d x_c / d xbar_b at point q of element el, left in RY by forward3.
-template <int P, int NQ, typename CT>
-__device__ inline void point_J3(const CT *RY, int el, int q, CT *J)
+template <int P, int NQ, typename CT, int NR = 9>
+__device__ __forceinline__ void point_J3(const CT *RY, int el, int q, CT *J)
 {
     constexpr int NQ3 = S3<P, NQ>::NQ3;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) J[k] = RY[(el * 9 + k) * NQ3 + q];
+    for (int k = 0; k < 9; ++k) J[k] = RY[(el * NR + k) * NQ3 + q];
 }
 
+// Product of the 1D quadrature weights at point q.
 template <int NQ>
-__device__ inline double point_weight3(const Tables &tb, const Target &tg, int q)
+__device__ __forceinline__ double qweight3(const Tables &tb, int q)
 {
     const int q1 = q % NQ, q2 = (q / NQ) % NQ, q3 = q / (NQ * NQ);
-    return tb.w[q1] * tb.w[q2] * tb.w[q3] * tg.detW;
+    return tab_w<NQ>(tb, q1) * tab_w<NQ>(tb, q2) * tab_w<NQ>(tb, q3);
+}
+
+// z = w_q det W: the weight of point q in the integral over the target element.
+template <int NQ>
+__device__ __forceinline__ double point_weight3(const Tables &tb, const Target &tg, int q)
+{
+    return qweight3<NQ>(tb, q) * tg.detW;
 }
 
 // ------------------------------------------------------------------------
 // Element bodies
 // ------------------------------------------------------------------------
 
+// Limiting term in the Hessian action (eq. eq_pa_limiting): the value planes
+// v_c(q) become 2 w_q lim v_c(q), a mass-like operator with no stored data
+// (lim = coef det W / delta^2 folds the target volume factor in).
+template <int NQ, typename CT, int NR>
+__device__ __forceinline__ void lim_point3(const Tables &tb, const Geom &g, int el, int q, CT *RY)
+{
+    constexpr int NQ3 = NQ * NQ * NQ;
+    const CT f = (CT)(2.0 * g.lim * qweight3<NQ>(tb, q));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) RY[(el * NR + 9 + c) * NQ3 + q] *= f;
+}
+
+// Values of x - x0 (limiting term) at the points of the block's elements,
+// into U[el][c][q]: forward sweeps with value planes on the difference.
+template <int P, int NQ, typename L3>
+__device__ __forceinline__ void lim_values3(const Geom &g, const Tables &tb, const double *__restrict__ x,
+                                   int e0, int nel, L3 &L, double *U)
+{
+    using S = S3<P, NQ>;
+    gather3<P, NQ>(g, x, e0, nel, L.X, false, g.x0);
+    __syncthreads();
+    forward3<P, NQ, double, 12, true>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    for (int idx = threadIdx.x; idx < nel * 3 * S::NQ3; idx += BLOCK) {
+        const int q = idx % S::NQ3, r = idx / S::NQ3;  // r = el*3 + c
+        U[idx] = L.RY[((r / 3) * 12 + 9 + r % 3) * S::NQ3 + q];
+    }
+    __syncthreads();
+}
+
 // Energy and minimum det A: per-block partial sums of z mu and minima of det A,
 // count of points with det T <= 0 (Sec. 3.3, eq. D0_expression; Sec. 2.3).
-template <int P, int NQ>
-__device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &tg,
+// LIM adds w_q lim |x - x0|^2 (the limiting integral of eq. eq_F_full with
+// xi = |y|^2 / delta^2 over the target element, lim = coef det W / delta^2).
+template <int P, int NQ, bool LIM = false>
+__device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, double *__restrict__ part, int e0,
                                  int nel)
 {
     using S = S3<P, NQ>;
-    __shared__ Lds3<P, NQ, double> L;
+    constexpr int NR = Planes3<LIM>::NR;
+    __shared__ Lds3<P, NQ, double, NR> L;
+    __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
     __shared__ double red[BLOCK / 64];
+    if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double esum = 0.0, dmin = 1.0e300, bad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         double J[9];
-        point_J3<P, NQ>(L.RY, el, q, J);
+        point_J3<P, NQ, double, NR>(L.RY, el, q, J);
         dmin = fmin(dmin, det_only<3>(J));
         const double z = point_weight3<NQ>(tb, tg, q);
         double mu, Pm[9];
@@ -340,6 +405,15 @@ __device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &
             esum += z * mu;
         else
             bad += 1.0;
+        if (LIM) {
+            double y2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u = U[(el * 3 + c) * S::NQ3 + q];
+                y2 += u * u;
+            }
+            esum += qweight3<NQ>(tb, q) * g.lim * y2;
+        }
     }
     const double s = block_sum(esum, red);
     const double m = block_min(dmin, red);
@@ -353,22 +427,26 @@ __device__ inline void b3_energy(const Geom &g, const Tables &tb, const Target &
 
 // Gradient E-vector (Sec. 3.3, eq. eq_vm_pa_grad): per point z P, then the
 // transposed contractions.  bad[blockIdx] counts points with det T <= 0.
-template <int P, int NQ>
-__device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
+// LIM adds 2 w_q lim (x - x0)_c(q) wbar_i(q) through the value planes.
+template <int P, int NQ, bool LIM = false>
+__device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
                                    const double *__restrict__ x, double *__restrict__ gE,
                                    double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
-    __shared__ Lds3<P, NQ, double> L;
+    constexpr int NR = Planes3<LIM>::NR;
+    __shared__ Lds3<P, NQ, double, NR> L;
+    __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
     __shared__ double red[BLOCK / 64];
+    if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         double J[9], Pm[9], mu;
-        point_J3<P, NQ>(L.RY, el, q, J);
+        point_J3<P, NQ, double, NR>(L.RY, el, q, J);
         const double z = point_weight3<NQ>(tb, tg, q);
         if (!metric_first<3>(tg, J, z, &mu, Pm)) {
             nbad += 1.0;
@@ -376,10 +454,16 @@ __device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target
             for (int k = 0; k < 9; ++k) Pm[k] = 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) L.RY[(el * 9 + k) * S::NQ3 + q] = Pm[k];
+        for (int k = 0; k < 9; ++k) L.RY[(el * NR + k) * S::NQ3 + q] = Pm[k];
+        if (LIM) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                L.RY[(el * NR + 9 + c) * S::NQ3 + q] =
+                    2.0 * qweight3<NQ>(tb, q) * g.lim * U[(el * 3 + c) * S::NQ3 + q];
+        }
     }
     __syncthreads();
-    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, gE);
+    backward3<P, NQ, double, double, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, gE);
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
@@ -387,7 +471,7 @@ __device__ inline void b3_gradient(const Geom &g, const Tables &tb, const Target
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
 // element-major [e][45][NQ^3] so that each entry is one coalesced plane.
 template <int P, int NQ, typename TT>
-__device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &tg,
+__device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const Target &tg,
                                 const double *__restrict__ x, TT *__restrict__ H,
                                 double *__restrict__ bad, int e0, int nel)
 {
@@ -422,15 +506,16 @@ __device__ inline void b3_setup(const Geom &g, const Tables &tb, const Target &t
 //   transposed contractions -> E-vector.
 // CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
 // accumulation).
-template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+__device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
                                 const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ>;
+    constexpr int NR = Planes3<LIM>::NR;
     // at most one quadrature point per lane: its tensor is loaded before the
     // sweeps and stays in flight behind them (barriers wait on LDS only)
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;
-    __shared__ Lds3<P, NQ, CT> L;
+    __shared__ Lds3<P, NQ, CT, NR> L;
     gather3<P, NQ>(g, v, e0, nel, L.X, true);
     const int npts = nel * S::NQ3;
     CT hv[45];
@@ -441,7 +526,7 @@ __device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__res
         for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
     }
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         if (!ONE) {
@@ -450,17 +535,18 @@ __device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__res
             for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
         }
         CT J[9];
-        point_J3<P, NQ>(L.RY, el, q, J);
+        point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
             CT s = 0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) s += hv[sym_index<9>(r, c)] * J[c];
-            L.RY[(el * 9 + r) * S::NQ3 + q] = s;
+            L.RY[(el * NR + r) * S::NQ3 + q] = s;
         }
+        if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
-    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
+    backward3<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
 }
 
 // ------------------------------------------------------------------------
@@ -475,7 +561,7 @@ __device__ inline void b3_apply(const Geom &g, const Tables &tb, const TT *__res
 constexpr int NC3 = 13;
 
 template <typename CT>
-__device__ inline void cof3(const CT *T, CT *C)
+__device__ __forceinline__ void cof3(const CT *T, CT *C)
 {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -487,7 +573,7 @@ __device__ inline void cof3(const CT *T, CT *C)
 }
 
 template <typename CT>
-__device__ inline void compact_action3(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
+__device__ __forceinline__ void compact_action3(const CT *T, CT ca, CT cb, CT cc, CT cd, const CT *M, CT *Y)
 {
     CT C[9];
     cof3(T, C);
@@ -511,7 +597,7 @@ __device__ inline void compact_action3(const CT *T, CT ca, CT cb, CT cc, CT cd, 
 
 // out = in W^{-1} (tr = false) or in W^{-T} (tr = true), D x D row-major.
 template <int D, typename CT>
-__device__ inline void mul_winv(const Target &t, const CT *in, CT *out, bool tr)
+__device__ __forceinline__ void mul_winv(const Target &t, const CT *in, CT *out, bool tr)
 {
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -526,7 +612,7 @@ __device__ inline void mul_winv(const Target &t, const CT *in, CT *out, bool tr)
 }
 
 template <int P, int NQ, typename TT>
-__device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
+__device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, TT *__restrict__ Q,
                                  double *__restrict__ bad, int e0, int nel)
 {
@@ -568,14 +654,15 @@ __device__ inline void b3_setupc(const Geom &g, const Tables &tb, const Target &
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
-template <int P, int NQ, typename TT, typename CT>
-__device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+__device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
                                  const TT *__restrict__ Q, const double *__restrict__ v,
                                  CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ>;
+    constexpr int NR = Planes3<LIM>::NR;
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;  // as in b3_apply
-    __shared__ Lds3<P, NQ, CT> L;
+    __shared__ Lds3<P, NQ, CT, NR> L;
     gather3<P, NQ>(g, v, e0, nel, L.X, true);
     const int npts = nel * S::NQ3;
     CT d[NC3];
@@ -586,7 +673,7 @@ __device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &
         for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
     }
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         if (!ONE) {
@@ -595,7 +682,7 @@ __device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &
             for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
         }
         CT J[9], Y[9];
-        point_J3<P, NQ>(L.RY, el, q, J);
+        point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
         if (tg.ideal) {
             compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
         } else {
@@ -605,36 +692,41 @@ __device__ inline void b3_applyc(const Geom &g, const Tables &tb, const Target &
             mul_winv<3, CT>(tg, Yt, Y, true);
         }
 #pragma unroll
-        for (int r = 0; r < 9; ++r) L.RY[(el * 9 + r) * S::NQ3 + q] = Y[r];
+        for (int r = 0; r < 9; ++r) L.RY[(el * NR + r) * S::NQ3 + q] = Y[r];
+        if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
-    backward3<P, NQ>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
+    backward3<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
 }
 
 // Hessian diagonal, element part (Sec. 3.4, last paragraph):
 //   d_a(i) = sum_q sum_{n,p} H[an,ap](q) dw_i/dxbar_n dw_i/dxbar_p,
 // contracted per (n,p) pair with the squared 1D tables BB, BG, GG.  The 18
 // needed entries H[an,ap] (3 components x 6 pairs n <= p, off-diagonal pairs
-// doubled) are first placed in LDS planes sQ[el][pair][a][q].
-template <int P, int NQ>
+// doubled) are first placed in LDS planes sQ[el][pair][a][q].  With the
+// limiting term a seventh "pair" holds 2 w_q lim, contracted with BB on every
+// axis (the diagonal of the mass-like term, eq. eq_pa_limiting).
+template <int P, int NQ, bool LIM = false>
 struct DiagLds3 {
     using S = S3<P, NQ>;
+    static constexpr int NPR = LIM ? 7 : 6;
     double T[3][NQ * S::NI];  // BB, BG, GG
-    double sQ[S::EPB * 18 * S::NQ3];
+    double sQ[S::EPB * NPR * 3 * S::NQ3];
     double U2[S::EPB * 3 * S::NI * NQ * NQ];
     double U1[S::EPB * 3 * S::NI * S::NI * NQ];
     double sD[S::EPB * 3 * S::NP];
 };
 
+// pair pr < 6: (n, p) = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2); pr = 6: value term
 __device__ constexpr int diag_pn(int pr) { return pr < 3 ? 0 : (pr < 5 ? 1 : 2); }
 __device__ constexpr int diag_pp(int pr) { return pr < 3 ? pr : (pr < 5 ? pr - 2 : 2); }
 
-template <int P, int NQ>
-__device__ inline void diag_contract3(const Tables &tb, const Geom &g, int e0, DiagLds3<P, NQ> &L,
-                                      int nel, double *__restrict__ dE)
+template <int P, int NQ, bool LIM>
+__device__ __forceinline__ void diag_contract3(const Tables &tb, const Geom &g, int e0,
+                                      DiagLds3<P, NQ, LIM> &L, int nel, double *__restrict__ dE)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, NQ3 = S::NQ3, NP = S::NP;
+    constexpr int NI = S::NI, NQ3 = S::NQ3, NP = S::NP, NPR = DiagLds3<P, NQ, LIM>::NPR;
     for (int k = threadIdx.x; k < NQ * NI; k += BLOCK) {
         const double b = tb.B[k], gg = tb.G[k];
         L.T[0][k] = b * b;
@@ -642,10 +734,12 @@ __device__ inline void diag_contract3(const Tables &tb, const Geom &g, int e0, D
         L.T[2][k] = gg * gg;
     }
     for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) L.sD[k] = 0.0;
-    for (int pr = 0; pr < 6; ++pr) {
+    for (int pr = 0; pr < NPR; ++pr) {
         const int n = diag_pn(pr), p = diag_pp(pr);
         // table index along axis k: number of derivative factors on that axis
-        const int t1 = (n == 0) + (p == 0), t2 = (n == 1) + (p == 1), t3 = (n == 2) + (p == 2);
+        const bool val = pr == 6;
+        const int t1 = val ? 0 : (n == 0) + (p == 0), t2 = val ? 0 : (n == 1) + (p == 1),
+                  t3 = val ? 0 : (n == 2) + (p == 2);
         __syncthreads();
         for (int idx = threadIdx.x; idx < nel * 3 * NI * NQ * NQ; idx += BLOCK) {
             const int q1 = idx % NQ;
@@ -655,7 +749,7 @@ __device__ inline void diag_contract3(const Tables &tb, const Geom &g, int e0, D
             const int i3 = r % NI;
             r /= NI;  // el*3 + a
             const int el = r / 3, a = r % 3;
-            const double *y = L.sQ + ((el * 6 + pr) * 3 + a) * NQ3 + q2 * NQ + q1;
+            const double *y = L.sQ + ((el * NPR + pr) * 3 + a) * NQ3 + q2 * NQ + q1;
             double s = 0.0;
 #pragma unroll
             for (int q3 = 0; q3 < NQ; ++q3) s += L.T[t3][q3 * NI + i3] * y[q3 * NQ * NQ];
@@ -693,11 +787,25 @@ __device__ inline void diag_contract3(const Tables &tb, const Geom &g, int e0, D
     }
 }
 
-template <int P, int NQ, typename TT>
-__device__ inline void b3_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H, double *__restrict__ dE, int e0, int nel)
+// the limiting pair's planes: 2 w_q lim for each component
+template <int P, int NQ, bool LIM>
+__device__ __forceinline__ void diag_lim3(const Tables &tb, const Geom &g, DiagLds3<P, NQ, LIM> &L, int el,
+                                 int q)
+{
+    if (!LIM) return;
+    constexpr int NQ3 = S3<P, NQ>::NQ3, NPR = DiagLds3<P, NQ, LIM>::NPR;
+    const double f = 2.0 * g.lim * qweight3<NQ>(tb, q);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L.sQ[((el * NPR + 6) * 3 + a) * NQ3 + q] = f;
+}
+
+template <int P, int NQ, typename TT, bool LIM = false>
+__device__ __forceinline__ void b3_diag(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+                               double *__restrict__ dE, int e0, int nel)
 {
     using S = S3<P, NQ>;
-    __shared__ DiagLds3<P, NQ> L;
+    constexpr int NPR = DiagLds3<P, NQ, LIM>::NPR;
+    __shared__ DiagLds3<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
@@ -707,21 +815,24 @@ __device__ inline void b3_diag(const Geom &g, const Tables &tb, const TT *__rest
             const double f = (n == p) ? 1.0 : 2.0;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                L.sQ[((el * 6 + pr) * 3 + a) * S::NQ3 + q] =
+                L.sQ[((el * NPR + pr) * 3 + a) * S::NQ3 + q] =
                     f * (double)h[sym_index<9>(a * 3 + n, a * 3 + p) * S::NQ3];
         }
+        diag_lim3<P, NQ, LIM>(tb, g, L, el, q);
     }
-    diag_contract3<P, NQ>(tb, g, e0, L, nel, dE);
+    diag_contract3<P, NQ, LIM>(tb, g, e0, L, nel, dE);
 }
 
 // Diagonal from compact data: within one component a the cofactor-derivative
 // term vanishes, so H[an,ap] = c_id (W^-1 W^-T)_np + c_tc (Tw_an Cw_ap +
 // Cw_an Tw_ap) + c_cc Cw_an Cw_ap with Tw = T W^{-T}, Cw = C W^{-T}.
-template <int P, int NQ, typename TT>
-__device__ inline void b3_diagc(const Geom &g, const Tables &tb, const Target &tg, const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+template <int P, int NQ, typename TT, bool LIM = false>
+__device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const Target &tg,
+                                const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
 {
     using S = S3<P, NQ>;
-    __shared__ DiagLds3<P, NQ> L;
+    constexpr int NPR = DiagLds3<P, NQ, LIM>::NPR;
+    __shared__ DiagLds3<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
@@ -759,34 +870,35 @@ __device__ inline void b3_diagc(const Geom &g, const Tables &tb, const Target &t
                 const double hv = cid * WW[n * 3 + p] +
                                   ctc * (Tw[a * 3 + n] * Cw[a * 3 + p] + Cw[a * 3 + n] * Tw[a * 3 + p]) +
                                   ccc * Cw[a * 3 + n] * Cw[a * 3 + p];
-                L.sQ[((el * 6 + pr) * 3 + a) * S::NQ3 + q] = f * hv;
+                L.sQ[((el * NPR + pr) * 3 + a) * S::NQ3 + q] = f * hv;
             }
         }
+        diag_lim3<P, NQ, LIM>(tb, g, L, el, q);
     }
-    diag_contract3<P, NQ>(tb, g, e0, L, nel, dE);
+    diag_contract3<P, NQ, LIM>(tb, g, e0, L, nel, dE);
 }
 
-
 // ------------------------------------------------------------------------
-// Kernel entry points: single mesh (grid over element blocks) and batched
-// (grid over a tile list of (slot, first element) with per-slot geometry,
-// target and offsets into packed pools).
+// Kernel entry points: single mesh (grid over element blocks; LIM selects the
+// variant with the limiting term) and batched (grid over a tile list of
+// (slot, first element) with per-slot geometry, target and offsets into
+// packed pools; no limiting term).
 // ------------------------------------------------------------------------
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_energy<P, NQ>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
+    b3_energy<P, NQ, LIM>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_gradient<P, NQ>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+    b3_gradient<P, NQ, LIM>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -797,12 +909,12 @@ __global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg, 
     b3_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_apply<P, NQ, TT, CT>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
+    b3_apply<P, NQ, TT, CT, LIM>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -813,28 +925,28 @@ __global__ __launch_bounds__(BLOCK) void k3_setupc(Geom g, Tables tb, Target tg,
     b3_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_applyc<P, NQ, TT, CT>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
+    b3_applyc<P, NQ, TT, CT, LIM>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__restrict__ H, double *__restrict__ dE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_diag<P, NQ, TT>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
+    b3_diag<P, NQ, TT, LIM>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_diagc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, double *__restrict__ dE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b3_diagc<P, NQ, TT>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
+    b3_diagc<P, NQ, TT, LIM>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ>

@@ -131,13 +131,19 @@ bool ops3_p4(int nq, Ops *out);
         o.epb = SZ<P, NQ>::EPB;                                                                  \
         o.energy = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w, \
                       const double *x, double *part) {                                          \
-            hipLaunchKernelGGL((K##_energy<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x,  \
-                               part);                                                           \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_energy<P, NQ, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, part); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_energy<P, NQ, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, part); \
+            }                                                                      \
         };                                                                                       \
         o.gradient = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
                         const Target &w, const double *x, double *gE, double *bad) {            \
-            hipLaunchKernelGGL((K##_gradient<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, g, t, w,   \
-                               x, gE, bad);                                                     \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_gradient<P, NQ, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, bad); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_gradient<P, NQ, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, bad); \
+            }                                                                      \
         };                                                                                       \
         o.setup64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w, \
                        const double *x, double *H, double *bad) {                                \
@@ -151,23 +157,35 @@ bool ops3_p4(int nq, Ops *out);
         };                                                                                       \
         o.apply64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const double *H, \
                        const double *v, double *yE) {                                            \
-            hipLaunchKernelGGL((K##_apply<P, NQ, double, double>), dim3(grid), dim3(BLOCK), 0,  \
-                               s, g, t, H, v, yE);                                              \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_apply<P, NQ, double, double, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, v, yE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_apply<P, NQ, double, double, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, v, yE); \
+            }                                                                      \
         };                                                                                       \
         o.apply32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const float *H,  \
                        const double *v, float *yE) {                                             \
-            hipLaunchKernelGGL((K##_apply<P, NQ, float, float>), dim3(grid), dim3(BLOCK), 0, s, \
-                               g, t, H, v, yE);                                                 \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_apply<P, NQ, float, float, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, v, yE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_apply<P, NQ, float, float, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, v, yE); \
+            }                                                                      \
         };                                                                                       \
         o.diag64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const double *H,  \
                       double *dE) {                                                              \
-            hipLaunchKernelGGL((K##_diag<P, NQ, double>), dim3(grid), dim3(BLOCK), 0, s, g, t,  \
-                               H, dE);                                                          \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_diag<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, dE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_diag<P, NQ, double, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, dE); \
+            }                                                                      \
         };                                                                                       \
         o.diag32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const float *H,   \
                       double *dE) {                                                              \
-            hipLaunchKernelGGL((K##_diag<P, NQ, float>), dim3(grid), dim3(BLOCK), 0, s, g, t,   \
-                               H, dE);                                                          \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_diag<P, NQ, float, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, dE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_diag<P, NQ, float, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, H, dE); \
+            }                                                                      \
         };                                                                                       \
         o.setupc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
                         const Target &w, const double *x, double *Q, double *bad) {             \
@@ -181,23 +199,35 @@ bool ops3_p4(int nq, Ops *out);
         };                                                                                       \
         o.applyc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
                         const Target &w, const double *Q, const double *v, double *yE) {        \
-            hipLaunchKernelGGL((K##_applyc<P, NQ, double, double>), dim3(grid), dim3(BLOCK), 0, \
-                               s, g, t, w, Q, v, yE);                                           \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_applyc<P, NQ, double, double, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, v, yE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_applyc<P, NQ, double, double, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, v, yE); \
+            }                                                                      \
         };                                                                                       \
         o.applyc32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,                \
                         const Target &w, const float *Q, const double *v, float *yE) {          \
-            hipLaunchKernelGGL((K##_applyc<P, NQ, float, float>), dim3(grid), dim3(BLOCK), 0,   \
-                               s, g, t, w, Q, v, yE);                                           \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_applyc<P, NQ, float, float, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, v, yE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_applyc<P, NQ, float, float, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, v, yE); \
+            }                                                                      \
         };                                                                                       \
         o.diagc64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,\
                        const double *Q, double *dE) {                                            \
-            hipLaunchKernelGGL((K##_diagc<P, NQ, double>), dim3(grid), dim3(BLOCK), 0, s, g, t, \
-                               w, Q, dE);                                                       \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_diagc<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, dE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_diagc<P, NQ, double, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, dE); \
+            }                                                                      \
         };                                                                                       \
         o.diagc32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,\
                        const float *Q, double *dE) {                                             \
-            hipLaunchKernelGGL((K##_diagc<P, NQ, float>), dim3(grid), dim3(BLOCK), 0, s, g, t,  \
-                               w, Q, dE);                                                       \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_diagc<P, NQ, float, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, dE); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_diagc<P, NQ, float, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, dE); \
+            }                                                                      \
         };                                                                                       \
         *out = o;                                                                                \
         return true;                                                                             \

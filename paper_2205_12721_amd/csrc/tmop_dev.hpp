@@ -27,6 +27,10 @@ struct Geom {
     const int32_t *e2n;    // general mesh connectivity or nullptr
     int ess_mode;          // 0 box boundary, 1 none, 2 mask
     const uint8_t *ess;    // [dim * nx] for mode 2
+    // limiting term (eq. eq_F_full, xi = |x - x0|^2 / delta^2): reference
+    // nodes x0 [dim * nx] and lim = coef det W / delta^2; lim = 0 means off
+    const double *x0;
+    double lim;
 };
 
 // 1D tables: B[q][i] = l_i(chi_q), G[q][i] = l_i'(chi_q), w[q] (Sec. 3.1, eq. eq_B_G_1D).
@@ -47,6 +51,19 @@ template <>
 __device__ inline double tabB<double>(const Tables &t, int k) { return t.B[k]; }
 template <>
 __device__ inline float tabB<float>(const Tables &t, int k) { return t.Bf[k]; }
+// 1D weight w[i] for a run-time i, selected with compile-time indices only:
+// indexing the by-value Tables argument with a run-time index would make the
+// compiler copy the whole structure to scratch memory.
+template <int NQ>
+__device__ __forceinline__ double tab_w(const Tables &t, int i)
+{
+    double w = 0.0;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        if (i == k) w = t.w[k];
+    return w;
+}
+
 template <typename CT>
 __device__ inline CT tabG(const Tables &t, int k);
 template <>

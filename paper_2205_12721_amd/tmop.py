@@ -93,6 +93,7 @@ SIGNATURES = {
                     ctypes.POINTER(ctypes.c_int)],
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
+    "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
     "tmop_pool_create": [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int, _P],
     "tmop_pool_destroy": [_P],
     "tmop_pool_request_bytes": [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
@@ -293,6 +294,11 @@ class Context:
         _check(lib().tmop_minres(self._h, self._vec(b), self._vec(out), int(max_its),
                                  float(rtol), int(bool(jacobi)), ctypes.byref(its)))
         return out, its.value
+
+    def set_limiting(self, x0=None, coef=1.0, delta=1.0):
+        """Add (or, with x0=None, remove) the limiting term coef*|x - x0|^2/delta^2."""
+        ptr = None if x0 is None else self._vec(x0)
+        _check(lib().tmop_set_limiting(self._h, ptr, float(coef), float(delta)))
 
     def set_timing(self, enable=True):
         _check(lib().tmop_set_timing(self._h, int(bool(enable))))
