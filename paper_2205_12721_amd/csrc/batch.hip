@@ -552,7 +552,7 @@ static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH 
     s.np = d == 3 ? (p + 1) * (p + 1) * (p + 1) : (p + 1) * (p + 1);
     s.S = s.storage ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
     const size_t tb = s.prec ? 4 : 8;
-    s.bytes = BNV * up256((size_t)s.ndof * 8) + up256((size_t)s.ne * s.nqe * s.S * tb) +
+    s.bytes = BNV * up256((size_t)s.ndof * 8) + up256((size_t)s.ne * qdata_stride(s.S, s.nqe, (int)tb) * tb) +
               up256((size_t)s.ne * d * s.np * 8);
     return TMOP_OK;
 }
@@ -1177,7 +1177,7 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
         o += up256((size_t)s.ndof * 8);
     }
     s.dev.H = base + o;
-    o += up256((size_t)s.ne * s.nqe * s.S * (s.prec ? 4 : 8));
+    o += up256((size_t)s.ne * qdata_stride(s.S, s.nqe, s.prec ? 4 : 8) * (s.prec ? 4 : 8));
     s.dev.eV = base + o;
     // copy the caller's nodes after the caller's stream has produced them
     hipEvent_t ev;

@@ -278,7 +278,7 @@ extern "C" int tmop_workspace_bytes(const tmop_mesh_desc *m, const tmop_params *
     const int d = m->dim;
     const int S = prm->hess_storage == TMOP_HESS_COMPACT ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
     const size_t tb = prm->precision == TMOP_MIXED ? 4 : 8;
-    size_t b = align256((size_t)ne * nqe * S * tb);
+    size_t b = align256((size_t)ne * qdata_stride(S, nqe, (int)tb) * tb);
     b += align256((size_t)ne * d * np * 8);
     b += align256(sizeof(double) * (3 * ((ne + 0) + 1024) + 64));
     b += 2 * align256((size_t)d * nx * 8);  // diag, minv
@@ -388,7 +388,7 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     // workspace
     const int S = c->storage == TMOP_HESS_COMPACT ? (d == 3 ? 13 : 8) : d * d * (d * d + 1) / 2;
     const size_t tbytes = c->precision == TMOP_MIXED ? 4 : 8;
-    c->H_bytes = (size_t)ne * nqe * S * tbytes;
+    c->H_bytes = (size_t)ne * qdata_stride(S, nqe, (int)tbytes) * tbytes;
     c->eV_bytes = (size_t)ne * d * np * 8;
     c->part_len = 3 * std::max(c->grid, 1024) + 64;
     hipError_t e = hipSuccess;

@@ -369,7 +369,7 @@ __device__ __forceinline__ void b2_setup(const Geom &g, const Tables &tb, const 
 #pragma unroll
             for (int k = 0; k < 10; ++k) Hp[k] = 0.0;
         }
-        TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
+        TT *h = H + (size_t)(e0 + el) * qdata_stride(10, S::NQ2, sizeof(TT)) + q;
 #pragma unroll
         for (int k = 0; k < 10; ++k) h[k * S::NQ2] = (TT)Hp[k];
     }
@@ -389,7 +389,7 @@ __device__ __forceinline__ void b2_apply(const Geom &g, const Tables &tb, const 
     forward2<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.RY, nel);
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
+        const TT *h = H + (size_t)(e0 + el) * qdata_stride(10, S::NQ2, sizeof(TT)) + q;
         CT hv[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) hv[k] = (CT)h[k * S::NQ2];
@@ -482,7 +482,7 @@ __device__ __forceinline__ void b2_setupc(const Geom &g, const Tables &tb, const
 #pragma unroll
             for (int k = 0; k < NC2; ++k) out[k] = 0.0;
         }
-        TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+        TT *h = Q + (size_t)(e0 + el) * qdata_stride(NC2, S::NQ2, sizeof(TT)) + q;
 #pragma unroll
         for (int k = 0; k < NC2; ++k) h[k * S::NQ2] = (TT)out[k];
     }
@@ -503,7 +503,7 @@ __device__ __forceinline__ void b2_applyc(const Geom &g, const Tables &tb, const
     forward2<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.RY, nel);
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+        const TT *h = Q + (size_t)(e0 + el) * qdata_stride(NC2, S::NQ2, sizeof(TT)) + q;
         CT d[NC2];
 #pragma unroll
         for (int k = 0; k < NC2; ++k) d[k] = (CT)h[k * S::NQ2];
@@ -606,7 +606,7 @@ __device__ __forceinline__ void b2_diag(const Geom &g, const Tables &tb, const T
     __shared__ DiagLds2<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const TT *h = H + (size_t)(e0 + el) * 10 * S::NQ2 + q;
+        const TT *h = H + (size_t)(e0 + el) * qdata_stride(10, S::NQ2, sizeof(TT)) + q;
 #pragma unroll
         for (int pr = 0; pr < 3; ++pr) {
             const int n = pr == 2 ? 1 : 0, p = pr == 0 ? 0 : 1;
@@ -630,7 +630,7 @@ __device__ __forceinline__ void b2_diagc(const Geom &g, const Tables &tb, const 
     __shared__ DiagLds2<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
-        const TT *h = Q + (size_t)(e0 + el) * NC2 * S::NQ2 + q;
+        const TT *h = Q + (size_t)(e0 + el) * qdata_stride(NC2, S::NQ2, sizeof(TT)) + q;
         double T[4], Tw[4], Cw[4], WW[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) T[k] = (double)h[k * S::NQ2];

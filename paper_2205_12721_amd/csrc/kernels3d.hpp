@@ -85,41 +85,64 @@ __device__ __forceinline__ int node3(const Geom &g, int e, int i1, int i2, int i
 
 // Gather 3 components of a global vector into X for the block's elements.
 // masked: fixed DoFs read as zero (the P of H_c = P H P + (I - P)); sub:
-// a vector subtracted entry by entry (x - x0 of the limiting term).  The
-// loop has a compile-time trip count so that all of a lane's loads are
-// issued before the first one is waited for.
-template <int P, int NQ, typename CT>
-__device__ __forceinline__ void gather3(const Geom &g, const double *__restrict__ vec, int e0, int nel,
-                               CT *sX, bool masked, const double *__restrict__ sub = nullptr)
-{
-    using S = S3<P, NQ>;
-    constexpr int NI = S::NI, NP = S::NP;
-    constexpr int NIT = (S::EPB * 3 * NP + BLOCK - 1) / BLOCK;
-    const int n = nel * 3 * NP;
+// a vector subtracted entry by entry (x - x0 of the limiting term).  Split in
+// a load phase (registers) and a store phase (LDS) so that a caller can issue
+// other loads in between; the loop has a compile-time trip count so that all
+// of a lane's loads are issued before the first one is waited for.
+template <int P, int NQ>
+struct Gath3 {
+    static constexpr int NIT = (S3<P, NQ>::EPB * 3 * S3<P, NQ>::NP + BLOCK - 1) / BLOCK;
     double val[NIT];
     bool fix[NIT];
+};
+
+template <int P, int NQ>
+__device__ __forceinline__ void gather3_load(const Geom &g, const double *__restrict__ vec, int e0,
+                                             int nel, bool masked, Gath3<P, NQ> &r,
+                                             const double *__restrict__ sub = nullptr)
+{
+    using S = S3<P, NQ>;
+    constexpr int NI = S::NI, NP = S::NP, NIT = Gath3<P, NQ>::NIT;
+    const int n = nel * 3 * NP;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = threadIdx.x + it * BLOCK;
-        val[it] = 0.0;
-        fix[it] = false;
+        r.val[it] = 0.0;
+        r.fix[it] = false;
         if (idx < n) {
             const int i = idx % NP;
-            const int r = idx / NP;  // el*3 + c
-            const int c = r % 3, el = r / 3;
+            const int rr = idx / NP;  // el*3 + c
+            const int c = rr % 3, el = rr / 3;
             const int i1 = i % NI, i2 = (i / NI) % NI, i3 = i / (NI * NI);
             int gx, gy, gz;
             const int node = node3<P>(g, e0 + el, i1, i2, i3, gx, gy, gz);
-            val[it] = vec[(size_t)c * g.nx + node];
-            if (sub) val[it] -= sub[(size_t)c * g.nx + node];
-            fix[it] = masked && is_fixed(g, c, node, gx, gy, gz);
+            r.val[it] = vec[(size_t)c * g.nx + node];
+            if (sub) r.val[it] -= sub[(size_t)c * g.nx + node];
+            r.fix[it] = masked && is_fixed(g, c, node, gx, gy, gz);
         }
     }
+}
+
+template <int P, int NQ, typename CT>
+__device__ __forceinline__ void gather3_store(const Gath3<P, NQ> &r, int nel, CT *sX)
+{
+    constexpr int NIT = Gath3<P, NQ>::NIT;
+    const int n = nel * 3 * S3<P, NQ>::NP;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = threadIdx.x + it * BLOCK;
-        if (idx < n) sX[idx] = fix[it] ? (CT)0 : (CT)val[it];
+        if (idx < n) sX[idx] = r.fix[it] ? (CT)0 : (CT)r.val[it];
     }
+}
+
+template <int P, int NQ, typename CT>
+__device__ __forceinline__ void gather3(const Geom &g, const double *__restrict__ vec, int e0,
+                                        int nel, CT *sX, bool masked,
+                                        const double *__restrict__ sub = nullptr)
+{
+    Gath3<P, NQ> r;
+    gather3_load<P, NQ>(g, vec, e0, nel, masked, r, sub);
+    gather3_store<P, NQ, CT>(r, nel, sX);
 }
 
 // Forward sweeps X -> R1 -> R2 -> RY (J at every point, plane el*NR + c*3 + b;
@@ -343,6 +366,65 @@ __device__ __forceinline__ double point_weight3(const Tables &tb, const Target &
 }
 
 // ------------------------------------------------------------------------
+// Quadrature data layout per element (hex kernels): NS values per point in
+// runs of VEC = 16 / sizeof(TT) consecutive values per point, [run][q][VEC],
+// then the NS % VEC remaining values as plain planes [s][q]; element blocks
+// of qdata_stride(NS, NQT, sizeof(TT)) values.  A lane reads or writes VEC
+// values of its point with one 16-byte access, and the lanes of a wave cover
+// consecutive 16-byte words.
+// ------------------------------------------------------------------------
+template <typename TT>
+struct alignas(16) Vec16 {
+    TT v[16 / sizeof(TT)];
+};
+
+template <typename TT, int NS, int NQT>
+struct QLay {
+    static constexpr int VEC = 16 / sizeof(TT);
+    static constexpr int NV = NS / VEC;    // full runs
+    static constexpr int TAIL = NV * VEC;  // first value stored in a plain plane
+    static constexpr long STRIDE = qdata_stride(NS, NQT, sizeof(TT));
+};
+
+template <typename TT, int NS, int NQT>
+__device__ __forceinline__ void qdata_load(const TT *__restrict__ he, int q, TT *out)
+{
+    using L = QLay<TT, NS, NQT>;
+#pragma unroll
+    for (int r = 0; r < L::NV; ++r) {
+        const Vec16<TT> w = *(const Vec16<TT> *)(he + ((long)r * NQT + q) * L::VEC);
+#pragma unroll
+        for (int k = 0; k < L::VEC; ++k) out[r * L::VEC + k] = w.v[k];
+    }
+#pragma unroll
+    for (int s = L::TAIL; s < NS; ++s) out[s] = he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q];
+}
+
+template <typename TT, int NS, int NQT>
+__device__ __forceinline__ void qdata_store(TT *__restrict__ he, int q, const TT *in)
+{
+    using L = QLay<TT, NS, NQT>;
+#pragma unroll
+    for (int r = 0; r < L::NV; ++r) {
+        Vec16<TT> w;
+#pragma unroll
+        for (int k = 0; k < L::VEC; ++k) w.v[k] = in[r * L::VEC + k];
+        *(Vec16<TT> *)(he + ((long)r * NQT + q) * L::VEC) = w;
+    }
+#pragma unroll
+    for (int s = L::TAIL; s < NS; ++s) he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q] = in[s];
+}
+
+// one value s (diagonal kernels read a subset)
+template <typename TT, int NS, int NQT>
+__device__ __forceinline__ TT qdata_at(const TT *__restrict__ he, int q, int s)
+{
+    using L = QLay<TT, NS, NQT>;
+    return s < L::TAIL ? he[((long)(s / L::VEC) * NQT + q) * L::VEC + s % L::VEC]
+                       : he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q];
+}
+
+// ------------------------------------------------------------------------
 // Element bodies
 // ------------------------------------------------------------------------
 
@@ -469,7 +551,7 @@ __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, con
 }
 
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
-// element-major [e][45][NQ^3] so that each entry is one coalesced plane.
+// element-major in the 16-byte-run layout of qdata_store.
 template <int P, int NQ, typename TT>
 __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const Target &tg,
                                 const double *__restrict__ x, TT *__restrict__ H,
@@ -492,9 +574,11 @@ __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const 
 #pragma unroll
             for (int k = 0; k < 45; ++k) Hp[k] = 0.0;
         }
-        TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
+        using QL = QLay<TT, 45, S::NQ3>;
+        TT hs[45];
 #pragma unroll
-        for (int k = 0; k < 45; ++k) h[k * S::NQ3] = (TT)Hp[k];
+        for (int k = 0; k < 45; ++k) hs[k] = (TT)Hp[k];
+        qdata_store<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QL::STRIDE, q, hs);
     }
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
@@ -516,24 +600,27 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
     // sweeps and stays in flight behind them (barriers wait on LDS only)
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;
     __shared__ Lds3<P, NQ, CT, NR> L;
-    gather3<P, NQ>(g, v, e0, nel, L.X, true);
+    // v loads first, then the tensor loads, then v to LDS: waiting for v
+    // leaves the tensor loads in flight
+    Gath3<P, NQ> gv;
+    gather3_load<P, NQ>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
-    CT hv[45];
+    TT hraw[45];
     if (ONE && threadIdx.x < npts) {
         const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
-        const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
-#pragma unroll
-        for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
+        qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q, hraw);
     }
+    gather3_store<P, NQ, CT>(gv, nel, L.X);
     __syncthreads();
     forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        if (!ONE) {
-            const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
+        if (!ONE)
+            qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q,
+                                       hraw);
+        CT hv[45];
 #pragma unroll
-            for (int k = 0; k < 45; ++k) hv[k] = (CT)h[k * S::NQ3];
-        }
+        for (int k = 0; k < 45; ++k) hv[k] = (CT)hraw[k];
         CT J[9];
         point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
 #pragma unroll
@@ -551,8 +638,8 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
 
 // ------------------------------------------------------------------------
 // Compact quadrature data: per point T = A W^{-1} (9 values) and the four
-// weighted metric coefficients z c_id, z c_tc, z c_cc, z c_dc (layout
-// [e][13][q]).  The fourth-order tensor is then applied in closed form:
+// weighted metric coefficients z c_id, z c_tc, z c_cc, z c_dc (13 values per
+// point, in the layout of qdata_store).  The fourth-order tensor is then applied in closed form:
 //   d2mu : M = c_id M + c_tc (T (C:M) + C (T:M)) + c_cc C (C:M) + c_dc dC[M],
 // with C = cof T and dC[M] the derivative of the cofactor at T in direction M
 // (the bilinear part of cof(T + M)).  Same result as the stored tensor,
@@ -646,9 +733,10 @@ __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const
 #pragma unroll
             for (int k = 0; k < NC3; ++k) out[k] = 0.0;
         }
-        TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+        TT hs[NC3];
 #pragma unroll
-        for (int k = 0; k < NC3; ++k) h[k * S::NQ3] = (TT)out[k];
+        for (int k = 0; k < NC3; ++k) hs[k] = (TT)out[k];
+        qdata_store<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hs);
     }
     const double b = block_sum(nbad, red);
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
@@ -663,24 +751,25 @@ __device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const
     constexpr int NR = Planes3<LIM>::NR;
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;  // as in b3_apply
     __shared__ Lds3<P, NQ, CT, NR> L;
-    gather3<P, NQ>(g, v, e0, nel, L.X, true);
+    Gath3<P, NQ> gv;
+    gather3_load<P, NQ>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
-    CT d[NC3];
+    TT draw[NC3];
     if (ONE && threadIdx.x < npts) {
         const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
-        const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
-#pragma unroll
-        for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
+        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, draw);
     }
+    gather3_store<P, NQ, CT>(gv, nel, L.X);
     __syncthreads();
     forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        if (!ONE) {
-            const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+        if (!ONE)
+            qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q,
+                                        draw);
+        CT d[NC3];
 #pragma unroll
-            for (int k = 0; k < NC3; ++k) d[k] = (CT)h[k * S::NQ3];
-        }
+        for (int k = 0; k < NC3; ++k) d[k] = (CT)draw[k];
         CT J[9], Y[9];
         point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
         if (tg.ideal) {
@@ -808,7 +897,7 @@ __device__ __forceinline__ void b3_diag(const Geom &g, const Tables &tb, const T
     __shared__ DiagLds3<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const TT *h = H + (size_t)(e0 + el) * 45 * S::NQ3 + q;
+        const TT *h = H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE;
 #pragma unroll
         for (int pr = 0; pr < 6; ++pr) {
             const int n = diag_pn(pr), p = diag_pp(pr);
@@ -816,7 +905,7 @@ __device__ __forceinline__ void b3_diag(const Geom &g, const Tables &tb, const T
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 L.sQ[((el * NPR + pr) * 3 + a) * S::NQ3 + q] =
-                    f * (double)h[sym_index<9>(a * 3 + n, a * 3 + p) * S::NQ3];
+                    f * (double)qdata_at<TT, 45, S::NQ3>(h, q, sym_index<9>(a * 3 + n, a * 3 + p));
         }
         diag_lim3<P, NQ, LIM>(tb, g, L, el, q);
     }
@@ -835,11 +924,12 @@ __device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const 
     __shared__ DiagLds3<P, NQ, LIM> L;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        const TT *h = Q + (size_t)(e0 + el) * NC3 * S::NQ3 + q;
+        TT hr[NC3];
+        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hr);
         double T[9], C[9], Tw[9], Cw[9], WW[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) T[k] = (double)h[k * S::NQ3];
-        const double cid = h[9 * S::NQ3], ctc = h[10 * S::NQ3], ccc = h[11 * S::NQ3];
+        for (int k = 0; k < 9; ++k) T[k] = (double)hr[k];
+        const double cid = hr[9], ctc = hr[10], ccc = hr[11];
         cof3(T, C);
         if (tg.ideal) {
 #pragma unroll

@@ -179,6 +179,14 @@ __device__ inline double block_min(double v, double *red)
 //   d2mu  = c_id Id + c_tc (T (x) C + C (x) T) + c_cc C (x) C + c_dc dC/dT
 // ------------------------------------------------------------------------
 
+// Quadrature data of one element: ns values per point at nqt points, the
+// element's block padded to a multiple of 16 bytes so that every element
+// starts 16-byte aligned (the hex kernels read it with 16-byte loads).
+inline __host__ __device__ constexpr long qdata_stride(int ns, int nqt, int tbytes)
+{
+    return ((long)ns * nqt + 16 / tbytes - 1) / (16 / tbytes) * (16 / tbytes);
+}
+
 // Metrics with kernels: 2, 7, 9, 55 in 2D; 303, 55 in 3D.
 inline __host__ __device__ bool metric_supported(int dim, int metric)
 {
