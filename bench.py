@@ -27,6 +27,33 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
+# HBM bytes per Hessian action (element kernel + gather), from two rocprofv3
+# --pmc runs of the standalone action (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by the same counter's reading for a device copy of
+# known size.  Valid only for the kernel sources they were taken on: the
+# entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
+# reported as null once they differ.  Summary and commands:
+# profiles/hessian_apply_traffic_24cube_q3.md.
+TRAFFIC = {}
+
+
+def csrc_sha256():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2205_12721_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(variant, workload):
+    t = TRAFFIC.get((workload, variant))
+    if not t or t["csrc_sha256"] != csrc_sha256():
+        return None
+    return t["bytes"]
+
 WORKLOADS = {
     # name: (inputs config, dim, n, p, nq)
     "c2": ("c2", 3, 24, 3, 5),
@@ -79,10 +106,19 @@ def run_steps(ctx, x, x0, steps, n_minres):
     return acc
 
 
-def roofline(ne, nqe, S, ndof, tbytes, acc):
-    napp = max(acc["n_apply"], 1)
-    t_app = acc["t_apply_ms"] / napp / 1e3
-    t_elem = acc["t_apply_elem_ms"] / napp / 1e3
+def time_actions(ctx, x, v, reps):
+    """Standalone Hessian actions after one setup at x: 3 warm-up actions, then
+    (element kernel mean, whole-action mean) in ms over `reps` actions each."""
+    import torch
+    y = torch.empty_like(v)
+    ctx.hessian_setup(x)
+    ctx.time_apply(v, y, 3)
+    return ctx.time_apply(v, y, reps)
+
+
+def roofline(ne, nqe, S, ndof, tbytes, elem_ms, total_ms, traffic=None):
+    t_app = total_ms / 1e3
+    t_elem = elem_ms / 1e3
     b_alg = ne * nqe * S * tbytes + 2 * ndof * 8          # tensor + v in + y out
     b_elem = ne * nqe * S * tbytes + ndof * 8             # tensor + v in
     achieved = b_alg / t_app / 1e9
@@ -92,12 +128,11 @@ def roofline(ne, nqe, S, ndof, tbytes, acc):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "kernel": "Hessian action = element kernel k3_apply + node gather k_gather_box",
+        "traffic": traffic,
+        "kernel": "Hessian action = element kernel k3_apply + node gather k_gather",
         "alg_bytes_per_launch": int(b_alg),
         "avg_us": round(t_app * 1e6, 2),
         "elem_avg_us": round(t_elem * 1e6, 2),
-        "gather_avg_us": round((t_app - t_elem) * 1e6, 2),
         "elem_achieved_GBs": round(b_elem / t_elem / 1e9, 1),
     }
 
@@ -270,6 +305,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--minres", type=int, default=20)
+    ap.add_argument("--apply-reps", type=int, default=30)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -318,14 +354,17 @@ def main():
     ne = int(np.prod([n] * dim))
     nqe = nq ** dim
 
-    # FP64
+    v0 = torch.as_tensor(inputs.gaussian_vector(ctx.ndof, inputs.CONFIGS[cname]["vec_seed"])).cuda()
+
+    # FP64: Newton steps (the whole path), then standalone actions for the metric
     run_steps(ctx, x, x0, args.warmup, args.minres)
     log("[bench] fp64 warmup done")
     acc = run_steps(ctx, x, x0, args.steps, args.minres)
     log("[bench] fp64 timed steps done")
     napp = max(acc["n_apply"], 1)
-    gdofs = ctx.ndof * acc["n_apply"] / (acc["t_apply_ms"] / 1e3) / 1e9
-    rf = roofline(ne, nqe, S, ctx.ndof, 8, acc)
+    elem_ms, tot_ms = time_actions(ctx, x0, v0, args.apply_reps)
+    gdofs = ctx.ndof / (tot_ms / 1e3) / 1e9
+    rf = roofline(ne, nqe, S, ctx.ndof, 8, elem_ms, tot_ms, traffic_for("tensor_fp64", cname))
     ms_step = acc["wall_s"] / args.steps * 1e3
 
     out = {
@@ -348,12 +387,15 @@ def main():
                         "2D quad box %d^2, Q%d, %d^2 points, mu_2" % (n, p, nq),
             "elements": ne, "order": p, "nq1d": nq, "dofs": ctx.ndof,
             "minres_per_step": args.minres, "mesh_seed": inputs.CONFIGS[cname]["seed"],
+            "actions_timed": args.apply_reps,
         },
         "roofline": rf,
         "step_gdof_s": round(ctx.ndof * args.minres / (ms_step / 1e3) / 1e9, 3),
         "phases_ms_per_step": {k: round(acc[k] / args.steps, 3)
                                for k in ("t_setup_ms", "t_minres_ms", "t_linesearch_ms")},
-        "apply_us": round(acc["t_apply_ms"] / napp * 1e3, 2),
+        # the action inside MINRES: element kernel + the gather fused with the
+        # first Lanczos vector update (HIP events around each, during the steps)
+        "apply_in_minres_us": round(acc["t_apply_ms"] / napp * 1e3, 2),
     }
 
     variants = [("compact", "fp64")]
@@ -365,14 +407,17 @@ def main():
         run_steps(cv, x, x0, args.warmup, args.minres)
         av = run_steps(cv, x, x0, args.steps, args.minres)
         log("[bench] %s %s timed steps done" % (storage, prec))
-        gv = cv.ndof * av["n_apply"] / (av["t_apply_ms"] / 1e3) / 1e9
+        em, tm = time_actions(cv, x0, v0, args.apply_reps)
         sv = S if storage == "tensor" else (13 if dim == 3 else 8)
-        out["%s_%s" % (storage, prec)] = {
-            "value": round(gv, 3), "unit": "GDoF/s",
+        key = "%s_%s" % (storage, prec)
+        out[key] = {
+            "value": round(cv.ndof / (tm / 1e3) / 1e9, 3), "unit": "GDoF/s",
             "dtype": "f64" if prec == "fp64" else "f32 action / f64 rest",
             "storage": storage, "values_per_point": sv,
             "ms_per_step": round(av["wall_s"] / args.steps * 1e3, 3),
-            "roofline": roofline(ne, nqe, sv, cv.ndof, 8 if prec == "fp64" else 4, av),
+            "apply_in_minres_us": round(av["t_apply_ms"] / max(av["n_apply"], 1) * 1e3, 2),
+            "roofline": roofline(ne, nqe, sv, cv.ndof, 8 if prec == "fp64" else 4, em, tm,
+                                 traffic_for(key, cname)),
         }
         cv.close()
 

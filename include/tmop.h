@@ -286,10 +286,12 @@ int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params 
 /* Timing helpers                                                          */
 /* ---------------------------------------------------------------------- */
 
-/* Run the Hessian action n times on the context's stream and return the
- * mean device time per call in milliseconds, measured with HIP events
- * recorded on that stream around the calls (elem_ms: element kernel only,
- * total_ms: element kernel plus the node gather). */
+/* Time the Hessian action on the context's stream with HIP events recorded
+ * on that stream (milliseconds per action): elem_ms is the mean time of the
+ * element kernel over n actions with events around each kernel; total_ms is
+ * the mean time of a whole action (element kernel plus node gather) over n
+ * further actions run back to back, events only before and after the run.
+ * 2n actions in all; y_dev receives the result. */
 int tmop_time_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev, int n, double *elem_ms,
                     double *total_ms);
 
