@@ -979,7 +979,7 @@ template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_energy<P, NQ, LIM>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
@@ -987,7 +987,7 @@ template <int P, int NQ, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_gradient<P, NQ, LIM>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
@@ -995,7 +995,7 @@ template <int P, int NQ, typename TT>
 __global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
 }
 
@@ -1003,7 +1003,7 @@ template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_apply<P, NQ, TT, CT, LIM>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
 }
 
@@ -1011,7 +1011,7 @@ template <int P, int NQ, typename TT>
 __global__ __launch_bounds__(BLOCK) void k3_setupc(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
 }
 
@@ -1019,7 +1019,7 @@ template <int P, int NQ, typename TT, typename CT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_applyc<P, NQ, TT, CT, LIM>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
 }
 
@@ -1027,7 +1027,7 @@ template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__restrict__ H, double *__restrict__ dE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_diag<P, NQ, TT, LIM>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
 }
 
@@ -1035,7 +1035,7 @@ template <int P, int NQ, typename TT, bool LIM>
 __global__ __launch_bounds__(BLOCK) void k3_diagc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, double *__restrict__ dE)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
-    const int e0 = blockIdx.x * EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_diagc<P, NQ, TT, LIM>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
 }
 

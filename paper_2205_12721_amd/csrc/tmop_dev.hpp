@@ -125,6 +125,18 @@ __device__ inline bool is_fixed(const Geom &g, int c, int node, int gx, int gy, 
     return box_boundary(g, gx, gy, gz);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i % 8), each with its own L2.  Renumbering them so that every XCD works
+// on one contiguous range of logical blocks keeps neighbouring elements, which
+// share nodes, in one L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int i, int n)
+{
+    constexpr int NXCD = 8;
+    const int q = n / NXCD, r = n % NXCD;
+    const int x = i % NXCD, k = i / NXCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // ------------------------------------------------------------------------
 // Block reductions (deterministic order)
 // ------------------------------------------------------------------------

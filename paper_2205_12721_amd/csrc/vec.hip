@@ -20,7 +20,8 @@ __global__ __launch_bounds__(VBLOCK) void k_gather(Geom g, const int32_t *__rest
                                                    const double *__restrict__ src)
 {
     const int total = DIM * g.nx;
-    for (int idx = blockIdx.x * VBLOCK + threadIdx.x; idx < total; idx += gridDim.x * VBLOCK) {
+    for (int idx = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; idx < total;
+         idx += gridDim.x * VBLOCK) {
         bool fixed;
         const double v = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
         out[idx] = fixed ? (fix_mode == 0 ? 0.0 : (fix_mode == 1 ? 1.0 : src[idx])) : v;
@@ -305,7 +306,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_l1(Geom g, const int32_t *
     const double cr = j >= 1 ? st->beta / st->oldb : 0.0;
     const int total = DIM * g.nx;
     double s = 0.0;
-    for (int idx = blockIdx.x * VBLOCK + threadIdx.x; idx < total; idx += gridDim.x * VBLOCK) {
+    for (int idx = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; idx < total;
+         idx += gridDim.x * VBLOCK) {
         bool fixed;
         const double a = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
         const double vi = v[idx];
