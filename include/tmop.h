@@ -272,10 +272,18 @@ int tmop_pool_info(tmop_pool *pool, size_t *used_bytes, size_t *budget_bytes, in
 /* Enable (default) or disable HIP-graph replay of the MINRES iterations. */
 int tmop_pool_set_graph(tmop_pool *pool, int enable);
 
+/* Autotuner of the pool: for every kernel class with resident meshes, time
+ * the batched Hessian action of each tile shape (as tmop_autotune) over
+ * `reps` launches on the pool's stream, keep the fastest for the class and
+ * record it for the process.  Call between steps (it overwrites the slots'
+ * element scratch only); results are unchanged by the tile shape. */
+int tmop_pool_autotune(tmop_pool *pool, int reps);
+
 /* Thread-local description of the last pool error. */
 const char *tmop_pool_last_error(void);
 
-/* Solve count independent meshes together (a pool sized to fit them all):
+/* Solve count independent meshes together (a pool sized to fit them all,
+ * Hessian-action tile shapes autotuned per kernel class after admission):
  * x_devs[k] holds mesh k's nodes on entry and the optimised nodes on return;
  * reps[k] its report.  Returns the first error, if any. */
 int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params *prms,
@@ -294,6 +302,24 @@ int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params 
  * 2n actions in all; y_dev receives the result. */
 int tmop_time_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev, int n, double *elem_ms,
                     double *total_ms);
+
+/* Autotuner of the Hessian action's tile shape (elements per workgroup):
+ * times the element kernel of the action for each tile shape the class has
+ * (half, base and double the base max(1, 256 / n_q^d) elements per workgroup,
+ * where they fit the LDS) over `reps` launches on the context's stream, keeps the
+ * fastest for this context and records it for the class (dim, p, n_q,
+ * storage, precision), so that contexts and pools created later in the
+ * process start with it.  Needs tmop_hessian_setup; leaves y_dev = H v.
+ * The tile shape changes no result (every element is computed alike).
+ * epb (may be NULL): the chosen elements per workgroup. */
+int tmop_autotune(tmop_ctx *ctx, const double *v_dev, double *y_dev, int reps, int *epb);
+
+/* Elements per workgroup of the context's current Hessian-action tile. */
+int tmop_tile_epb(tmop_ctx *ctx, int *epb);
+
+/* Use the Hessian-action tile with epb elements per workgroup (one of the
+ * shapes tmop_autotune considers), else TMOP_ERR_UNSUPPORTED. */
+int tmop_set_tile(tmop_ctx *ctx, int epb);
 
 /* Limiting term (Sec. 2.2, eq. eq_F_full, second integral; Sec. 3.5, eq.
  * eq_pa_limiting): adds coef * sum_E int_{E_t} |x - x0|^2 / delta^2 to F, with

@@ -485,6 +485,12 @@ struct ClassH {
     Tile *d_tiles = nullptr;
     int cap = 0;
     int pbase = 0;
+    // Hessian action tile shape (index into BOps::epb_t) and, when it is not
+    // the base shape, its own tile list
+    int tile = 1;
+    std::vector<Tile> atiles;
+    Tile *d_atiles = nullptr;
+    int acap = 0;
 };
 
 enum { PH_NEW = 0, PH_ITER = 1, PH_DONE = 2 };
@@ -647,7 +653,10 @@ static void invalidate_graph(tmop_pool *P)
 static int pool_rebuild(tmop_pool *P)
 {
     invalidate_graph(P);
-    for (auto &kv : P->classes) kv.second.tiles.clear();
+    for (auto &kv : P->classes) {
+        kv.second.tiles.clear();
+        kv.second.atiles.clear();
+    }
     // element tiles per class
     for (int si = 0; si < P->max_slots; ++si) {
         SlotH &s = P->slots[si];
@@ -661,10 +670,16 @@ static int pool_rebuild(tmop_pool *P)
                 return pfail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d)");
             if (internal_tables(s.p, s.nq, &c.tb) != TMOP_OK)
                 return pfail(TMOP_ERR_INVALID_ARG, "bad order / quadrature");
+            // start from the tile shape recorded for the class by the autotuner
+            const int tt = tuned_tile(s.dim, s.p, s.nq, s.storage ? TMOP_HESS_COMPACT : TMOP_HESS_TENSOR,
+                                      s.prec ? TMOP_MIXED : TMOP_FP64);
+            if (tt >= 0 && c.bops.epb_t[tt] > 0) c.tile = tt;
             it = P->classes.emplace(k, c).first;
         }
         ClassH &c = it->second;
         for (int e = 0; e < s.ne; e += c.bops.epb) c.tiles.push_back(Tile{si, e});
+        if (c.tile != 1)
+            for (int e = 0; e < s.ne; e += c.bops.epb_t[c.tile]) c.atiles.push_back(Tile{si, e});
     }
     int pb = 0;
     P->rg.assign(P->max_slots, SlotRange{0, 0, 1, 0, 0});
@@ -679,6 +694,14 @@ static int pool_rebuild(tmop_pool *P)
             PHIP(hipMalloc((void **)&c.d_tiles, sizeof(Tile) * c.cap));
         }
         if (nt) PHIP(hipMemcpyAsync(c.d_tiles, c.tiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice, P->s));
+        const int na = (int)c.atiles.size();
+        if (na > c.acap) {
+            hipFree(c.d_atiles);
+            c.d_atiles = nullptr;
+            c.acap = std::max(na, 2 * c.acap);
+            PHIP(hipMalloc((void **)&c.d_atiles, sizeof(Tile) * c.acap));
+        }
+        if (na) PHIP(hipMemcpyAsync(c.d_atiles, c.atiles.data(), sizeof(Tile) * na, hipMemcpyHostToDevice, P->s));
         for (int t = 0; t < nt; ++t) {
             SlotRange &r = P->rg[c.tiles[t].slot];
             if (r.ecount == 0) {
@@ -740,6 +763,11 @@ static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
         const int nt = (int)c.tiles.size();
         if (!nt) continue;
         const int st = c.key.storage, pr = c.key.prec;
+        if (which == 3 && c.tile != 1) {
+            c.bops.apply_t[st][pr][c.tile]((int)c.atiles.size(), P->s, c.tb, c.d_atiles, P->d_slots,
+                                          gate, vin, nullptr);
+            continue;
+        }
         BLaunch f = which == 0   ? c.bops.energy
                     : which == 1 ? c.bops.gradient
                     : which == 2 ? c.bops.setup[st][pr]
@@ -1086,7 +1114,10 @@ extern "C" int tmop_pool_destroy(tmop_pool *P)
     if (!P) return TMOP_OK;
     if (P->s) hipStreamSynchronize(P->s);
     invalidate_graph(P);
-    for (auto &kv : P->classes) hipFree(kv.second.d_tiles);
+    for (auto &kv : P->classes) {
+        hipFree(kv.second.d_tiles);
+        hipFree(kv.second.d_atiles);
+    }
     hipFree(P->arena);
     hipFree(P->d_slots);
     hipFree(P->d_rg);
@@ -1259,6 +1290,63 @@ extern "C" int tmop_pool_info(tmop_pool *P, size_t *used_bytes, size_t *budget_b
     return TMOP_OK;
 }
 
+extern "C" int tmop_pool_autotune(tmop_pool *P, int reps)
+{
+    if (!P || reps <= 0) return pfail(TMOP_ERR_INVALID_ARG, "bad argument");
+    if (P->dirty) PCHK(pool_rebuild(P));
+    hipEvent_t e0, e1;
+    PHIP(hipEventCreate(&e0));
+    PHIP(hipEventCreate(&e1));
+    for (auto &kv : P->classes) {
+        ClassH &c = kv.second;
+        if (c.tiles.empty()) continue;
+        const int st = c.key.storage, pr = c.key.prec;
+        int best = -1;
+        float tbest = 0.f;
+        for (int t = 0; t < 3; ++t) {
+            if (c.bops.epb_t[t] == 0) continue;
+            const Tile *dl = c.d_tiles;
+            int n = (int)c.tiles.size();
+            if (t != 1) {
+                // tile list of this shape for the class's resident meshes
+                std::vector<Tile> tl;
+                for (const Tile &b : c.tiles)
+                    if (b.e0 == 0)  // first tile of each resident mesh of the class
+                        for (int e = 0; e < P->slots[b.slot].ne; e += c.bops.epb_t[t])
+                            tl.push_back(Tile{b.slot, e});
+                n = (int)tl.size();
+                if (n > c.acap) {
+                    hipFree(c.d_atiles);
+                    c.d_atiles = nullptr;
+                    c.acap = std::max(n, 2 * c.acap);
+                    PHIP(hipMalloc((void **)&c.d_atiles, sizeof(Tile) * c.acap));
+                }
+                PHIP(hipMemcpyAsync(c.d_atiles, tl.data(), sizeof(Tile) * n, hipMemcpyHostToDevice, P->s));
+                dl = c.d_atiles;
+            }
+            BLaunch f = c.bops.apply_t[st][pr][t];
+            for (int k = 0; k < 2; ++k) f(n, P->s, c.tb, dl, P->d_slots, nullptr, 0, nullptr);
+            PHIP(hipEventRecord(e0, P->s));
+            for (int k = 0; k < reps; ++k) f(n, P->s, c.tb, dl, P->d_slots, nullptr, 0, nullptr);
+            PHIP(hipEventRecord(e1, P->s));
+            PHIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            PHIP(hipEventElapsedTime(&ms, e0, e1));
+            if (best < 0 || ms < tbest) {
+                best = t;
+                tbest = ms;
+            }
+        }
+        c.tile = best;
+        record_tile(c.key.dim, c.key.p, c.key.nq, st ? TMOP_HESS_COMPACT : TMOP_HESS_TENSOR,
+                    pr ? TMOP_MIXED : TMOP_FP64, best);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    P->dirty = true;
+    return TMOP_OK;
+}
+
 extern "C" int tmop_pool_set_graph(tmop_pool *P, int enable)
 {
     if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
@@ -1287,6 +1375,8 @@ extern "C" int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const t
     int r = TMOP_OK;
     for (int k = 0; k < count && r == TMOP_OK; ++k)
         r = tmop_pool_admit(P, meshes + k, prms + k, sps + k, x_devs[k], stream, &slot[k]);
+    // tile shapes of the Hessian action, per class, for this batch
+    if (r == TMOP_OK) r = tmop_pool_autotune(P, 3);
     int active = count;
     while (r == TMOP_OK && active > 0) r = tmop_pool_step(P, &active);
     for (int k = 0; k < count && r == TMOP_OK; ++k) {

@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tmop.h"
@@ -146,6 +149,9 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 namespace tmop {
 
+int tuned_tile(int dim, int p, int nq, int storage, int precision);
+void record_tile(int dim, int p, int nq, int storage, int precision, int t);
+
 int internal_tables(int p, int nq, Tables *tb)
 {
     if (p < 1 || p >= MAXNI || nq < 1 || nq > MAXNQ) return TMOP_ERR_INVALID_ARG;
@@ -210,6 +216,7 @@ enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_HV, SV_V, SV_W, SV_W1, 
 
 struct tmop_ctx {
     double *x0buf = nullptr;  // reference nodes of the limiting term (library copy)
+    int tile = 1;             // Hessian-action tile shape (index into Ops::epb_t)
     Geom g{};
     Tables tb{};
     Target tg{};
@@ -362,6 +369,8 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     c->storage = prm->hess_storage;
     c->s = (hipStream_t)stream;
     c->grid = (int)((ne + ops.epb - 1) / ops.epb);
+    const int tt = tuned_tile(d, p, nq, c->storage, c->precision);
+    if (tt >= 0 && ops.epb_t[tt] > 0) c->tile = tt;
 
     Geom &g = c->g;
     g.dim = d;
@@ -526,17 +535,24 @@ extern "C" int tmop_hessian_setup(tmop_ctx *c, const double *x)
 
 static void apply_elem(tmop_ctx *c, const double *v)
 {
+    // the autotuned tile shape; the variant with the limiting term has the base one
+    const int t = c->g.lim != 0.0 ? 1 : c->tile;
+    const int grid = (int)((c->g.ne + c->ops.epb_t[t] - 1) / c->ops.epb_t[t]);
     if (c->storage == TMOP_HESS_COMPACT) {
         if (c->precision == TMOP_MIXED)
-            c->ops.applyc32(c->grid, c->s, c->g, c->tb, c->tg, (const float *)c->H, v, (float *)c->eV);
+            (t == 1 ? c->ops.applyc32 : c->ops.applyc32_t[t])(grid, c->s, c->g, c->tb, c->tg,
+                                                              (const float *)c->H, v, (float *)c->eV);
         else
-            c->ops.applyc64(c->grid, c->s, c->g, c->tb, c->tg, (const double *)c->H, v, (double *)c->eV);
+            (t == 1 ? c->ops.applyc64 : c->ops.applyc64_t[t])(grid, c->s, c->g, c->tb, c->tg,
+                                                              (const double *)c->H, v, (double *)c->eV);
         return;
     }
     if (c->precision == TMOP_MIXED)
-        c->ops.apply32(c->grid, c->s, c->g, c->tb, (const float *)c->H, v, (float *)c->eV);
+        (t == 1 ? c->ops.apply32 : c->ops.apply32_t[t])(grid, c->s, c->g, c->tb, (const float *)c->H, v,
+                                                        (float *)c->eV);
     else
-        c->ops.apply64(c->grid, c->s, c->g, c->tb, (const double *)c->H, v, (double *)c->eV);
+        (t == 1 ? c->ops.apply64 : c->ops.apply64_t[t])(grid, c->s, c->g, c->tb, (const double *)c->H, v,
+                                                        (double *)c->eV);
 }
 
 static void apply_gather(tmop_ctx *c, const double *v, double *y)
@@ -862,6 +878,90 @@ extern "C" int tmop_newton_step(tmop_ctx *c, double *x, int n_minres, int jacobi
     rep->status = r;
     rep->t_total_ms = now_ms() - t0;
     return r;
+}
+
+// Process-wide table of autotuned tile shapes per kernel class.
+namespace {
+struct TileKey {
+    int dim, p, nq, storage, precision;
+    bool operator<(const TileKey &o) const
+    {
+        return std::tie(dim, p, nq, storage, precision) <
+               std::tie(o.dim, o.p, o.nq, o.storage, o.precision);
+    }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tile;
+
+}  // namespace
+
+namespace tmop {
+// tile shape index recorded for a class by an earlier autotuning, or -1
+int tuned_tile(int dim, int p, int nq, int storage, int precision)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile.find(TileKey{dim, p, nq, storage, precision});
+    return it == g_tile.end() ? -1 : it->second;
+}
+void record_tile(int dim, int p, int nq, int storage, int precision, int t)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile[TileKey{dim, p, nq, storage, precision}] = t;
+}
+}  // namespace tmop
+
+extern "C" int tmop_autotune(tmop_ctx *c, const double *v, double *y, int reps, int *epb)
+{
+    if (!c || !v || !y || reps <= 0) return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int keep = c->tile;
+    int best = -1;
+    float tbest = 0.f;
+    for (int t = 0; t < 3; ++t) {
+        if (c->ops.epb_t[t] == 0) continue;
+        c->tile = t;
+        for (int k = 0; k < 2; ++k) apply_elem(c, v);
+        HIPCHK(hipEventRecord(e0, c->s));
+        for (int k = 0; k < reps; ++k) apply_elem(c, v);
+        HIPCHK(hipEventRecord(e1, c->s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0 || ms < tbest) {
+            best = t;
+            tbest = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tile = best < 0 ? keep : best;
+    record_tile(c->dim, c->p, c->nq, c->storage, c->precision, c->tile);
+    // leave y = H v with the chosen shape
+    apply_elem(c, v);
+    apply_gather(c, v, y);
+    if (epb) *epb = c->ops.epb_t[c->tile];
+    return TMOP_OK;
+}
+
+extern "C" int tmop_set_tile(tmop_ctx *c, int epb)
+{
+    if (!c) return fail(TMOP_ERR_INVALID_ARG, "null context");
+    for (int t = 0; t < 3; ++t)
+        if (c->ops.epb_t[t] > 0 && c->ops.epb_t[t] == epb) {
+            c->tile = t;
+            return TMOP_OK;
+        }
+    return fail(TMOP_ERR_UNSUPPORTED, "no Hessian-action tile with this many elements per workgroup");
+}
+
+extern "C" int tmop_tile_epb(tmop_ctx *c, int *epb)
+{
+    if (!c || !epb) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    *epb = c->ops.epb_t[c->tile];
+    return TMOP_OK;
 }
 
 extern "C" int tmop_set_limiting(tmop_ctx *c, const double *x0, double coef, double delta)

@@ -1,6 +1,7 @@
 // Hex kernel instantiations for order p = 2, n_q = p+1 .. p+3 and 9 (9^3 points).
 #include "kernels3d.hpp"
 #include "ops.hpp"
+#include "tiles3.hpp"
 
 namespace tmop {
 

@@ -27,13 +27,18 @@
 
 namespace tmop {
 
-template <int P, int NQ>
+// T2 = tile shape of the workgroup, in halves of the base number of
+// elements per workgroup EPB0 = max(1, 256 / NQ^3): 1 half, 2 base (one point
+// per lane), 4 double (two points per lane).  Only the Hessian action is
+// instantiated with other than the base shape (its autotuned tile).
+template <int P, int NQ, int T2 = 2>
 struct S3 {
     static constexpr int NI = P + 1;
     static constexpr int NP = NI * NI * NI;
     static constexpr int NQ2 = NQ * NQ;
     static constexpr int NQ3 = NQ * NQ * NQ;
-    static constexpr int EPB = NQ3 >= BLOCK ? 1 : BLOCK / NQ3;
+    static constexpr int EPB0 = NQ3 >= BLOCK ? 1 : BLOCK / NQ3;
+    static constexpr int EPB = EPB0 * T2 / 2 >= 1 ? EPB0 * T2 / 2 : 1;
     static constexpr int L1 = NI * NI * NQ;  // one R1 plane
     static constexpr int L2 = NI * NQ * NQ;  // one R2 plane
     static constexpr int NS = 45;            // packed tensor entries
@@ -44,9 +49,9 @@ struct S3 {
 // barrier that ends the last read of its previous contents.
 // NR = planes of RY per element: 9 (J or Y), or 12 when the three value
 // planes of the limiting term (the vector itself at the points) follow.
-template <int P, int NQ, typename CT, int NR = 9>
+template <int P, int NQ, typename CT, int NR = 9, int T2 = 2>
 struct Lds3 {
-    using S = S3<P, NQ>;
+    using S = S3<P, NQ, T2>;
     union {
         CT X[S::EPB * 3 * S::NP];
         CT R2[S::EPB * 9 * S::L2];
@@ -89,20 +94,20 @@ __device__ __forceinline__ int node3(const Geom &g, int e, int i1, int i2, int i
 // a load phase (registers) and a store phase (LDS) so that a caller can issue
 // other loads in between; the loop has a compile-time trip count so that all
 // of a lane's loads are issued before the first one is waited for.
-template <int P, int NQ>
+template <int P, int NQ, int T2 = 2>
 struct Gath3 {
-    static constexpr int NIT = (S3<P, NQ>::EPB * 3 * S3<P, NQ>::NP + BLOCK - 1) / BLOCK;
+    static constexpr int NIT = (S3<P, NQ, T2>::EPB * 3 * S3<P, NQ>::NP + BLOCK - 1) / BLOCK;
     double val[NIT];
     bool fix[NIT];
 };
 
-template <int P, int NQ>
+template <int P, int NQ, int T2 = 2>
 __device__ __forceinline__ void gather3_load(const Geom &g, const double *__restrict__ vec, int e0,
-                                             int nel, bool masked, Gath3<P, NQ> &r,
+                                             int nel, bool masked, Gath3<P, NQ, T2> &r,
                                              const double *__restrict__ sub = nullptr)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, NP = S::NP, NIT = Gath3<P, NQ>::NIT;
+    constexpr int NI = S::NI, NP = S::NP, NIT = Gath3<P, NQ, T2>::NIT;
     const int n = nel * 3 * NP;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -123,10 +128,10 @@ __device__ __forceinline__ void gather3_load(const Geom &g, const double *__rest
     }
 }
 
-template <int P, int NQ, typename CT>
-__device__ __forceinline__ void gather3_store(const Gath3<P, NQ> &r, int nel, CT *sX)
+template <int P, int NQ, typename CT, int T2 = 2>
+__device__ __forceinline__ void gather3_store(const Gath3<P, NQ, T2> &r, int nel, CT *sX)
 {
-    constexpr int NIT = Gath3<P, NQ>::NIT;
+    constexpr int NIT = Gath3<P, NQ, T2>::NIT;
     const int n = nel * 3 * S3<P, NQ>::NP;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -590,27 +595,27 @@ __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const 
 //   transposed contractions -> E-vector.
 // CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
 // accumulation).
-template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
                                 const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
-    using S = S3<P, NQ>;
+    using S = S3<P, NQ, T2>;
     constexpr int NR = Planes3<LIM>::NR;
     // at most one quadrature point per lane: its tensor is loaded before the
     // sweeps and stays in flight behind them (barriers wait on LDS only)
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;
-    __shared__ Lds3<P, NQ, CT, NR> L;
+    __shared__ Lds3<P, NQ, CT, NR, T2> L;
     // v loads first, then the tensor loads, then v to LDS: waiting for v
     // leaves the tensor loads in flight
-    Gath3<P, NQ> gv;
-    gather3_load<P, NQ>(g, v, e0, nel, true, gv);
+    Gath3<P, NQ, T2> gv;
+    gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
     TT hraw[45];
     if (ONE && threadIdx.x < npts) {
         const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
         qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q, hraw);
     }
-    gather3_store<P, NQ, CT>(gv, nel, L.X);
+    gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
     __syncthreads();
     forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
@@ -742,24 +747,24 @@ __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
-template <int P, int NQ, typename TT, typename CT, bool LIM = false>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
                                  const TT *__restrict__ Q, const double *__restrict__ v,
                                  CT *__restrict__ yE, int e0, int nel)
 {
-    using S = S3<P, NQ>;
+    using S = S3<P, NQ, T2>;
     constexpr int NR = Planes3<LIM>::NR;
     constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;  // as in b3_apply
-    __shared__ Lds3<P, NQ, CT, NR> L;
-    Gath3<P, NQ> gv;
-    gather3_load<P, NQ>(g, v, e0, nel, true, gv);
+    __shared__ Lds3<P, NQ, CT, NR, T2> L;
+    Gath3<P, NQ, T2> gv;
+    gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
     TT draw[NC3];
     if (ONE && threadIdx.x < npts) {
         const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
         qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, draw);
     }
-    gather3_store<P, NQ, CT>(gv, nel, L.X);
+    gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
     __syncthreads();
     forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
@@ -999,12 +1004,12 @@ __global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg, 
     b3_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT, bool LIM>
+template <int P, int NQ, typename TT, typename CT, bool LIM, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *__restrict__ H, const double *__restrict__ v, CT *__restrict__ yE)
 {
-    constexpr int EPB = S3<P, NQ>::EPB;
+    constexpr int EPB = S3<P, NQ, T2>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_apply<P, NQ, TT, CT, LIM>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
+    b3_apply<P, NQ, TT, CT, LIM, T2>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -1015,12 +1020,12 @@ __global__ __launch_bounds__(BLOCK) void k3_setupc(Geom g, Tables tb, Target tg,
     b3_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT, typename CT, bool LIM>
+template <int P, int NQ, typename TT, typename CT, bool LIM, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void k3_applyc(Geom g, Tables tb, Target tg, const TT *__restrict__ Q, const double *__restrict__ v, CT *__restrict__ yE)
 {
-    constexpr int EPB = S3<P, NQ>::EPB;
+    constexpr int EPB = S3<P, NQ, T2>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_applyc<P, NQ, TT, CT, LIM>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
+    b3_applyc<P, NQ, TT, CT, LIM, T2>(g, tb, tg, Q, v, yE, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT, bool LIM>
@@ -1069,14 +1074,14 @@ __global__ __launch_bounds__(BLOCK) void kb3_setup(Tables tb, const Tile *__rest
     b3_setup<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void kb3_apply(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
-    constexpr int EPB = S3<P, NQ>::EPB;
+    constexpr int EPB = S3<P, NQ, T2>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_apply<P, NQ, TT, CT>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_apply<P, NQ, TT, CT, false, T2>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -1089,14 +1094,23 @@ __global__ __launch_bounds__(BLOCK) void kb3_setupc(Tables tb, const Tile *__res
     b3_setupc<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void kb3_applyc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
-    constexpr int EPB = S3<P, NQ>::EPB;
+    constexpr int EPB = S3<P, NQ, T2>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_applyc<P, NQ, TT, CT>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_applyc<P, NQ, TT, CT, false, T2>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+}
+
+// Does the Hessian action of this class have a tile shape T2 distinct from
+// the base one that fits the LDS?  (FP64 data, the larger of the two types.)
+template <int P, int NQ, int T2>
+constexpr bool tile_ok3()
+{
+    return T2 == 2 || (S3<P, NQ, T2>::EPB != S3<P, NQ>::EPB &&
+                       sizeof(Lds3<P, NQ, double, 9, T2>) <= 96 * 1024);
 }
 
 template <int P, int NQ, typename TT>

@@ -40,6 +40,14 @@ struct Ops {
                     const double *Q, double *dE);
     void (*diagc32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
                     const float *Q, double *dE);
+    // Hessian action (without the limiting term) per tile shape t: 0 half, 1
+    // base, 2 double the elements per workgroup; epb_t[t] = 0 where the shape
+    // does not exist for this class.  Index 1 is the launcher set above.
+    int epb_t[3];
+    decltype(apply64) apply64_t[3];
+    decltype(apply32) apply32_t[3];
+    decltype(applyc64) applyc64_t[3];
+    decltype(applyc32) applyc32_t[3];
 };
 
 // Batched launchers (grid = number of tiles); every batched element kernel
@@ -54,12 +62,44 @@ struct BOps {
     BLaunch setup[2][2];  // [storage tensor/compact][fp64/fp32]
     BLaunch apply[2][2];
     BLaunch diag[2][2];
+    // Hessian action per tile shape (as in Ops); apply_t[..][..][1] == apply
+    int epb_t[3];
+    BLaunch apply_t[2][2][3];
 };
+
+// Base tile shape only (quads).
+template <int P, int NQ>
+inline void fill_tiles_k2(Ops &o)
+{
+    for (int t = 0; t < 3; ++t) {
+        o.epb_t[t] = t == 1 ? o.epb : 0;
+        o.apply64_t[t] = t == 1 ? o.apply64 : nullptr;
+        o.apply32_t[t] = t == 1 ? o.apply32 : nullptr;
+        o.applyc64_t[t] = t == 1 ? o.applyc64 : nullptr;
+        o.applyc32_t[t] = t == 1 ? o.applyc32 : nullptr;
+    }
+}
+
+template <int P, int NQ>
+inline void fill_tiles_kb2(BOps &o)
+{
+    for (int t = 0; t < 3; ++t) {
+        o.epb_t[t] = t == 1 ? o.epb : 0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) o.apply_t[a][b][t] = t == 1 ? o.apply[a][b] : nullptr;
+    }
+}
 
 // Host-side 1D tables (GLL basis at Gauss-Legendre points) and constant
 // target of a (p, n_q) / params pair; defined in capi.hip.
 int internal_tables(int p, int nq, Tables *tb);
 int internal_target(const tmop_params *prm, int dim, Target *tg);
+
+// Tile shapes of the Hessian action chosen by the autotuner, per class
+// (process-wide; tmop_autotune / tmop_pool_autotune record them): the shape
+// index, or -1 when the class was not tuned.  Defined in capi.hip.
+int tuned_tile(int dim, int p, int nq, int storage, int precision);
+void record_tile(int dim, int p, int nq, int storage, int precision, int t);
 
 // Returns false if no kernel was built for this combination.
 bool find_ops(int dim, int p, int nq, Ops *out);
@@ -86,6 +126,7 @@ bool bops3_p4(int nq, BOps *out);
         };                                                                                     \
         TMOP_BOPS_PREC(K, P, NQ, 0, double, double)                                            \
         TMOP_BOPS_PREC(K, P, NQ, 1, float, float)                                              \
+        fill_tiles_##K<P, NQ>(o);                                                              \
         *out = o;                                                                              \
         return true;                                                                           \
     }
@@ -229,6 +270,7 @@ bool ops3_p4(int nq, Ops *out);
                 hipLaunchKernelGGL((K##_diagc<P, NQ, float, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, Q, dE); \
             }                                                                      \
         };                                                                                       \
+        fill_tiles_##K<P, NQ>(o);                                                                \
         *out = o;                                                                                \
         return true;                                                                             \
     }

@@ -1,0 +1,93 @@
+// Hessian-action launchers of the hex kernels for every tile shape of a
+// class (elements per workgroup: half, base, double), filled into the launch
+// tables; shapes that do not exist for a class (tile_ok3) are never
+// instantiated.
+#pragma once
+#include "kernels3d.hpp"
+#include "ops.hpp"
+
+namespace tmop {
+
+template <int P, int NQ, int T2, int IDX>
+inline void fill_tile3(Ops &o)
+{
+    if constexpr (tile_ok3<P, NQ, T2>()) {
+        o.epb_t[IDX] = S3<P, NQ, T2>::EPB;
+        o.apply64_t[IDX] = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                              const double *H, const double *v, double *yE) {
+            hipLaunchKernelGGL((k3_apply<P, NQ, double, double, false, T2>), dim3(grid),
+                               dim3(BLOCK), 0, s, g, t, H, v, yE);
+        };
+        o.apply32_t[IDX] = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                              const float *H, const double *v, float *yE) {
+            hipLaunchKernelGGL((k3_apply<P, NQ, float, float, false, T2>), dim3(grid),
+                               dim3(BLOCK), 0, s, g, t, H, v, yE);
+        };
+        o.applyc64_t[IDX] = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                               const Target &w, const double *Q, const double *v, double *yE) {
+            hipLaunchKernelGGL((k3_applyc<P, NQ, double, double, false, T2>), dim3(grid),
+                               dim3(BLOCK), 0, s, g, t, w, Q, v, yE);
+        };
+        o.applyc32_t[IDX] = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                               const Target &w, const float *Q, const double *v, float *yE) {
+            hipLaunchKernelGGL((k3_applyc<P, NQ, float, float, false, T2>), dim3(grid),
+                               dim3(BLOCK), 0, s, g, t, w, Q, v, yE);
+        };
+    } else {
+        o.epb_t[IDX] = 0;
+        o.apply64_t[IDX] = nullptr;
+        o.apply32_t[IDX] = nullptr;
+        o.applyc64_t[IDX] = nullptr;
+        o.applyc32_t[IDX] = nullptr;
+    }
+}
+
+template <int P, int NQ>
+inline void fill_tiles_k3(Ops &o)
+{
+    fill_tile3<P, NQ, 1, 0>(o);
+    fill_tile3<P, NQ, 2, 1>(o);
+    fill_tile3<P, NQ, 4, 2>(o);
+}
+
+template <int P, int NQ, int T2, int IDX>
+inline void fill_btile3(BOps &o)
+{
+    if constexpr (tile_ok3<P, NQ, T2>()) {
+        o.epb_t[IDX] = S3<P, NQ, T2>::EPB;
+        o.apply_t[0][0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
+                                  const SlotDev *sl, const int *gt, int vin, double *) {
+            hipLaunchKernelGGL((kb3_apply<P, NQ, double, double, T2>), dim3(grid), dim3(BLOCK),
+                               0, s, t, tl, sl, gt, vin);
+        };
+        o.apply_t[0][1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
+                                  const SlotDev *sl, const int *gt, int vin, double *) {
+            hipLaunchKernelGGL((kb3_apply<P, NQ, float, float, T2>), dim3(grid), dim3(BLOCK), 0,
+                               s, t, tl, sl, gt, vin);
+        };
+        o.apply_t[1][0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
+                                  const SlotDev *sl, const int *gt, int vin, double *) {
+            hipLaunchKernelGGL((kb3_applyc<P, NQ, double, double, T2>), dim3(grid), dim3(BLOCK),
+                               0, s, t, tl, sl, gt, vin);
+        };
+        o.apply_t[1][1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
+                                  const SlotDev *sl, const int *gt, int vin, double *) {
+            hipLaunchKernelGGL((kb3_applyc<P, NQ, float, float, T2>), dim3(grid), dim3(BLOCK), 0,
+                               s, t, tl, sl, gt, vin);
+        };
+    } else {
+        o.epb_t[IDX] = 0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) o.apply_t[a][b][IDX] = nullptr;
+    }
+}
+
+template <int P, int NQ>
+inline void fill_tiles_kb3(BOps &o)
+{
+    fill_btile3<P, NQ, 1, 0>(o);
+    fill_btile3<P, NQ, 2, 1>(o);
+    fill_btile3<P, NQ, 4, 2>(o);
+}
+
+}  // namespace tmop

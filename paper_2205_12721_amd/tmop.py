@@ -94,6 +94,9 @@ SIGNATURES = {
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
     "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
+    "tmop_autotune": [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "tmop_tile_epb": [_P, ctypes.POINTER(ctypes.c_int)],
+    "tmop_set_tile": [_P, ctypes.c_int],
     "tmop_pool_create": [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int, _P],
     "tmop_pool_destroy": [_P],
     "tmop_pool_request_bytes": [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
@@ -107,6 +110,7 @@ SIGNATURES = {
     "tmop_pool_info": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                        ctypes.POINTER(ctypes.c_int)],
     "tmop_pool_set_graph": [_P, ctypes.c_int],
+    "tmop_pool_autotune": [_P, ctypes.c_int],
     "tmop_pool_last_error": [],
     "tmop_batch_solve": [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
                          ctypes.POINTER(_P), ctypes.POINTER(SolveParams),
@@ -295,6 +299,21 @@ class Context:
                                  float(rtol), int(bool(jacobi)), ctypes.byref(its)))
         return out, its.value
 
+    def autotune(self, v, y, reps=10):
+        """Pick the fastest Hessian-action tile shape (needs hessian_setup); returns the
+        chosen elements per workgroup."""
+        e = ctypes.c_int()
+        _check(lib().tmop_autotune(self._h, self._vec(v), self._vec(y), int(reps), ctypes.byref(e)))
+        return e.value
+
+    def set_tile(self, epb):
+        _check(lib().tmop_set_tile(self._h, int(epb)))
+
+    def tile_epb(self):
+        e = ctypes.c_int()
+        _check(lib().tmop_tile_epb(self._h, ctypes.byref(e)))
+        return e.value
+
     def set_limiting(self, x0=None, coef=1.0, delta=1.0):
         """Add (or, with x0=None, remove) the limiting term coef*|x - x0|^2/delta^2."""
         ptr = None if x0 is None else self._vec(x0)
@@ -425,6 +444,10 @@ class Pool:
     def release(self, slot):
         _pcheck(lib().tmop_pool_release(self._h, int(slot)))
         self._keep.pop(slot, None)
+
+    def autotune(self, reps=5):
+        """Pick the Hessian-action tile shape of every resident kernel class."""
+        _pcheck(lib().tmop_pool_autotune(self._h, int(reps)))
 
     def info(self):
         u, b, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()

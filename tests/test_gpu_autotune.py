@@ -1,0 +1,85 @@
+"""Tile-shape autotuner of the Hessian action (elements per workgroup: half,
+base and double the base max(1, 256 / n_q^3) where they fit the LDS).
+
+* every tile shape gives bitwise the same action (each element is computed
+  alike), and that action matches the oracle within 1e-11
+* tmop_autotune picks one of the shapes, leaves y = H v, and the choice is
+  recorded for the class (a later context of the class starts with it)
+* the pool's autotuner runs between steps and the batched solve still ends
+  at the single-context solution
+"""
+import numpy as np
+import pytest
+
+from paper_2205_12721_amd import inputs
+from tests.gpu_common import TOL64, log, make_case, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _shapes(base):
+    return [e for e in (base // 2, base, 2 * base) if e >= 1]
+
+
+@pytest.mark.parametrize("storage", ["tensor", "compact"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ns,p,nq", [((5, 4, 3), 1, 3), ((4, 3, 3), 2, 4), ((3, 3, 2), 3, 5),
+                                     ((3, 2, 2), 4, 6)])
+def test_tile_shapes_agree(ns, p, nq, storage, precision):
+    from paper_2205_12721_amd.tmop import Context, TmopError
+    log("case", ns, p, nq, storage, precision)
+    pb, x = make_case(3, ns, p, nq, seed=3)
+    v = to_dev(inputs.gaussian_vector(pb.ndof, 11, pb.ess))
+    ctx = Context(3, ns, p, nq, storage=storage, precision=precision)
+    ctx.hessian_setup(to_dev(x))
+    base = ctx.tile_epb()
+    ys = {}
+    for e in _shapes(base):
+        try:
+            ctx.set_tile(e)
+        except TmopError:
+            continue  # this shape does not fit the LDS for this class
+        ys[e] = to_host(ctx.hessian_apply(v))
+    assert base in ys
+    for e, y in ys.items():
+        assert np.array_equal(y, ys[base]), e
+    if precision == "fp64":
+        assert rel(ys[base], pb.hvp(x, to_host(v))) <= TOL64
+    y = ctx.new_vector()
+    chosen = ctx.autotune(v, y, reps=3)
+    assert chosen in ys
+    assert np.array_equal(to_host(y), ys[base])
+    ctx.close()
+    # recorded for the class
+    c2 = Context(3, ns, p, nq, storage=storage, precision=precision)
+    assert c2.tile_epb() == chosen
+    c2.close()
+
+
+def test_pool_autotune_solution():
+    import torch
+    from paper_2205_12721_amd.tmop import Context, Pool, basis_nodes, request, solve_params
+    specs = [(3, 1, 3), (4, 2, 4), (2, 3, 5)]
+    xs = [inputs.perturbed_box(3, n, p, basis_nodes(p), 20 + k, recipe="smooth", amp=0.05)[0]
+          for k, (n, p, nq) in enumerate(specs)]
+    pool = Pool(1 << 30, 8)
+    sp = solve_params(rel_grad_tol=1e-10, max_newton=60)
+    slots = []
+    for (n, p, nq), x in zip(specs, xs):
+        md, prm = request(3, n, p, nq)
+        slots.append((pool.admit(md, prm, sp, to_dev(x)), n, p, nq, x))
+    pool.autotune(3)
+    while pool.step():
+        pass
+    for slot, n, p, nq, x in slots:
+        done, rep = pool.poll(slot)
+        assert done and rep["status"] == 0
+        out = torch.empty(x.size, dtype=torch.float64, device="cuda")
+        pool.result(slot, out)
+        ctx = Context(3, n, p, nq)
+        xd = to_dev(x)
+        r1 = ctx.solve(xd, rel_grad_tol=1e-10, max_newton=60)
+        ctx.close()
+        assert r1["status"] == 0
+        assert rel(to_host(out), to_host(xd)) <= 1e-9
+    pool.close()
