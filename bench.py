@@ -34,7 +34,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-TRAFFIC = {}
+_SHA_C2 = "fdae341fbc6c4020d4a04d8694a121f9deaa17ace9c6443299383f28b8be24cf"
+TRAFFIC = {
+    ("c2", "tensor_fp64"): {"bytes": 688983372, "elements_per_workgroup": 2,
+                        "csrc_sha256": _SHA_C2},
+    ("c2", "tensor_mixed"): {"bytes": 358235613, "elements_per_workgroup": 2,
+                        "csrc_sha256": _SHA_C2},
+    ("c2", "compact_fp64"): {"bytes": 245852092, "elements_per_workgroup": 2,
+                        "csrc_sha256": _SHA_C2},
+    ("c2", "compact_mixed"): {"bytes": 134706390, "elements_per_workgroup": 2,
+                        "csrc_sha256": _SHA_C2},
+}
 
 
 def csrc_sha256():
@@ -48,9 +58,9 @@ def csrc_sha256():
     return h.hexdigest()
 
 
-def traffic_for(variant, workload):
+def traffic_for(variant, workload, epb):
     t = TRAFFIC.get((workload, variant))
-    if not t or t["csrc_sha256"] != csrc_sha256():
+    if not t or t["csrc_sha256"] != csrc_sha256() or t["elements_per_workgroup"] != epb:
         return None
     return t["bytes"]
 
@@ -107,13 +117,16 @@ def run_steps(ctx, x, x0, steps, n_minres):
 
 
 def time_actions(ctx, x, v, reps):
-    """Standalone Hessian actions after one setup at x: 3 warm-up actions, then
-    (element kernel mean, whole-action mean) in ms over `reps` actions each."""
+    """Standalone Hessian actions after one setup at x, with the autotuned tile
+    shape: 3 warm-up actions, then (element kernel mean, whole-action mean) in ms
+    over `reps` actions each, and the elements per workgroup used."""
     import torch
     y = torch.empty_like(v)
     ctx.hessian_setup(x)
+    epb = ctx.autotune(v, y, 5)
     ctx.time_apply(v, y, 3)
-    return ctx.time_apply(v, y, reps)
+    e, t = ctx.time_apply(v, y, reps)
+    return e, t, epb
 
 
 def roofline(ne, nqe, S, ndof, tbytes, elem_ms, total_ms, traffic=None):
@@ -362,9 +375,9 @@ def main():
     acc = run_steps(ctx, x, x0, args.steps, args.minres)
     log("[bench] fp64 timed steps done")
     napp = max(acc["n_apply"], 1)
-    elem_ms, tot_ms = time_actions(ctx, x0, v0, args.apply_reps)
+    elem_ms, tot_ms, epb = time_actions(ctx, x0, v0, args.apply_reps)
     gdofs = ctx.ndof / (tot_ms / 1e3) / 1e9
-    rf = roofline(ne, nqe, S, ctx.ndof, 8, elem_ms, tot_ms, traffic_for("tensor_fp64", cname))
+    rf = roofline(ne, nqe, S, ctx.ndof, 8, elem_ms, tot_ms, traffic_for("tensor_fp64", cname, epb))
     ms_step = acc["wall_s"] / args.steps * 1e3
 
     out = {
@@ -387,7 +400,7 @@ def main():
                         "2D quad box %d^2, Q%d, %d^2 points, mu_2" % (n, p, nq),
             "elements": ne, "order": p, "nq1d": nq, "dofs": ctx.ndof,
             "minres_per_step": args.minres, "mesh_seed": inputs.CONFIGS[cname]["seed"],
-            "actions_timed": args.apply_reps,
+            "actions_timed": args.apply_reps, "elements_per_workgroup": epb,
         },
         "roofline": rf,
         "step_gdof_s": round(ctx.ndof * args.minres / (ms_step / 1e3) / 1e9, 3),
@@ -407,7 +420,7 @@ def main():
         run_steps(cv, x, x0, args.warmup, args.minres)
         av = run_steps(cv, x, x0, args.steps, args.minres)
         log("[bench] %s %s timed steps done" % (storage, prec))
-        em, tm = time_actions(cv, x0, v0, args.apply_reps)
+        em, tm, eb = time_actions(cv, x0, v0, args.apply_reps)
         sv = S if storage == "tensor" else (13 if dim == 3 else 8)
         key = "%s_%s" % (storage, prec)
         out[key] = {
@@ -416,8 +429,9 @@ def main():
             "storage": storage, "values_per_point": sv,
             "ms_per_step": round(av["wall_s"] / args.steps * 1e3, 3),
             "apply_in_minres_us": round(av["t_apply_ms"] / max(av["n_apply"], 1) * 1e3, 2),
+            "elements_per_workgroup": eb,
             "roofline": roofline(ne, nqe, sv, cv.ndof, 8 if prec == "fp64" else 4, em, tm,
-                                 traffic_for(key, cname)),
+                                 traffic_for(key, cname, eb)),
         }
         cv.close()
 
