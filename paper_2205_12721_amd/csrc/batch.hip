@@ -215,12 +215,10 @@ __global__ __launch_bounds__(VB) void kv_gather(const VTile *__restrict__ vt,
     double *out = S.vec[vout];
     const double *src = S.vec[vsrc];
     for (int i = i0; i < i1; i += VB) {
-        const int c = i / g.nx, node = i - c * g.nx;
+        const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
+        const int node = i - c * g.nx;
         int gc[3];
-        gc[0] = node % g.M[0];
-        const int tt = node / g.M[0];
-        gc[1] = DIM == 3 ? tt % g.M[1] : tt;
-        gc[2] = DIM == 3 ? tt / g.M[1] : 0;
+        box_coords<DIM>(g, node, gc);
         const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
         double v;
         if (fixed)
@@ -323,12 +321,10 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_l1(const VTile *__restrict__ 
     double *hv = S.vec[vhv];
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
-        const int c = i / g.nx, node = i - c * g.nx;
+        const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
+        const int node = i - c * g.nx;
         int gc[3];
-        gc[0] = node % g.M[0];
-        const int tt = node / g.M[0];
-        gc[1] = DIM == 3 ? tt % g.M[1] : tt;
-        gc[2] = DIM == 3 ? tt / g.M[1] : 0;
+        box_coords<DIM>(g, node, gc);
         const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
         const double vi = v[i];
         double h = fixed ? vi : (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
@@ -1194,6 +1190,7 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     g.nel[2] = s.dim == 3 ? m->nz : 1;
     for (int k = 0; k < 3; ++k) g.M[k] = g.nel[k] * s.p + 1;
     if (s.dim == 2) g.M[2] = 1;
+    set_divisors(g);
     g.e2n = nullptr;
     g.ess_mode = m->ess_mode;
     g.ess = m->ess_mask;

@@ -384,6 +384,7 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
         for (int k = 0; k < 3; ++k) g.M[k] = g.nel[k] * p + 1;
         if (d == 2) g.M[2] = 1;
     }
+    set_divisors(g);
     g.e2n = m->elem_to_node;
     g.ess_mode = m->ess_mode;
     g.ess = m->ess_mask;

@@ -49,8 +49,8 @@ __device__ __forceinline__ int node2(const Geom &g, int e, int i1, int i2, int &
         gx = gy = -1;
         return g.e2n[(size_t)e * (NI * NI) + i1 + NI * i2];
     }
-    const int ex = e % g.nel[0];
-    const int ey = e / g.nel[0];
+    int ex, ey, ez;
+    box_elem<2>(g, e, ex, ey, ez);
     gx = ex * P + i1;
     gy = ey * P + i2;
     return gx + g.M[0] * gy;
@@ -64,7 +64,8 @@ __device__ __forceinline__ long ev_index2(const Geom &g, int e, int c, int i1, i
 {
     constexpr int NI = P + 1, NP = NI * NI;
     if (g.e2n) return ((long)e * 2 + c) * NP + i1 + NI * i2;
-    const int ex = e % g.nel[0], ey = e / g.nel[0];
+    int ex, ey, ez;
+    box_elem<2>(g, e, ex, ey, ez);
     const long EX = (long)g.nel[0] * NI;
     return (long)c * g.ne * NP + (long)(ey * NI + i2) * EX + ex * NI + i1;
 }

@@ -78,10 +78,8 @@ __device__ __forceinline__ int node3(const Geom &g, int e, int i1, int i2, int i
         gx = gy = gz = -1;
         return g.e2n[(size_t)e * (NI * NI * NI) + i1 + NI * (i2 + NI * i3)];
     }
-    const int ex = e % g.nel[0];
-    const int t = e / g.nel[0];
-    const int ey = t % g.nel[1];
-    const int ez = t / g.nel[1];
+    int ex, ey, ez;
+    box_elem<3>(g, e, ex, ey, ez);
     gx = ex * P + i1;
     gy = ey * P + i2;
     gz = ez * P + i3;
@@ -101,6 +99,33 @@ struct Gath3 {
     bool fix[NIT];
 };
 
+template <int P, int NQ, int T2, bool SUB>
+__device__ __forceinline__ void gather3_box(const Geom &g, const double *__restrict__ vec,
+                                            const double *__restrict__ sub, int e0, int n,
+                                            bool bmask, Gath3<P, NQ, T2> &r)
+{
+    using S = S3<P, NQ>;
+    constexpr int NI = S::NI, NP = S::NP, NIT = Gath3<P, NQ, T2>::NIT;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * BLOCK;
+        const bool in = idx < n;
+        const int i = idx % NP;
+        const int rr = idx / NP;  // el*3 + c
+        const int c = rr % 3, el = rr / 3;
+        const int i1 = i % NI, i2 = (i / NI) % NI, i3 = i / (NI * NI);
+        int ex, ey, ez;
+        box_elem<3>(g, e0 + el, ex, ey, ez);
+        const int gx = ex * P + i1, gy = ey * P + i2, gz = ez * P + i3;
+        // lanes past the end read node 0 and are dropped
+        const size_t at = in ? (size_t)c * g.nx + gx + g.M[0] * (gy + g.M[1] * gz) : 0;
+        double v = vec[at];
+        if (SUB) v -= sub[at];
+        r.val[it] = v;
+        r.fix[it] = !in || (bmask && box_boundary(g, gx, gy, gz));
+    }
+}
+
 template <int P, int NQ, int T2 = 2>
 __device__ __forceinline__ void gather3_load(const Geom &g, const double *__restrict__ vec, int e0,
                                              int nel, bool masked, Gath3<P, NQ, T2> &r,
@@ -109,6 +134,16 @@ __device__ __forceinline__ void gather3_load(const Geom &g, const double *__rest
     using S = S3<P, NQ>;
     constexpr int NI = S::NI, NP = S::NP, NIT = Gath3<P, NQ, T2>::NIT;
     const int n = nel * 3 * NP;
+    if (!g.e2n && !(masked && g.ess_mode == 2)) {
+        // box mesh without a mask array: branch-free, so that every load of
+        // the lane is issued before any is waited for
+        const bool bmask = masked && g.ess_mode == 0;
+        if (sub)
+            gather3_box<P, NQ, T2, true>(g, vec, sub, e0, n, bmask, r);
+        else
+            gather3_box<P, NQ, T2, false>(g, vec, sub, e0, n, bmask, r);
+        return;
+    }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = threadIdx.x + it * BLOCK;
@@ -248,10 +283,8 @@ __device__ __forceinline__ long ev_index3(const Geom &g, int e, int c, int i1, i
 {
     constexpr int NI = P + 1, NP = NI * NI * NI;
     if (g.e2n) return ((long)e * 3 + c) * NP + i1 + NI * (i2 + NI * i3);
-    const int ex = e % g.nel[0];
-    const int t = e / g.nel[0];
-    const int ey = t % g.nel[1];
-    const int ez = t / g.nel[1];
+    int ex, ey, ez;
+    box_elem<3>(g, e, ex, ey, ez);
     const long EX = (long)g.nel[0] * NI, EY = (long)g.nel[1] * NI;
     return (long)c * g.ne * NP + ((long)(ez * NI + i3) * EY + (ey * NI + i2)) * EX + ex * NI + i1;
 }
@@ -611,8 +644,12 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
     gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
     TT hraw[45];
-    if (ONE && threadIdx.x < npts) {
-        const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
+    if (ONE) {
+        // every lane loads (lanes past the last point re-read the first
+        // point): with no branch around these loads, the wait for the v loads
+        // can leave all of them in flight
+        const int t = threadIdx.x < npts ? threadIdx.x : 0;
+        const int el = t / S::NQ3, q = t % S::NQ3;
         qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q, hraw);
     }
     gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
@@ -760,8 +797,10 @@ __device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const
     gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
     TT draw[NC3];
-    if (ONE && threadIdx.x < npts) {
-        const int el = threadIdx.x / S::NQ3, q = threadIdx.x % S::NQ3;
+    if (ONE) {
+        // branch-free, as in b3_apply
+        const int t = threadIdx.x < npts ? threadIdx.x : 0;
+        const int el = t / S::NQ3, q = t % S::NQ3;
         qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, draw);
     }
     gather3_store<P, NQ, CT, T2>(gv, nel, L.X);

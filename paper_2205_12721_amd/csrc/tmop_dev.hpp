@@ -16,6 +16,32 @@ constexpr int BLOCK = 256;
 constexpr int MAXNI = 9;   // p <= 8
 constexpr int MAXNQ = 10;  // up to 10 points per direction
 
+// Division by a divisor d >= 1 fixed at set-up, exact for 0 <= n < 2^31:
+// floor(n / d) = (n m) >> s with l = ceil(log2 d), m = ceil(2^(31+l) / d),
+// s = 31 + l (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, Thm. 4.2; m < 2^32).  Two multiplies and a shift
+// in place of the long sequence of a run-time integer division.
+struct FastDiv {
+    uint32_t m;
+    uint32_t s;
+};
+
+inline FastDiv make_fastdiv(int d)
+{
+    int l = 0;
+    while ((1ll << l) < (long long)d) ++l;
+    const unsigned long long num = 1ull << (31 + l);
+    FastDiv f;
+    f.m = (uint32_t)((num + (unsigned long long)d - 1) / (unsigned long long)d);
+    f.s = (uint32_t)(31 + l);
+    return f;
+}
+
+__host__ __device__ __forceinline__ int fdiv(int n, FastDiv f)
+{
+    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.s);
+}
+
 // Mesh geometry passed by value to every kernel.
 struct Geom {
     int dim;
@@ -31,7 +57,49 @@ struct Geom {
     // nodes x0 [dim * nx] and lim = coef det W / delta^2; lim = 0 means off
     const double *x0;
     double lim;
+    // box meshes: divisions by M[0], M[1], p, nel[0] and nel[1] (set by
+    // set_divisors)
+    FastDiv dM0, dM1, dP, dE0, dE1;
 };
+
+inline void set_divisors(Geom &g)
+{
+    g.dM0 = make_fastdiv(g.M[0] > 0 ? g.M[0] : 1);
+    g.dM1 = make_fastdiv(g.M[1] > 0 ? g.M[1] : 1);
+    g.dP = make_fastdiv(g.p > 0 ? g.p : 1);
+    g.dE0 = make_fastdiv(g.nel[0] > 0 ? g.nel[0] : 1);
+    g.dE1 = make_fastdiv(g.nel[1] > 0 ? g.nel[1] : 1);
+}
+
+// Element coordinates (ex, ey[, ez]) of element e of a box mesh.
+template <int DIM>
+__device__ __forceinline__ void box_elem(const Geom &g, int e, int &ex, int &ey, int &ez)
+{
+    const int t = fdiv(e, g.dE0);
+    ex = e - t * g.nel[0];
+    if (DIM == 3) {
+        ez = fdiv(t, g.dE1);
+        ey = t - ez * g.nel[1];
+    } else {
+        ey = t;
+        ez = 0;
+    }
+}
+
+// Grid coordinates of global node `node` of a box mesh.
+template <int DIM>
+__device__ __forceinline__ void box_coords(const Geom &g, int node, int gc[3])
+{
+    const int t = fdiv(node, g.dM0);
+    gc[0] = node - t * g.M[0];
+    if (DIM == 3) {
+        gc[2] = fdiv(t, g.dM1);
+        gc[1] = t - gc[2] * g.M[1];
+    } else {
+        gc[1] = t;
+        gc[2] = 0;
+    }
+}
 
 // 1D tables: B[q][i] = l_i(chi_q), G[q][i] = l_i'(chi_q), w[q] (Sec. 3.1, eq. eq_B_G_1D).
 // Bf, Gf: the same tables rounded to FP32 for the mixed-precision action.

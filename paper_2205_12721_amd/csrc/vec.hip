@@ -19,12 +19,17 @@ __global__ __launch_bounds__(VBLOCK) void k_gather(Geom g, const int32_t *__rest
                                                    double *__restrict__ out, int fix_mode,
                                                    const double *__restrict__ src)
 {
-    const int total = DIM * g.nx;
-    for (int idx = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; idx < total;
-         idx += gridDim.x * VBLOCK) {
-        bool fixed;
-        const double v = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
-        out[idx] = fixed ? (fix_mode == 0 ? 0.0 : (fix_mode == 1 ? 1.0 : src[idx])) : v;
+    // one lane per node, all components
+    for (int node = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; node < g.nx;
+         node += gridDim.x * VBLOCK) {
+        double a[DIM];
+        bool fixed[DIM];
+        gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t idx = (size_t)c * g.nx + node;
+            out[idx] = fixed[c] ? (fix_mode == 0 ? 0.0 : (fix_mode == 1 ? 1.0 : src[idx])) : a[c];
+        }
     }
 }
 
@@ -39,7 +44,7 @@ static int vgrid(long n, int cap = 2048)
 void launch_gather(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
                    bool fp32, double *out, int fix_mode, const double *src, hipStream_t s)
 {
-    const int grid = vgrid((long)g.dim * g.nx, 8192);
+    const int grid = vgrid((long)g.nx, 8192);
 #define TMOP_G(D, T)                                                                          \
     hipLaunchKernelGGL((k_gather<D, T>), dim3(grid), dim3(VBLOCK), 0, s, g, csr_ptr, csr_ent, \
                        (const T *)eV, out, fix_mode, src);
@@ -304,17 +309,22 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_l1(Geom g, const int32_t *
     if (j > st->stop) return;
     __shared__ double red[VBLOCK / 64];
     const double cr = j >= 1 ? st->beta / st->oldb : 0.0;
-    const int total = DIM * g.nx;
     double s = 0.0;
-    for (int idx = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; idx < total;
-         idx += gridDim.x * VBLOCK) {
-        bool fixed;
-        const double a = gather_entry<DIM, ET>(g, ptr, ent, eV, idx, &fixed);
-        const double vi = v[idx];
-        double h = fixed ? vi : a;
-        if (j >= 1) h -= cr * r1[idx];
-        hv[idx] = h;
-        s += vi * h;
+    // one lane per node, all components
+    for (int node = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; node < g.nx;
+         node += gridDim.x * VBLOCK) {
+        double a[DIM];
+        bool fixed[DIM];
+        gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t idx = (size_t)c * g.nx + node;
+            const double vi = v[idx];
+            double h = fixed[c] ? vi : a[c];
+            if (j >= 1) h -= cr * r1[idx];
+            hv[idx] = h;
+            s += vi * h;
+        }
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
