@@ -291,7 +291,7 @@ __device__ __forceinline__ long ev_index3(const Geom &g, int e, int c, int i1, i
 
 // Backward (transposed) sweeps RY -> R2 -> R1 -> E-vector:
 //   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q)  (+ RY[9+c](q) w_i(q) with VAL).
-template <int P, int NQ, typename CT, typename OT, int NR = 9, bool VAL = false>
+template <int P, int NQ, typename CT, typename OT, int NR = 9, bool VAL = false, bool CW = false>
 __device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
                                  CT *R1, int nel, OT *__restrict__ out)
 {
@@ -357,25 +357,59 @@ __device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e
     }
     __syncthreads();
     // axis 1: pencils (r, i3, i2) -> NI consecutive outputs
+    if (!CW) {
+        for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
+            const int i2 = pen % NI, i3 = (pen / NI) % NI, r = pen / (NI * NI);
+            const int c = r % 3, el = r / 3;
+            const CT *t = R1 + r * 2 * L1 + (i3 * NI + i2) * NQ;
+            CT u0[NQ], u1[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                u0[q] = t[q];
+                u1[q] = t[L1 + q];
+            }
+            OT *o = out + ev_index3<P>(g, e0 + el, c, 0, i2, i3);
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                CT s = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    s += tabG<CT>(tb, q * NI + k) * u0[q] + tabB<CT>(tb, q * NI + k) * u1[q];
+                o[k] = (OT)s;
+            }
+        }
+        return;
+    }
+    // CW (coalesced writes): the outputs are staged in R2 (free again) as
+    // [el][c][i3][i2][i1]
+    static_assert(9 * L2 >= 3 * S::NP, "staging of the element outputs must fit in R2");
+    CT *Y = R2;
     for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
-        const int i2 = pen % NI, i3 = (pen / NI) % NI, r = pen / (NI * NI);
-        const int c = r % 3, el = r / 3;
-        const CT *t = R1 + r * 2 * L1 + (i3 * NI + i2) * NQ;
+        const int r = pen / (NI * NI), i32 = pen % (NI * NI);
+        const CT *t = R1 + r * 2 * L1 + i32 * NQ;
         CT u0[NQ], u1[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             u0[q] = t[q];
             u1[q] = t[L1 + q];
         }
-        OT *o = out + ev_index3<P>(g, e0 + el, c, 0, i2, i3);
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             CT s = 0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
                 s += tabG<CT>(tb, q * NI + k) * u0[q] + tabB<CT>(tb, q * NI + k) * u1[q];
-            o[k] = (OT)s;
+            Y[pen * NI + k] = s;
         }
+    }
+    __syncthreads();
+    // E-vector writes with the lanes in (c, i3, i2, el, i1) order: on the box
+    // the tile's elements are neighbours along x, so consecutive lanes write
+    // consecutive addresses of the exploded grid (runs of nel*NI values)
+    for (int idx = threadIdx.x; idx < nel * 3 * NI * NI * NI; idx += BLOCK) {
+        const int k = idx % NI, el = (idx / NI) % nel, rest = idx / (NI * nel);
+        const int i2 = rest % NI, i3 = (rest / NI) % NI, c = rest / (NI * NI);
+        out[ev_index3<P>(g, e0 + el, c, k, i2, i3)] = (OT)Y[(((el * 3 + c) * NI + i3) * NI + i2) * NI + k];
     }
 }
 
@@ -424,18 +458,25 @@ struct QLay {
     static constexpr long STRIDE = qdata_stride(NS, NQT, sizeof(TT));
 };
 
-template <typename TT, int NS, int NQT>
+// NT: non-temporal loads, for a stream read once per call that should not
+// displace reused data from the caches (the stored tensor of the Hessian action).
+template <typename TT, int NS, int NQT, bool NT = false>
 __device__ __forceinline__ void qdata_load(const TT *__restrict__ he, int q, TT *out)
 {
     using L = QLay<TT, NS, NQT>;
+    typedef TT V __attribute__((ext_vector_type(L::VEC)));
 #pragma unroll
     for (int r = 0; r < L::NV; ++r) {
-        const Vec16<TT> w = *(const Vec16<TT> *)(he + ((long)r * NQT + q) * L::VEC);
+        const V *a = (const V *)(he + ((long)r * NQT + q) * L::VEC);
+        const V w = NT ? __builtin_nontemporal_load(a) : *a;
 #pragma unroll
-        for (int k = 0; k < L::VEC; ++k) out[r * L::VEC + k] = w.v[k];
+        for (int k = 0; k < L::VEC; ++k) out[r * L::VEC + k] = w[k];
     }
 #pragma unroll
-    for (int s = L::TAIL; s < NS; ++s) out[s] = he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q];
+    for (int s = L::TAIL; s < NS; ++s) {
+        const TT *a = he + (long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q;
+        out[s] = NT ? __builtin_nontemporal_load(a) : *a;
+    }
 }
 
 template <typename TT, int NS, int NQT>
@@ -650,7 +691,8 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
         // can leave all of them in flight
         const int t = threadIdx.x < npts ? threadIdx.x : 0;
         const int el = t / S::NQ3, q = t % S::NQ3;
-        qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q, hraw);
+        qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q,
+                                         hraw);
     }
     gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
     __syncthreads();
@@ -658,8 +700,8 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
     for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         if (!ONE)
-            qdata_load<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q,
-                                       hraw);
+            qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE,
+                                             q, hraw);
         CT hv[45];
 #pragma unroll
         for (int k = 0; k < 45; ++k) hv[k] = (CT)hraw[k];
@@ -675,7 +717,7 @@ __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const 
         if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
-    backward3<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
+    backward3<P, NQ, CT, CT, NR, LIM, true>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
 }
 
 // ------------------------------------------------------------------------
