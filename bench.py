@@ -34,15 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "fdae341fbc6c4020d4a04d8694a121f9deaa17ace9c6443299383f28b8be24cf"
+_SHA_C2 = "57b0ec15ecd44eeafbfb8dd36044913884e487555f742139c0f4f351307acbdd"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 688983372, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 720996486, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 358235613, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 369888148, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245852092, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 246715269, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 134706390, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135280078, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
@@ -73,8 +73,11 @@ WORKLOADS = {
 }
 
 
+_T0 = time.monotonic()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%7.1f s]" % (time.monotonic() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def copy_bandwidth(torch, nbytes=4 << 30, reps=5):

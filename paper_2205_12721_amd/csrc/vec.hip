@@ -75,7 +75,25 @@ __global__ __launch_bounds__(VBLOCK) void k_reduce3(const double *__restrict__ p
 {
     __shared__ double red[VBLOCK / 64];
     double s = 0.0, m = 1.0e300, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += VBLOCK) {
+    // loads in batches of RU strides, each lane's sums in the order of k
+    constexpr int RU = 8;
+    int k = threadIdx.x;
+    for (; k + (RU - 1) * VBLOCK < nb; k += RU * VBLOCK) {
+        double a[RU], c[RU], d[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            a[u] = part[k + u * VBLOCK];
+            c[u] = part[nb + k + u * VBLOCK];
+            d[u] = part[2 * nb + k + u * VBLOCK];
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            s += a[u];
+            m = fmin(m, c[u]);
+            b += d[u];
+        }
+    }
+    for (; k < nb; k += VBLOCK) {
         s += part[k];
         m = fmin(m, part[nb + k]);
         b += part[2 * nb + k];
@@ -95,7 +113,16 @@ __global__ __launch_bounds__(VBLOCK) void k_reduce_sum(const double *__restrict_
 {
     __shared__ double red[VBLOCK / 64];
     double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += VBLOCK) s += part[k];
+    constexpr int RU = 8;  // batched loads, sums in the order of k
+    int k = threadIdx.x;
+    for (; k + (RU - 1) * VBLOCK < nb; k += RU * VBLOCK) {
+        double a[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) a[u] = part[k + u * VBLOCK];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) s += a[u];
+    }
+    for (; k < nb; k += VBLOCK) s += part[k];
     s = block_sum(s, red);
     if (threadIdx.x == 0) *out = s;
 }
