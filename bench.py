@@ -277,6 +277,23 @@ def serve_leg(rate, nreq):
     }
 
 
+def serve_sweep(rates, nreq):
+    """The served stream at several arrival rates (same seed and size mix): p50/p99
+    latency and throughput per rate."""
+    from paper_2205_12721_amd import inputs, serve
+    out = []
+    for rate in rates:
+        reqs = inputs.serving_stream(rate, count=nreq, seed=6)
+        xs = serve.make_inputs(reqs)
+        budget = serve.budget_for(reqs, factor=1.0, cap=64 << 30)
+        s, _ = serve.serve(reqs, xs, budget, max_slots=min(512, nreq))
+        out.append({"rate_per_s": rate, "requests": nreq, "p50_ms": round(s["p50_ms"], 3),
+                    "p99_ms": round(s["p99_ms"], 3), "solves_per_s": round(s["solves_per_s"], 3),
+                    "solved": s["solved"], "ticks": s["ticks"]})
+        log("[bench] serve rate", rate, "p50", out[-1]["p50_ms"], "p99", out[-1]["p99_ms"])
+    return out
+
+
 # Sec. 4.1, Table tab_kershaw_baseline: GPU PA* (Jacobi) on 4 V100s, for context
 KERSHAW_PAPER = {1: (0.4, 11, 203), 2: (0.9, 18, 507), 3: (3.9, 41, 1536), 4: (8.5, 70, 3110)}
 
@@ -333,6 +350,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sweep", default="50,100,200,500,1000,2000",
+                    help="arrival rates (req/s) of the served-stream sweep; empty to skip")
+    ap.add_argument("--serve-sweep-requests", type=int, default=400)
     ap.add_argument("--kershaw-orders", default="1,2,3,4")
     ap.add_argument("--no-kershaw", action="store_true")
     args = ap.parse_args()
@@ -443,6 +463,9 @@ def main():
         log("[bench] batch leg done")
     if not args.no_serve:
         out["serve"] = serve_leg(args.serve_rate, args.serve_requests)
+        if args.serve_sweep:
+            rates = [float(r) for r in args.serve_sweep.split(",") if r]
+            out["serve"]["sweep"] = serve_sweep(rates, args.serve_sweep_requests)
         log("[bench] serve leg done")
 
     if not args.no_kershaw:
