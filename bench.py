@@ -143,6 +143,60 @@ def time_actions(ctx, x, v, reps):
     return e, t, epb, med
 
 
+def sweep_fma(dim, p, nq):
+    """Multiply-adds of the sum-factorized forward (or backward) sweeps of one
+    element, all components (Sec. 3.2): per component
+    2 n_i^3 n_q + 3 n_i^2 n_q^2 + 3 n_i n_q^3 in 3D, 2 n_i^2 n_q + 2 n_i n_q^2 in 2D."""
+    ni = p + 1
+    if dim == 3:
+        return 3 * (2 * ni ** 3 * nq + 3 * ni ** 2 * nq ** 2 + 3 * ni * nq ** 3)
+    return 2 * (2 * ni ** 2 * nq + 2 * ni * nq ** 2)
+
+
+def kernel_leg(ctx, x, ne, nqe, S, dim, p, nq, reps=20):
+    """The other steps of the path on the headline context, each call timed alone
+    (median of `reps`, HIP events on the context's stream): setup (a8), gradient
+    (a7), energy (a6), diagonal (a10).  Sweep GFLOP/s counts only the
+    sum-factorized sweeps (2 FLOP per multiply-add), not the point stage."""
+    import numpy as np
+    import torch
+    g = torch.empty_like(x)
+    d = torch.empty_like(x)
+
+    def med(f):
+        for _ in range(3):
+            f()
+        t = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(ctx._stream)
+            f()
+            b.record(ctx._stream)
+            b.synchronize()
+            t.append(a.elapsed_time(b) * 1e3)
+        return float(np.median(t))
+
+    fw = sweep_fma(dim, p, nq) * ne * 2.0   # FLOP of one set of sweeps over the mesh
+    t_setup = med(lambda: ctx.hessian_setup(x))
+    t_grad = med(lambda: ctx.gradient(x, g))
+    t_en = med(lambda: ctx.energy(x))
+    ctx.hessian_setup(x)
+    t_diag = med(lambda: ctx.hessian_diag(d))
+    tens = ne * nqe * S * 8
+    r2 = lambda v: round(v, 2)  # noqa: E731
+    return {
+        "setup": {"us": r2(t_setup), "tensor_GB_s_written": r2(tens / t_setup / 1e3),
+                  "sweep_GFLOP_s": r2(fw / t_setup / 1e3)},
+        "gradient": {"us": r2(t_grad), "GDoF_s": r2(ctx.ndof / t_grad / 1e3),
+                     "sweep_GFLOP_s": r2(2 * fw / t_grad / 1e3)},
+        "energy": {"us": r2(t_en), "sweep_GFLOP_s": r2(fw / t_en / 1e3),
+                   "note": "includes the copy of the result to the host"},
+        "diagonal": {"us": r2(t_diag), "tensor_GB_s_read": r2(tens / t_diag / 1e3)},
+        "action_GFLOP_s": None,
+    }
+
+
 def roofline(ne, nqe, S, ndof, tbytes, elem_ms, total_ms, traffic=None):
     t_app = total_ms / 1e3
     t_elem = elem_ms / 1e3
@@ -414,6 +468,11 @@ def main():
     gdofs = ctx.ndof / (med_ms / 1e3) / 1e9
     rf = roofline(ne, nqe, S, ctx.ndof, 8, elem_ms, tot_ms, traffic_for("tensor_fp64", cname, epb))
     rf["median_action_us"] = round(med_ms * 1e3, 2)
+    kl = kernel_leg(ctx, x0, ne, nqe, S, dim, p, nq)
+    # action FLOP: forward and backward sweeps plus the d^2 x d^2 point product
+    act_flop = 2.0 * ne * (2 * sweep_fma(dim, p, nq) + nqe * (dim * dim) ** 2)
+    kl["action_GFLOP_s"] = round(act_flop / (tot_ms / 1e3) / 1e9, 2)
+    log("[bench] kernel leg done")
     ms_step = acc["wall_s"] / args.steps * 1e3
 
     out = {
@@ -439,6 +498,7 @@ def main():
             "actions_timed": args.apply_reps, "elements_per_workgroup": epb,
         },
         "roofline": rf,
+        "kernels": kl,
         "step_gdof_s": round(ctx.ndof * args.minres / (ms_step / 1e3) / 1e9, 3),
         "phases_ms_per_step": {k: round(acc[k] / args.steps, 3)
                                for k in ("t_setup_ms", "t_minres_ms", "t_linesearch_ms")},
