@@ -212,7 +212,7 @@ int internal_target(const tmop_params *prm, int d, Target *tp)
 // Context
 // ---------------------------------------------------------------------------
 
-enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_HV, SV_V, SV_W, SV_W1, SV_W2, SV_COUNT };
+enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_V, SV_W, SV_W1, SV_W2, SV_COUNT };
 
 struct tmop_ctx {
     double *x0buf = nullptr;  // reference nodes of the limiting term (library copy)
@@ -666,53 +666,71 @@ static void make_jacobi(tmop_ctx *c)
 }
 
 // MINRES on H_c dx = b.  Buffers from the solver pool; device state
-// double-buffered in c->mst[0..1] (see vec.hip).
+// double-buffered in c->mst[0..1] (see vec.hip for the recurrences).
 static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
                        bool jacobi, int check_every, int *its_out)
 {
     CHK(ensure_solver(c));
     const long n = c->ndof;
-    double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *Y = c->sv[SV_Y], *HV = c->sv[SV_HV];
-    double *V = c->sv[SV_V], *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
-    double *part1 = c->part, *part2 = c->part + 1024;
+    // R1: r1, overwritten in place by hv; R2: r2; ZC: z_{j-1} (the element
+    // kernel's input, v_j = z_{j-1} / beta_j); ZP: z_{j-2}, then z_j
+    double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *ZC = c->sv[SV_Y], *ZP = c->sv[SV_V];
+    double *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
+    // part1 alternates between iterations (iteration j reads j-1's while writing its own)
+    double *P1[2] = {c->part, c->part + 2048};
+    double *P2 = c->part + 1024;
     const double *minv = jacobi ? c->minv : nullptr;
     const bool fp32 = c->precision == TMOP_MIXED;
-    mr_init(n, b, minv, R1, R2, Y, V, dx, W, W1, W2, part1, c->mst, rtol, c->s);
+    // z_{-1} = M^{-1} b goes to ZC; no separate v
+    mr_init(n, b, minv, R1, R2, ZC, nullptr, dx, W, W1, W2, P1[0], c->mst, rtol, c->s);
     c->tev_used = 0;
+    int J = 0;  // iterations run
     for (int j = 0; j < max_its; ++j) {
-        MinresState *sin = c->mst + (j & 1), *sout = c->mst + ((j + 1) & 1);
+        // S_{j-1} in mst[(j-1)&1], S_j to mst[j&1]
+        MinresState *sin = c->mst + ((j + 1) & 1), *sout = c->mst + (j & 1);
         const bool rec = c->timing && c->tev_used + 3 <= (int)c->tev.size();
         if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used], c->s));
-        apply_elem(c, V);
+        apply_elem(c, ZC);
         if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used + 1], c->s));
-        // G^T fused with the first Lanczos update
-        mr_gather_l1(c->g, c->csr_ptr, c->csr_ent, c->eV, fp32, j, sin, V, R1, HV, part1, c->s);
+        // deferred update of iteration j-1 (formula's w1, w2 = buffers W2, W;
+        // new w into W1), then G^T with the first Lanczos update into R1
+        mr_gather_upd(c->g, c->csr_ptr, c->csr_ent, c->eV, fp32, j, sin, sout, P1[(j + 1) & 1],
+                      P2, ZP, ZC, W2, W, W1, dx, R1, P1[j & 1], c->s);
         if (rec) {
             HIPCHK(hipEventRecord(c->tev[c->tev_used + 2], c->s));
             c->tev_used += 3;
         }
-        // z goes to the old r1 buffer (r1 is dead after gather_l1)
-        mr_lanczos2(n, j, sin, part1, HV, R2, minv, R1, part2, c->s);
-        // new w goes to the old w1 buffer; (w1, w2) of the formula = (old w2, old w)
-        mr_update(n, j, sin, sout, part1, part2, V, W2, W, W1, dx, R1, c->s);
-        double *oR1 = R1, *oR2 = R2, *oHV = HV;
-        R1 = oR2;
-        R2 = oHV;
-        HV = oR1;
-        double *oW = W, *oW1 = W1, *oW2 = W2;
-        W1 = oW2;
-        W2 = oW;
-        W = oW1;
+        // z_j into ZP (z_{j-2} is dead after the update above)
+        mr_lanczos2(n, j, sout, P1[j & 1], R1, R2, minv, ZP, P2, c->s);
+        std::swap(R1, R2);  // r1 <- r2, r2 <- hv
+        std::swap(ZP, ZC);  // z_{j-1}, z_j
+        if (j >= 1) {
+            double *oW = W, *oW1 = W1, *oW2 = W2;
+            W1 = oW2;
+            W2 = oW;
+            W = oW1;
+        }
+        J = j + 1;
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
             HIPCHK(hipMemcpyAsync(c->hmst, sout, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipStreamSynchronize(c->s));
             if (c->hmst->stop != 0x7fffffff) break;
         }
     }
+    // the update of the last iteration run
+    if (J > 0) {
+        mr_finish(n, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2, ZP, W2,
+                  W, W1, dx, c->s);
+        double *oW = W, *oW1 = W1, *oW2 = W2;
+        W1 = oW2;
+        W2 = oW;
+        W = oW1;
+    }
+    c->sv[SV_Y] = ZC;
+    c->sv[SV_V] = ZP;
     // keep the rotated pointers consistent for the next call
     c->sv[SV_R1] = R1;
     c->sv[SV_R2] = R2;
-    c->sv[SV_HV] = HV;
     c->sv[SV_W] = W;
     c->sv[SV_W1] = W1;
     c->sv[SV_W2] = W2;

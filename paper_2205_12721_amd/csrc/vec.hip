@@ -231,18 +231,24 @@ void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hi
 // Preconditioned MINRES (Paige-Saunders), device-resident scalars.
 //
 // Lanczos on M^{-1} H with the three-term recurrence, Givens QR of the
-// tridiagonal matrix, short-recurrence update of the solution.  Per
-// iteration j, after the element kernel has produced the E-vector of H v:
-//   gather_l1:  hv = G^T eV (fixed DoFs: v);  hv -= (beta/oldb) r1;  part1 = <v, hv>
-//   l2:         alpha = sum part1;  hv -= (alpha/beta) r2;  z = M^{-1} hv;  part2 = <hv, z>
-//   update:     beta' = sqrt(sum part2), Givens rotation, phi;
-//               w' = (v - oldeps w1 - delta w2)/gamma;  x += phi w';  v = z/beta'
+// tridiagonal matrix, short-recurrence update of the solution.  The Lanczos
+// vector v_j = z_{j-1} / beta_j is never written: the element kernel runs on
+// z_{j-1} and the gather scales its result by 1/beta_j (H is linear).  Per
+// iteration j, after the element kernel has produced the E-vector of H z_{j-1}:
+//   gather_upd: the update of iteration j-1, deferred to here (its scalars
+//               need beta_j, known only after the previous l2):
+//                 Givens rotation, phi;  w' = (v_{j-1} - oldeps w1 - delta w2)/gamma;
+//                 x += phi w'
+//               then hv = G^T eV / beta_j (fixed DoFs: v_j) - (beta_j/beta_{j-1}) r1
+//               (in place of r1);  part1 = <v_j, hv>
+//   l2:         alpha = sum part1;  hv -= (alpha/beta) r2;  z_j = M^{-1} hv;  part2 = <hv, z_j>
+// and after the last iteration a finishing pass applies its deferred update.
 // The scalar recurrences run redundantly in every workgroup (same partials,
 // same order, same result) so no single-lane kernels sit between the vector
-// passes; the state is double-buffered (iteration j reads st[j&1], the update
-// writes st[(j+1)&1], also when it skips, so the stop flag propagates).
-// Kernels of iteration j return at once when j > stop (set when the residual
-// estimate drops below rtol*beta1 or the Lanczos vector vanishes).
+// passes; the state is double-buffered (the state after the update of
+// iteration j - 1 goes to st[j&1], also when nothing runs, so the stop flag
+// propagates).  Work of iteration j is skipped when j > stop (set when the
+// residual estimate drops below rtol*beta1 or the Lanczos vector vanishes).
 // ------------------------------------------------------------------------
 
 // Sum of part[0..nb) in a fixed order, identical in every workgroup.
@@ -293,7 +299,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, do
     const double b1 = sqrt(fmax(bb, 0.0));
     const double s = b1 > 0.0 ? 1.0 / b1 : 0.0;
     for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
-        v[i] = s * y[i];
+        if (v) v[i] = s * y[i];
         x[i] = 0.0;
         w[i] = 0.0;
         w1[i] = 0.0;
@@ -323,38 +329,138 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, do
     }
 }
 
-template <int DIM, typename ET>
-__global__ __launch_bounds__(VBLOCK) void k_mr_gather_l1(Geom g, const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ ent,
-                                                         const ET *__restrict__ eV, int j,
-                                                         const MinresState *__restrict__ st,
-                                                         const double *__restrict__ v,
-                                                         const double *__restrict__ r1,
-                                                         double *__restrict__ hv,
-                                                         double *__restrict__ part)
+// Scalars of the update of iteration jm (Givens rotation of the Lanczos
+// tridiagonal matrix) from the state before it, alpha_jm and beta_{jm+1}^2.
+struct MrUpd {
+    MinresState o;  // state after the update
+    double ig, oldeps, delta, phi;
+};
+
+__device__ inline MrUpd mr_scalars(const MinresState &sin, int jm, double alpha, double bb)
 {
-    if (j > st->stop) return;
+    MrUpd u;
+    const double beta = sqrt(fmax(bb, 0.0));
+    u.oldeps = sin.eps;
+    u.delta = sin.cs * sin.dbar + sin.sn * alpha;
+    const double gbar = sin.sn * sin.dbar - sin.cs * alpha;
+    const double eps = sin.sn * beta;
+    const double dbar = -sin.cs * beta;
+    const double gamma = fmax(hypot(gbar, beta), 2.2250738585072014e-308);
+    const double cs = gbar / gamma, sn = beta / gamma;
+    u.phi = cs * sin.phibar;
+    const double phibar = sn * sin.phibar;
+    u.ig = 1.0 / gamma;
+    MinresState o = sin;
+    o.tmp = bb;
+    o.alpha = alpha;
+    o.oldb = sin.beta;
+    o.beta = beta;
+    o.oldeps = u.oldeps;
+    o.eps = eps;
+    o.dbar = dbar;
+    o.delta = u.delta;
+    o.gamma = gamma;
+    o.cs = cs;
+    o.sn = sn;
+    o.phi = u.phi;
+    o.phibar = phibar;
+    o.its = jm + 1;
+    if (bb < 0.0) o.indefinite_precond = 1;
+    if (phibar <= sin.rtol * sin.beta1 || beta == 0.0) o.stop = jm;
+    u.o = o;
+    return u;
+}
+
+// Iteration j after the element kernel ran on z_{j-1} (the Lanczos vector
+// v_j = z_{j-1} / beta_j, left unscaled so that nothing writes v):
+//   the deferred update of iteration j-1 (state S_{j-1} -> S_j, from the
+//   partials of alpha_{j-1} and beta_j^2):
+//     w' = (z_{j-2}/beta_{j-1} - oldeps w1 - delta w2) / gamma;  x += phi w'
+//   then hv = G^T eV / beta_j (fixed DoFs: v_j) - (beta_j/beta_{j-1}) r1, in
+//   place of r1;  part1 = <v_j, hv>.
+template <int DIM, typename ET>
+__global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
+    Geom g, const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
+    const ET *__restrict__ eV, int j, const MinresState *__restrict__ sin,
+    MinresState *__restrict__ sout, const double *__restrict__ p1prev,
+    const double *__restrict__ p2prev, int nb, const double *__restrict__ zp,
+    const double *__restrict__ zc, const double *__restrict__ w1, const double *__restrict__ w2,
+    double *__restrict__ wout, double *__restrict__ x, double *__restrict__ r1hv,
+    double *__restrict__ part)
+{
     __shared__ double red[VBLOCK / 64];
-    const double cr = j >= 1 ? st->beta / st->oldb : 0.0;
+    const MinresState S = *sin;
+    const bool upd = j >= 1 && j - 1 <= S.stop;
+    MrUpd u{};
+    u.o = S;
+    if (upd) {
+        const double alpha = sum_partials(p1prev, nb, red);
+        const double bb = sum_partials(p2prev, nb, red);
+        u = mr_scalars(S, j - 1, alpha, bb);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sout = u.o;
+    const bool gat = j <= u.o.stop;
+    if (!upd && !gat) return;
+    const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;      // v_{j-1} = sp z_{j-2}
+    const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;  // v_j = sc z_{j-1}
+    const double cr = j >= 1 ? u.o.beta / u.o.oldb : 0.0;
     double s = 0.0;
     // one lane per node, all components
     for (int node = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; node < g.nx;
          node += gridDim.x * VBLOCK) {
         double a[DIM];
         bool fixed[DIM];
-        gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
+        if (gat) gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t idx = (size_t)c * g.nx + node;
-            const double vi = v[idx];
-            double h = fixed[c] ? vi : a[c];
-            if (j >= 1) h -= cr * r1[idx];
-            hv[idx] = h;
-            s += vi * h;
+            if (upd) {
+                const double wn = (sp * zp[idx] - u.oldeps * w1[idx] - u.delta * w2[idx]) * u.ig;
+                wout[idx] = wn;
+                x[idx] += u.phi * wn;
+            }
+            if (gat) {
+                const double vi = sc * zc[idx];
+                double h = fixed[c] ? vi : sc * a[c];
+                if (j >= 1) h -= cr * r1hv[idx];
+                r1hv[idx] = h;
+                s += vi * h;
+            }
         }
     }
+    if (!gat) return;
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// The update of the last iteration jm run (deferred past the loop).
+__global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
+                                                      const MinresState *__restrict__ sin,
+                                                      MinresState *__restrict__ sout,
+                                                      const double *__restrict__ p1,
+                                                      const double *__restrict__ p2, int nb,
+                                                      const double *__restrict__ zp,
+                                                      const double *__restrict__ w1,
+                                                      const double *__restrict__ w2,
+                                                      double *__restrict__ wout,
+                                                      double *__restrict__ x)
+{
+    __shared__ double red[VBLOCK / 64];
+    const MinresState S = *sin;
+    if (jm < 0 || jm > S.stop) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *sout = S;
+        return;
+    }
+    const double alpha = sum_partials(p1, nb, red);
+    const double bb = sum_partials(p2, nb, red);
+    const MrUpd u = mr_scalars(S, jm, alpha, bb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sout = u.o;
+    const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
+    for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
+        const double wn = (sp * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
+        wout[i] = wn;
+        x[i] += u.phi * wn;
+    }
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresState *__restrict__ st,
@@ -381,66 +487,6 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresSta
     if (threadIdx.x == 0) part2[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(VBLOCK) void k_mr_update(long n, int j,
-                                                      const MinresState *__restrict__ sin,
-                                                      MinresState *__restrict__ sout,
-                                                      const double *__restrict__ part1,
-                                                      const double *__restrict__ part2, int nb,
-                                                      double *__restrict__ v,
-                                                      const double *__restrict__ w1,
-                                                      const double *__restrict__ w2,
-                                                      double *__restrict__ wout,
-                                                      double *__restrict__ x,
-                                                      const double *__restrict__ z)
-{
-    if (j > sin->stop) {
-        // carry the stopped state forward so later iterations see it
-        if (blockIdx.x == 0 && threadIdx.x == 0) *sout = *sin;
-        return;
-    }
-    __shared__ double red[VBLOCK / 64];
-    const double alpha = sum_partials(part1, nb, red);
-    const double bb = sum_partials(part2, nb, red);
-    const double beta = sqrt(fmax(bb, 0.0));
-    const double oldeps = sin->eps;
-    const double delta = sin->cs * sin->dbar + sin->sn * alpha;
-    const double gbar = sin->sn * sin->dbar - sin->cs * alpha;
-    const double eps = sin->sn * beta;
-    const double dbar = -sin->cs * beta;
-    const double gamma = fmax(hypot(gbar, beta), 2.2250738585072014e-308);
-    const double cs = gbar / gamma, sn = beta / gamma;
-    const double phi = cs * sin->phibar;
-    const double phibar = sn * sin->phibar;
-    const double ig = 1.0 / gamma;
-    const double sv = beta > 0.0 ? 1.0 / beta : 0.0;
-    for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
-        const double wn = (v[i] - oldeps * w1[i] - delta * w2[i]) * ig;
-        wout[i] = wn;
-        x[i] += phi * wn;
-        v[i] = sv * z[i];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        MinresState o = *sin;
-        o.tmp = bb;
-        o.alpha = alpha;
-        o.oldb = sin->beta;
-        o.beta = beta;
-        o.oldeps = oldeps;
-        o.eps = eps;
-        o.dbar = dbar;
-        o.delta = delta;
-        o.gamma = gamma;
-        o.cs = cs;
-        o.sn = sn;
-        o.phi = phi;
-        o.phibar = phibar;
-        o.its = j + 1;
-        if (bb < 0.0) o.indefinite_precond = 1;
-        if (phibar <= sin->rtol * sin->beta1 || beta == 0.0) o.stop = j;
-        *sout = o;
-    }
-}
-
 void mr_init(long n, const double *b, const double *minv, double *r1, double *r2, double *y,
              double *v, double *x, double *w, double *w1, double *w2, double *part,
              MinresState *st, double rtol, hipStream_t s)
@@ -451,14 +497,18 @@ void mr_init(long n, const double *b, const double *minv, double *r1, double *r2
                        w, w1, w2);
 }
 
-void mr_gather_l1(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
-                  bool fp32, int j, const MinresState *st, const double *v, const double *r1,
-                  double *hv, double *part, hipStream_t s)
+void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
+                   bool fp32, int j, const MinresState *sin, MinresState *sout,
+                   const double *p1prev, const double *p2prev, const double *zp, const double *zc,
+                   const double *w1, const double *w2, double *wout, double *x, double *r1hv,
+                   double *part, hipStream_t s)
 {
+    // the partials of every kernel of the iteration use the same block count
     const int nb = reduce_blocks((long)g.dim * g.nx);
-#define TMOP_G(D, T)                                                                            \
-    hipLaunchKernelGGL((k_mr_gather_l1<D, T>), dim3(nb), dim3(VBLOCK), 0, s, g, csr_ptr, csr_ent, \
-                       (const T *)eV, j, st, v, r1, hv, part);
+#define TMOP_G(D, T)                                                                           \
+    hipLaunchKernelGGL((k_mr_gather_upd<D, T>), dim3(nb), dim3(VBLOCK), 0, s, g, csr_ptr,      \
+                       csr_ent, (const T *)eV, j, sin, sout, p1prev, p2prev, nb, zp, zc, w1, w2, \
+                       wout, x, r1hv, part);
     if (g.dim == 3) {
         if (fp32) {
             TMOP_G(3, float)
@@ -483,13 +533,13 @@ void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, doub
                        part2);
 }
 
-void mr_update(long n, int j, const MinresState *sin, MinresState *sout, const double *part1,
-               const double *part2, double *v, const double *w1, const double *w2, double *wout,
-               double *x, const double *z, hipStream_t s)
+void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
+               const double *p2, const double *zp, const double *w1, const double *w2,
+               double *wout, double *x, hipStream_t s)
 {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mr_update, dim3(nb), dim3(VBLOCK), 0, s, n, j, sin, sout, part1, part2, nb,
-                       v, w1, w2, wout, x, z);
+    hipLaunchKernelGGL(k_mr_finish, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, p2, nb, zp,
+                       w1, w2, wout, x);
 }
 
 }  // namespace tmop

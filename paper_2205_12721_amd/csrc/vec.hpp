@@ -32,13 +32,15 @@ void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hi
 void mr_init(long n, const double *b, const double *minv, double *r1, double *r2, double *y,
              double *v, double *x, double *w, double *w1, double *w2, double *part,
              MinresState *st, double rtol, hipStream_t s);
-void mr_gather_l1(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
-                  bool fp32, int j, const MinresState *st, const double *v, const double *r1,
-                  double *hv, double *part, hipStream_t s);
+void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
+                   bool fp32, int j, const MinresState *sin, MinresState *sout,
+                   const double *p1prev, const double *p2prev, const double *zp, const double *zc,
+                   const double *w1, const double *w2, double *wout, double *x, double *r1hv,
+                   double *part, hipStream_t s);
 void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, double *hv,
                  const double *r2, const double *minv, double *z, double *part2, hipStream_t s);
-void mr_update(long n, int j, const MinresState *sin, MinresState *sout, const double *part1,
-               const double *part2, double *v, const double *w1, const double *w2, double *wout,
-               double *x, const double *z, hipStream_t s);
+void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
+               const double *p2, const double *zp, const double *w1, const double *w2,
+               double *wout, double *x, hipStream_t s);
 
 }  // namespace tmop
