@@ -64,6 +64,8 @@ enum { SC_F, SC_MD, SC_BAD, SC_DOT, SC_DMAX, SC_ALPHA, NSC = 8 };
 struct BState {
     double beta1, beta, oldb, dbar, eps, phibar, cs, sn, rtol;
     int j, maxit, stop, indefinite;
+    int first;  // no iteration has run yet (no update pending)
+    int pad;
 };
 
 __device__ inline bool bs_skip(const BState &s) { return s.j > s.stop || s.j >= s.maxit; }
@@ -271,11 +273,11 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
     const SlotRange r = rg[t.slot];
     const double bb = seg_sum(part, r.vbegin, r.vcount, red);
     const double b1 = sqrt(fmax(bb, 0.0));
-    const double sv = b1 > 0.0 ? 1.0 / b1 : 0.0;
     const double *y = S.vec[BY];
+    // z_{-1} = M^{-1} b, unscaled (the first Lanczos vector is z_{-1} / beta1)
     double *v = S.vec[BV], *x = S.vec[BDX], *w = S.vec[BW], *w1 = S.vec[BW1], *w2 = S.vec[BW2];
     for (int i = i0; i < i1; i += VB) {
-        v[i] = sv * y[i];
+        v[i] = y[i];
         x[i] = 0.0;
         w[i] = 0.0;
         w1[i] = 0.0;
@@ -296,44 +298,111 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
         o.maxit = maxit[t.slot];
         o.stop = (b1 > 0.0 && bb >= 0.0) ? 0x7fffffff : -1;
         o.indefinite = bb < 0.0 ? 1 : 0;
+        o.first = 1;
+        o.pad = 0;
         st[2 * t.slot] = o;
         st[2 * t.slot + 1] = o;
         run[t.slot] = bs_skip(o) ? 0 : 1;
     }
 }
 
+// Update of iteration si.j (Givens rotation) from the state before it and
+// the slot's partials of alpha_j and beta_{j+1}^2.
+struct BUpd {
+    BState o;
+    double ig, oldeps, delta, phi;
+};
+
+__device__ inline BUpd bs_update(const BState &si, double alpha, double bb)
+{
+    BUpd u;
+    const double beta = sqrt(fmax(bb, 0.0));
+    u.oldeps = si.eps;
+    u.delta = si.cs * si.dbar + si.sn * alpha;
+    const double gbar = si.sn * si.dbar - si.cs * alpha;
+    const double gamma = fmax(hypot(gbar, beta), 2.2250738585072014e-308);
+    const double cs = gbar / gamma, sn = beta / gamma;
+    u.phi = cs * si.phibar;
+    u.ig = 1.0 / gamma;
+    BState o = si;
+    o.oldb = si.beta;
+    o.beta = beta;
+    o.eps = si.sn * beta;
+    o.dbar = -si.cs * beta;
+    o.cs = cs;
+    o.sn = sn;
+    o.phibar = sn * si.phibar;
+    if (bb < 0.0) o.indefinite = 1;
+    if (o.phibar <= si.rtol * si.beta1 || beta == 0.0) o.stop = si.j;
+    o.j = si.j + 1;
+    u.o = o;
+    return u;
+}
+
+// One lockstep position, after the element kernel ran on z_{j-1} (the
+// Lanczos vector v_j = z_{j-1} / beta_j is never written).  Per slot: the
+// deferred update of the iteration before (state st[par^1] -> st[par]):
+//   w' = (z_{j-2}/beta_{j-1} - oldeps w1 - delta w2)/gamma;  x += phi w'
+// then, while the slot runs, hv = G^T eV / beta_j (fixed DoFs: v_j)
+// - (beta_j/beta_{j-1}) r1 in place of r1 and the partials of <v_j, hv>.
+// Every iterating slot writes its state (carried forward when nothing runs)
+// and its run flag.
 template <int DIM, typename ET>
-__global__ __launch_bounds__(VB) void kv_mr_gather_l1(const VTile *__restrict__ vt,
-                                                      const SlotDev *__restrict__ slots,
-                                                      const int *__restrict__ gate,
-                                                      const BState *__restrict__ st, int par,
-                                                      int vr1, int vhv,
-                                                      double *__restrict__ part)
+__global__ __launch_bounds__(VB) void kv_mr_gather_upd(
+    const VTile *__restrict__ vt, const SlotDev *__restrict__ slots, const int *__restrict__ gate,
+    const SlotRange *__restrict__ rg, BState *__restrict__ st, int par,
+    const double *__restrict__ p1prev, const double *__restrict__ p2, int vr1, int vzc, int vzp,
+    int vw1, int vw2, int vwout, double *__restrict__ part, int pbase, int *__restrict__ run)
 {
     VT_PROLOGUE
-    const BState &s = st[2 * t.slot + par];
-    if (bs_skip(s)) return;
     __shared__ double red[VB / 64];
-    const double cr = s.j >= 1 ? s.beta / s.oldb : 0.0;
+    const BState sp = st[2 * t.slot + (par ^ 1)];
+    const bool upd = !sp.first && !bs_skip(sp);
+    BUpd u{};
+    u.o = sp;
+    if (upd) {
+        const SlotRange r = rg[t.slot];
+        const double alpha = seg_sum(p1prev, r.vbegin, r.vcount, red);
+        const double bb = seg_sum(p2, r.vbegin, r.vcount, red);
+        u = bs_update(sp, alpha, bb);
+    }
+    u.o.first = 0;
+    const bool gat = !bs_skip(u.o);
+    if (t.start == 0 && threadIdx.x == 0) {
+        st[2 * t.slot + par] = u.o;
+        run[t.slot] = gat ? 1 : 0;
+    }
+    if (!upd && !gat) return;
     const Geom &g = S.g;
     const ET *eV = (const ET *)S.eV;
-    const double *v = S.vec[BV], *r1 = S.vec[vr1];
-    double *hv = S.vec[vhv];
+    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
+    const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;
+    const double cr = u.o.j >= 1 ? u.o.beta / u.o.oldb : 0.0;
+    const double *zc = S.vec[vzc], *zp = S.vec[vzp], *w1 = S.vec[vw1], *w2 = S.vec[vw2];
+    double *r1 = S.vec[vr1], *x = S.vec[BDX], *wo = S.vec[vwout];
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
-        const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
-        const int node = i - c * g.nx;
-        int gc[3];
-        box_coords<DIM>(g, node, gc);
-        const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
-        const double vi = v[i];
-        double h = fixed ? vi : (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
-        if (s.j >= 1) h -= cr * r1[i];
-        hv[i] = h;
-        acc += vi * h;
+        if (upd) {
+            const double wn = (sprev * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
+            wo[i] = wn;
+            x[i] += u.phi * wn;
+        }
+        if (gat) {
+            const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
+            const int node = i - c * g.nx;
+            int gc[3];
+            box_coords<DIM>(g, node, gc);
+            const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
+            const double vi = sc * zc[i];
+            double h = fixed ? vi : sc * (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
+            if (u.o.j >= 1) h -= cr * r1[i];
+            r1[i] = h;
+            acc += vi * h;
+        }
     }
+    if (!gat) return;
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[pbase + blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
@@ -367,61 +436,39 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
     if (threadIdx.x == 0) part2[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(VB) void kv_mr_update(const VTile *__restrict__ vt,
+// The deferred update of the last iteration of every slot still running
+// after the lockstep loop (state st[par] -> st[par^1]); every slot's run flag
+// is cleared (the element kernels of later MINRES calls are gated by it).
+__global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
                                                    const SlotDev *__restrict__ slots,
                                                    const int *__restrict__ gate,
                                                    const SlotRange *__restrict__ rg,
                                                    BState *__restrict__ st, int par,
-                                                   const double *__restrict__ part1,
-                                                   const double *__restrict__ part2, int vw1,
-                                                   int vw2, int vwout, int vz,
+                                                   const double *__restrict__ p1,
+                                                   const double *__restrict__ p2, int vzp,
+                                                   int vw1, int vw2, int vwout,
                                                    int *__restrict__ run)
 {
     VT_PROLOGUE
-    const BState si = st[2 * t.slot + par];
-    BState *so = st + 2 * t.slot + (par ^ 1);
-    if (bs_skip(si)) {
-        if (t.start == 0 && threadIdx.x == 0) {
-            *so = si;
-            run[t.slot] = 0;
-        }
+    __shared__ double red[VB / 64];
+    const BState sp = st[2 * t.slot + par];
+    if (t.start == 0 && threadIdx.x == 0) run[t.slot] = 0;
+    if (sp.first || bs_skip(sp)) {
+        if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = sp;
         return;
     }
-    __shared__ double red[VB / 64];
     const SlotRange r = rg[t.slot];
-    const double alpha = seg_sum(part1, r.vbegin, r.vcount, red);
-    const double bb = seg_sum(part2, r.vbegin, r.vcount, red);
-    const double beta = sqrt(fmax(bb, 0.0));
-    const double oldeps = si.eps;
-    const double delta = si.cs * si.dbar + si.sn * alpha;
-    const double gbar = si.sn * si.dbar - si.cs * alpha;
-    const double gamma = fmax(hypot(gbar, beta), 2.2250738585072014e-308);
-    const double cs = gbar / gamma, sn = beta / gamma;
-    const double phi = cs * si.phibar;
-    const double ig = 1.0 / gamma;
-    const double sv = beta > 0.0 ? 1.0 / beta : 0.0;
-    double *v = S.vec[BV], *x = S.vec[BDX], *wo = S.vec[vwout];
-    const double *w1 = S.vec[vw1], *w2 = S.vec[vw2], *z = S.vec[vz];
+    const double alpha = seg_sum(p1, r.vbegin, r.vcount, red);
+    const double bb = seg_sum(p2, r.vbegin, r.vcount, red);
+    const BUpd u = bs_update(sp, alpha, bb);
+    if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = u.o;
+    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
+    const double *zp = S.vec[vzp], *w1 = S.vec[vw1], *w2 = S.vec[vw2];
+    double *x = S.vec[BDX], *wo = S.vec[vwout];
     for (int i = i0; i < i1; i += VB) {
-        const double wn = (v[i] - oldeps * w1[i] - delta * w2[i]) * ig;
+        const double wn = (sprev * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
         wo[i] = wn;
-        x[i] += phi * wn;
-        v[i] = sv * z[i];
-    }
-    if (t.start == 0 && threadIdx.x == 0) {
-        BState o = si;
-        o.oldb = si.beta;
-        o.beta = beta;
-        o.eps = si.sn * beta;
-        o.dbar = -si.cs * beta;
-        o.cs = cs;
-        o.sn = sn;
-        o.phibar = sn * si.phibar;
-        if (bb < 0.0) o.indefinite = 1;
-        if (o.phibar <= si.rtol * si.beta1 || beta == 0.0) o.stop = si.j;
-        o.j = si.j + 1;
-        *so = o;
-        run[t.slot] = bs_skip(o) ? 0 : 1;
+        x[i] += u.phi * wn;
     }
 }
 
@@ -734,7 +781,7 @@ static int pool_rebuild(tmop_pool *P)
         PHIP(hipMalloc((void **)&P->d_vt, sizeof(VTile) * P->vt_cap));
     }
     if (nvt) PHIP(hipMemcpyAsync(P->d_vt, P->vts.data(), sizeof(VTile) * nvt, hipMemcpyHostToDevice, P->s));
-    const size_t need = (size_t)P->epart + 2 * (size_t)nvt + 64;
+    const size_t need = (size_t)P->epart + 3 * (size_t)nvt + 64;
     if (need > P->part_cap) {
         hipFree(P->d_part);
         P->d_part = nullptr;
@@ -751,6 +798,12 @@ static int pool_rebuild(tmop_pool *P)
 
 static double *vpart1(tmop_pool *P) { return P->d_part + P->epart; }
 static double *vpart2(tmop_pool *P) { return P->d_part + P->epart + P->vts.size(); }
+// the first-Lanczos partials alternate between lockstep positions (a position
+// reads the previous one's while writing its own)
+static double *vpart1_at(tmop_pool *P, int par)
+{
+    return par ? P->d_part + P->epart + 2 * P->vts.size() : vpart1(P);
+}
 
 static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
 {
@@ -823,36 +876,48 @@ static int read_sc(tmop_pool *P)
     return TMOP_OK;
 }
 
-// one lockstep MINRES iteration for all running slots; ids rotate with k
+// vector ids of lockstep position k: r1 (overwritten in place by hv) and r2
+// swap every position, as do z_{j-1} (the element kernel's input) and
+// z_{j-2} (overwritten by z_j); (w, w1, w2) of the update of iteration m
+// rotate with period 3: W[m % 3]
+static const int MR_W[3][3] = {{BW, BW1, BW2}, {BW1, BW2, BW}, {BW2, BW, BW1}};
+static int mr_r1(int k) { return (k & 1) ? BR2 : BR1; }
+static int mr_r2(int k) { return (k & 1) ? BR1 : BR2; }
+static int mr_zc(int k) { return (k & 1) ? BHV : BV; }
+static int mr_zp(int k) { return (k & 1) ? BV : BHV; }
+
+// one lockstep MINRES iteration for all running slots (see vec.hip for the
+// recurrences; here the update of iteration j - 1 runs in position j's gather)
 static void minres_iter(tmop_pool *P, int k)
 {
-    // ids of (r1, r2, hv) rotate with period 3, (w, w1, w2) likewise; state parity period 2
-    static const int R[3][3] = {{BR1, BR2, BHV}, {BR2, BHV, BR1}, {BHV, BR1, BR2}};
-    static const int W[3][3] = {{BW, BW1, BW2}, {BW1, BW2, BW}, {BW2, BW, BW1}};
-    const int r1 = R[k % 3][0], r2 = R[k % 3][1], hv = R[k % 3][2];
-    const int w = W[k % 3][0], w1 = W[k % 3][1], w2 = W[k % 3][2];
+    const int r1 = mr_r1(k), r2 = mr_r2(k), zc = mr_zc(k), zp = mr_zp(k);
+    const int *W = MR_W[(k + 2) % 3];  // update of iteration k - 1
     const int par = k & 1;
-    launch_elem(P, 3, P->d_run, BV);
+    double *p1 = vpart1_at(P, par);
+    const double *p1prev = vpart1_at(P, par ^ 1);
+    launch_elem(P, 3, P->d_run, zc);
     for (int grp = 0; grp < 4; ++grp) {
         const int b = P->vt_range[grp][0], n = P->vt_range[grp][1];
         if (!n) continue;
         const VTile *vt = P->d_vt + b;
-        double *pp = vpart1(P) + b;
+        // formula (w1, w2) = (ids w2, w), new w into id w1
+#define TMOP_KG(D, T)                                                                           \
+    hipLaunchKernelGGL((kv_mr_gather_upd<D, T>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots,   \
+                       P->d_gate[1], P->d_rg, P->d_st, par, p1prev, vpart2(P), r1, zc, zp,     \
+                       W[2], W[0], W[1], p1, b, P->d_run);
         if (grp == 0)
-            hipLaunchKernelGGL((kv_mr_gather_l1<3, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+            TMOP_KG(3, double)
         else if (grp == 1)
-            hipLaunchKernelGGL((kv_mr_gather_l1<3, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+            TMOP_KG(3, float)
         else if (grp == 2)
-            hipLaunchKernelGGL((kv_mr_gather_l1<2, double>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+            TMOP_KG(2, double)
         else
-            hipLaunchKernelGGL((kv_mr_gather_l1<2, float>), dim3(n), dim3(VB), 0, P->s, vt, P->d_slots, P->d_run, P->d_st, par, r1, hv, pp);
+            TMOP_KG(2, float)
+#undef TMOP_KG
     }
     const int n = nvt_all(P);
-    // z goes to the r1 buffer (r1 is dead after gather_l1)
-    hipLaunchKernelGGL(kv_mr_l2, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_jac, P->d_st, par, vpart1(P), hv, r2, r1, vpart2(P));
-    // new w into the old w1 buffer; formula (w1, w2) = (old w2, old w)
-    hipLaunchKernelGGL(kv_mr_update, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_st, par, vpart1(P), vpart2(P), w2, w, w1, r1, P->d_run);
-    (void)w;
+    // hv -> r2 of the next position (in place in r1); z_j into zp
+    hipLaunchKernelGGL(kv_mr_l2, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_jac, P->d_st, par, p1, r1, r2, zp, vpart2(P));
 }
 
 static int run_minres(tmop_pool *P, int maxj)
@@ -886,6 +951,13 @@ static int run_minres(tmop_pool *P, int maxj)
             for (int si = 0; si < P->max_slots; ++si) any = any || (P->slots[si].used && P->h_int[si]);
             if (!any) break;
         }
+    }
+    if (j > 0) {
+        // the deferred update of the last iteration run (position k = (j - 1) % 6,
+        // whose element-kernel input z_{j-2} gives v_{j-1})
+        const int k = (j - 1) % 6, par = k & 1;
+        const int *W = MR_W[(j - 1) % 3];
+        hipLaunchKernelGGL(kv_mr_finish, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_st, par, vpart1_at(P, par), vpart2(P), mr_zc(k), W[2], W[0], W[1], P->d_run);
     }
     PHIP(hipMemcpyAsync(P->h_st, P->d_st, sizeof(BState) * 2 * P->max_slots, hipMemcpyDeviceToHost, P->s));
     PHIP(hipStreamSynchronize(P->s));
