@@ -885,7 +885,7 @@ template <int P, int NQ, bool LIM = false>
 struct DiagLds3 {
     using S = S3<P, NQ>;
     static constexpr int NPR = LIM ? 7 : 6;
-    double T[3][NQ * S::NI];  // BB, BG, GG
+    double T[3][NQ * S::NI];  // B B, B G, G G at (chi_q, node i)
     double sQ[S::EPB * NPR * 3 * S::NQ3];
     double U2[S::EPB * 3 * S::NI * NQ * NQ];
     double U1[S::EPB * 3 * S::NI * S::NI * NQ];
@@ -895,6 +895,21 @@ struct DiagLds3 {
 // pair pr < 6: (n, p) = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2); pr = 6: value term
 __device__ constexpr int diag_pn(int pr) { return pr < 3 ? 0 : (pr < 5 ? 1 : 2); }
 __device__ constexpr int diag_pp(int pr) { return pr < 3 ? pr : (pr < 5 ? pr - 2 : 2); }
+
+// One 1D line of the diagonal contraction: out[i] = sum_q Tt[q*NI + i] y[q],
+// Tt the product table of the axis in LDS; every lane reads the same entry at
+// once (a broadcast).
+template <int NQ, int NI>
+__device__ __forceinline__ void diag_line(const double *Tt, const double *yv, double *out)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s += Tt[q * NI + i] * yv[q];
+        out[i] = s;
+    }
+}
 
 template <int P, int NQ, bool LIM>
 __device__ __forceinline__ void diag_contract3(const Tables &tb, const Geom &g, int e0,
@@ -909,50 +924,55 @@ __device__ __forceinline__ void diag_contract3(const Tables &tb, const Geom &g, 
         L.T[2][k] = gg * gg;
     }
     for (int k = threadIdx.x; k < nel * 3 * NP; k += BLOCK) L.sD[k] = 0.0;
+    // one pass per pair as three pencil sweeps: a lane loads one 1D line from
+    // LDS and produces the n_i outputs of that line
     for (int pr = 0; pr < NPR; ++pr) {
         const int n = diag_pn(pr), p = diag_pp(pr);
-        // table index along axis k: number of derivative factors on that axis
+        // number of derivative factors on each axis
         const bool val = pr == 6;
         const int t1 = val ? 0 : (n == 0) + (p == 0), t2 = val ? 0 : (n == 1) + (p == 1),
                   t3 = val ? 0 : (n == 2) + (p == 2);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nel * 3 * NI * NQ * NQ; idx += BLOCK) {
-            const int q1 = idx % NQ;
-            int r = idx / NQ;
-            const int q2 = r % NQ;
-            r /= NQ;
-            const int i3 = r % NI;
-            r /= NI;  // el*3 + a
+        // sQ and sD ready; later pairs need no barrier here (their axis-3 pass
+        // writes U2 only, which the previous pair's axis-1 pass does not read)
+        if (pr == 0) __syncthreads();
+        // axis 3: pencils (r = el*3 + a, q2, q1) -> U2[r][i3][q2][q1]
+        for (int pen = threadIdx.x; pen < nel * 3 * NQ * NQ; pen += BLOCK) {
+            const int q21 = pen % (NQ * NQ), r = pen / (NQ * NQ);
             const int el = r / 3, a = r % 3;
-            const double *y = L.sQ + ((el * NPR + pr) * 3 + a) * NQ3 + q2 * NQ + q1;
-            double s = 0.0;
+            const double *y = L.sQ + ((el * NPR + pr) * 3 + a) * NQ3 + q21;
+            double yv[NQ];
 #pragma unroll
-            for (int q3 = 0; q3 < NQ; ++q3) s += L.T[t3][q3 * NI + i3] * y[q3 * NQ * NQ];
-            L.U2[((r * NI + i3) * NQ + q2) * NQ + q1] = s;
+            for (int q = 0; q < NQ; ++q) yv[q] = y[q * NQ * NQ];
+            double o[NI];
+            diag_line<NQ, NI>(L.T[t3], yv, o);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) L.U2[(r * NI + i) * NQ * NQ + q21] = o[i];
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < nel * 3 * NI * NI * NQ; idx += BLOCK) {
-            const int q1 = idx % NQ;
-            int r = idx / NQ;
-            const int i2 = r % NI;
-            r /= NI;
-            const int i3 = r % NI;
-            r /= NI;
-            const double *y = L.U2 + (r * NI + i3) * NQ * NQ + q1;
-            double s = 0.0;
+        // axis 2: pencils (r, i3, q1) -> U1[r][i3][i2][q1]
+        for (int pen = threadIdx.x; pen < nel * 3 * NI * NQ; pen += BLOCK) {
+            const int q1 = pen % NQ, ri3 = pen / NQ;
+            const double *y = L.U2 + ri3 * NQ * NQ + q1;
+            double yv[NQ];
 #pragma unroll
-            for (int q2 = 0; q2 < NQ; ++q2) s += L.T[t2][q2 * NI + i2] * y[q2 * NQ];
-            L.U1[((r * NI + i3) * NI + i2) * NQ + q1] = s;
+            for (int q = 0; q < NQ; ++q) yv[q] = y[q * NQ];
+            double o[NI];
+            diag_line<NQ, NI>(L.T[t2], yv, o);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) L.U1[(ri3 * NI + i) * NQ + q1] = o[i];
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < nel * 3 * NP; idx += BLOCK) {
-            const int i1 = idx % NI;
-            const int rest = idx / NI;  // (r*NI + i3)*NI + i2
-            const double *y = L.U1 + rest * NQ;
-            double s = 0.0;
+        // axis 1: pencils (r, i3, i2) -> the n_i diagonal entries of the line,
+        // each written by one lane
+        for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
+            const double *y = L.U1 + pen * NQ;
+            double yv[NQ];
 #pragma unroll
-            for (int q1 = 0; q1 < NQ; ++q1) s += L.T[t1][q1 * NI + i1] * y[q1];
-            L.sD[idx] += s;
+            for (int q = 0; q < NQ; ++q) yv[q] = y[q];
+            double o[NI];
+            diag_line<NQ, NI>(L.T[t1], yv, o);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) L.sD[pen * NI + i] += o[i];
         }
     }
     __syncthreads();
