@@ -34,15 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "57b0ec15ecd44eeafbfb8dd36044913884e487555f742139c0f4f351307acbdd"
+_SHA_C2 = "d24b233e95081f3463f1633bd688684ead9fba58b1f7237e27755ec7efadf67d"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 720996486, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 720784820, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 369888148, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 366328946, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 246715269, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 246732705, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135280078, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135287919, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
