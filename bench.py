@@ -359,41 +359,48 @@ def serve_sweep(rates, nreq):
     return out
 
 
-# Sec. 4.1, Table tab_kershaw_baseline: GPU PA* (Jacobi) on 4 V100s, for context
-KERSHAW_PAPER = {1: (0.4, 11, 203), 2: (0.9, 18, 507), 3: (3.9, 41, 1536), 4: (8.5, 70, 3110)}
+# Sec. 4.1, Table tab_kershaw_baseline: GPU runs on 4 V100s with (PA*) and without
+# (PA) the Jacobi preconditioner, for context: (seconds, Newton its, MINRES its)
+KERSHAW_PAPER = {
+    True: {1: (0.4, 11, 203), 2: (0.9, 18, 507), 3: (3.9, 41, 1536), 4: (8.5, 70, 3110)},
+    False: {1: (0.5, 19, 284), 2: (1.7, 29, 1107), 3: (4.7, 44, 2060), 4: (7.8, 67, 3139)},
+}
 
 
 def kershaw_leg(orders, storage="compact"):
     """Kershaw benchmark (Sec. 4.1): 24^3 hexes, eps_y = eps_z = 0.3, 9^3 points per
-    element, mu_303, at most 50 Jacobi-MINRES iterations per Newton step, stop at
-    |g|/|g0| <= 1e-10; boundary nodes slide along their faces.  Time to solution on one
-    GPU, FP64, next to the paper's 4-V100 numbers (context, not a like-for-like target)."""
+    element, mu_303, at most 50 MINRES iterations per Newton step, with the Jacobi
+    preconditioner ("PA*") and without ("PA"), stop at |g|/|g0| <= 1e-10; boundary nodes
+    slide along their faces.  Time to solution on one GPU, FP64, next to the paper's
+    4-V100 numbers (context, not a like-for-like target)."""
     import torch
     from paper_2205_12721_amd import inputs
     from paper_2205_12721_amd.tmop import Context, basis_nodes
     ns = (24, 24, 24)
-    res = {}
-    for p in orders:
-        mask = torch.as_tensor(inputs.sliding_mask(ns, p)).cuda()
-        ctx = Context(3, ns, p, 9, ess=mask, storage=storage)
-        x0 = torch.as_tensor(inputs.kershaw_nodes(ns, p, basis_nodes(p), 0.3, 0.3)).cuda()
-        x = x0.clone()
-        ctx.solve(x, rel_grad_tol=1e-10, max_newton=1, max_minres=2)  # warm-up (JIT of modules)
-        x.copy_(x0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rep = ctx.solve(x, rel_grad_tol=1e-10, max_newton=300, max_minres=50)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ctx.close()
-        pt, pn, pm = KERSHAW_PAPER.get(p, (None, None, None))
-        res["p%d" % p] = {
-            "dofs": 3 * (24 * p + 1) ** 3, "seconds": round(dt, 3), "status": rep["status_name"],
-            "newton_its": rep["newton_its"], "minres_its": rep["minres_its_total"],
-            "F0": rep["F0"], "F": rep["F"], "g_rel": rep["g_norm"] / rep["g0_norm"],
-            "paper_4xV100_seconds": pt, "paper_newton_its": pn, "paper_minres_its": pm,
-        }
-    res["storage"] = storage
+    res = {"storage": storage}
+    for jac, key in ((True, "PA*"), (False, "PA")):
+        res[key] = {}
+        for p in orders:
+            mask = torch.as_tensor(inputs.sliding_mask(ns, p)).cuda()
+            ctx = Context(3, ns, p, 9, ess=mask, storage=storage)
+            x0 = torch.as_tensor(inputs.kershaw_nodes(ns, p, basis_nodes(p), 0.3, 0.3)).cuda()
+            x = x0.clone()
+            ctx.solve(x, rel_grad_tol=1e-10, max_newton=1, max_minres=2)  # warm-up
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = ctx.solve(x, rel_grad_tol=1e-10, max_newton=300, max_minres=50, jacobi=jac)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ctx.close()
+            pt, pn, pm = KERSHAW_PAPER[jac].get(p, (None, None, None))
+            res[key]["p%d" % p] = {
+                "dofs": 3 * (24 * p + 1) ** 3, "seconds": round(dt, 3),
+                "status": rep["status_name"], "newton_its": rep["newton_its"],
+                "minres_its": rep["minres_its_total"], "F0": rep["F0"], "F": rep["F"],
+                "g_rel": rep["g_norm"] / rep["g0_norm"],
+                "paper_4xV100_seconds": pt, "paper_newton_its": pn, "paper_minres_its": pm,
+            }
     return res
 
 
