@@ -45,19 +45,20 @@ def test_kershaw_operators(p, storage):
     ctx.close()
 
 
+@pytest.mark.parametrize("jacobi", [True, False])
 @pytest.mark.parametrize("p", [1, 2])
-def test_kershaw_solve_reaches_uniform_grid(p):
+def test_kershaw_solve_reaches_uniform_grid(p, jacobi):
     import torch
     from paper_2205_12721_amd.tmop import Context
     pb, x, mask = _problem(p)
-    xo, ro = oracle.newton_solve(pb, x, rel_grad_tol=1e-10, max_newton=200)
+    xo, ro = oracle.newton_solve(pb, x, rel_grad_tol=1e-10, max_newton=200, jacobi=jacobi)
     ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda())
     xd = to_dev(x)
-    rg = ctx.solve(xd, rel_grad_tol=1e-10, max_newton=200)
+    rg = ctx.solve(xd, rel_grad_tol=1e-10, max_newton=200, jacobi=jacobi)
     ctx.close()
     xu = inputs.uniform_nodes(NS, p, basis.gll_nodes(p))
-    log("kershaw p=%d oracle its %d F %.3e | gpu its %d F %.3e" % (p, ro["newton_its"], ro["F"],
-                                                                   rg["newton_its"], rg["F"]))
+    log("kershaw p=%d jacobi %d oracle its %d F %.3e | gpu its %d F %.3e"
+        % (p, jacobi, ro["newton_its"], ro["F"], rg["newton_its"], rg["F"]))
     assert rg["status"] == 0 and ro["status"] == 0
     assert rel(to_host(xd), xo) <= TOLX
     assert np.abs(to_host(xd) - xu).max() < 1e-6

@@ -108,22 +108,25 @@ def test_solve_error_codes():
     ctx.close()
 
 
+@pytest.mark.parametrize("jacobi", [True, False])
 @pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq,its", [(3, (3, 3, 3), 2, 4, 12), (2, (5, 4), 3, 5, 12),
                                               (3, (2, 2, 2), 1, 3, 50)])
-def test_minres_matches_oracle(dim, ns, p, nq, its, storage):
-    """Device MINRES (fused kernels, double-buffered state) vs the oracle's MINRES on the
-    same operator; the last case converges in fewer than max_its iterations, so the
-    early-exit path of the device kernels is exercised."""
+def test_minres_matches_oracle(dim, ns, p, nq, its, storage, jacobi):
+    """Device MINRES (fused kernels, double-buffered state, the solution update deferred
+    to the next iteration) vs the oracle's MINRES on the same operator, with and without
+    the Jacobi preconditioner; the last case converges in fewer than max_its iterations,
+    so the early-exit path of the device kernels is exercised."""
     from oracle import solver
     from paper_2205_12721_amd.tmop import Context
     pb, x = make_case(dim, ns, p, nq, seed=61)
     g = pb.gradient(x)
     minv = solver.jacobi_inverse(pb.diag(x), pb.ess)
-    xo, ito, _ = solver.minres(lambda v: pb.hvp(x, v), g, lambda r: minv * r, rtol=1e-12, maxit=its)
+    pre = (lambda r: minv * r) if jacobi else None
+    xo, ito, _ = solver.minres(lambda v: pb.hvp(x, v), g, pre, rtol=1e-12, maxit=its)
     ctx = Context(dim, ns, p, nq, storage=storage)
     ctx.hessian_setup(to_dev(x))
-    dx, itg = ctx.minres(to_dev(g), max_its=its, rtol=1e-12, jacobi=True)
+    dx, itg = ctx.minres(to_dev(g), max_its=its, rtol=1e-12, jacobi=jacobi)
     log("minres", dim, ns, p, nq, storage, "its oracle", ito, "gpu", itg, "rel", rel(to_host(dx), xo))
     assert itg == ito
     assert rel(to_host(dx), xo) <= 1e-9
