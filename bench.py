@@ -371,18 +371,19 @@ def kershaw_leg(orders, storage="compact"):
     """Kershaw benchmark (Sec. 4.1): 24^3 hexes, eps_y = eps_z = 0.3, 9^3 points per
     element, mu_303, at most 50 MINRES iterations per Newton step, with the Jacobi
     preconditioner ("PA*") and without ("PA"), stop at |g|/|g0| <= 1e-10; boundary nodes
-    slide along their faces.  Time to solution on one GPU, FP64, next to the paper's
-    4-V100 numbers (context, not a like-for-like target)."""
+    slide along their faces.  Gauss-Legendre points, and for the unpreconditioned solve
+    also the 9-point Gauss-Lobatto rule ("PA_gll").  Time to solution on one GPU, FP64,
+    next to the paper's 4-V100 numbers (context, not a like-for-like target)."""
     import torch
     from paper_2205_12721_amd import inputs
     from paper_2205_12721_amd.tmop import Context, basis_nodes
     ns = (24, 24, 24)
     res = {"storage": storage}
-    for jac, key in ((True, "PA*"), (False, "PA")):
+    for jac, key, quad in ((True, "PA*", "gl"), (False, "PA", "gl"), (False, "PA_gll", "gll")):
         res[key] = {}
         for p in orders:
             mask = torch.as_tensor(inputs.sliding_mask(ns, p)).cuda()
-            ctx = Context(3, ns, p, 9, ess=mask, storage=storage)
+            ctx = Context(3, ns, p, 9, ess=mask, storage=storage, quad=quad)
             x0 = torch.as_tensor(inputs.kershaw_nodes(ns, p, basis_nodes(p), 0.3, 0.3)).cuda()
             x = x0.clone()
             ctx.solve(x, rel_grad_tol=1e-10, max_newton=1, max_minres=2)  # warm-up

@@ -73,6 +73,7 @@ typedef enum {
 enum { TMOP_FP64 = 0, TMOP_MIXED = 1 };       /* tmop_params.precision */
 enum { TMOP_ESS_BOUNDARY = 0, TMOP_ESS_NONE = 1, TMOP_ESS_MASK = 2 };
 enum { TMOP_HESS_TENSOR = 0, TMOP_HESS_COMPACT = 1 };  /* tmop_params.hess_storage */
+enum { TMOP_QUAD_GL = 0, TMOP_QUAD_GLL = 1 };          /* tmop_params.quad_rule */
 
 typedef struct tmop_ctx tmop_ctx;
 
@@ -109,6 +110,12 @@ typedef struct {
                        the metric's second derivative (13 / 8 entries), the
                        tensor applied in closed form in the action.  Same
                        results; the compact form moves 3.5x fewer bytes. */
+    int quad_rule;  /* 1D rule of the tensor quadrature (Sec. 3.1 builds the
+                       element rule from a 1D rule without naming it):
+                       TMOP_QUAD_GL (0, default) Gauss-Legendre, or
+                       TMOP_QUAD_GLL (1) Gauss-Lobatto-Legendre (nq1d >= 2;
+                       includes the element's faces, so the det test also
+                       covers its vertices).  Pooled solves take GL only. */
 } tmop_params;
 
 typedef struct {

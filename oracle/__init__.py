@@ -118,16 +118,17 @@ class Problem:
     ``ess``   bool/uint8 mask of length dim*nx (True = fixed DoF) or None
     """
 
-    def __init__(self, dim, p, nq1d, e2n, nx, metric_id=None, W=None, ess=None):
+    def __init__(self, dim, p, nq1d, e2n, nx, metric_id=None, W=None, ess=None, quad="gl"):
         self.dim = dim
         self.p = p
         self.nq1d = nq1d
+        self.quad = quad
         self.metric = metric_id if metric_id is not None else (2 if dim == 2 else 303)
         self.e2n = np.ascontiguousarray(e2n, dtype=np.int32)
         self.ne, self.npe = self.e2n.shape
         self.nx = int(nx)
         self.ndof = dim * self.nx
-        self.wq, dphi, phi = _dense_tables(dim, p, nq1d)
+        self.wq, dphi, phi = _dense_tables(dim, p, nq1d, quad)
         self.dphi = np.ascontiguousarray(dphi)
         self.phi = np.ascontiguousarray(phi)
         self.nqe = len(self.wq)
@@ -173,7 +174,7 @@ class Problem:
         self._pb.lim_delta = float(delta)
 
     @classmethod
-    def box(cls, dim, n, p, nq1d, metric_id=None, W=None, constrain="boundary"):
+    def box(cls, dim, n, p, nq1d, metric_id=None, W=None, constrain="boundary", quad="gl"):
         """Structured box [0,1]^dim with n (int or tuple) elements per side."""
         ns = (n,) * dim if np.isscalar(n) else tuple(n)
         e2n, nx = mesh.box_topology(dim, ns, p)
@@ -182,7 +183,7 @@ class Problem:
             ess = mesh.box_boundary_mask(dim, ns, p)
         elif constrain not in (None, "none"):
             raise ValueError(constrain)
-        pb = cls(dim, p, nq1d, e2n, nx, metric_id=metric_id, W=W, ess=ess)
+        pb = cls(dim, p, nq1d, e2n, nx, metric_id=metric_id, W=W, ess=ess, quad=quad)
         pb.shape = ns
         return pb
 
@@ -275,9 +276,9 @@ class Problem:
 
 
 @functools.lru_cache(maxsize=32)
-def _dense_tables(dim, p, nq1d):
-    wq, dphi = basis.dense_tables(dim, p, nq1d)
-    phi = basis.dense_values(dim, p, nq1d)
+def _dense_tables(dim, p, nq1d, quad="gl"):
+    wq, dphi = basis.dense_tables(dim, p, nq1d, quad)
+    phi = basis.dense_values(dim, p, nq1d, quad)
     for a in (wq, dphi, phi):
         a.setflags(write=False)
     return wq, dphi, phi
@@ -296,7 +297,7 @@ def restrict_to_nodes(pb, nodes):
     nodes = np.asarray(nodes)
     keep = np.isin(pb.e2n, nodes).any(axis=1)
     sub = Problem(pb.dim, pb.p, pb.nq1d, pb.e2n[keep], pb.nx, metric_id=pb.metric, W=pb.W,
-                  ess=pb.ess)
+                  ess=pb.ess, quad=pb.quad)
     if pb.lim_x0 is not None:
         sub.set_limiting(pb.lim_x0, pb._pb.lim_coef, pb._pb.lim_delta)
     return sub

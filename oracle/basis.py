@@ -8,6 +8,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   which coincide with equispaced points for p <= 2).
 * ``gl_rule``     -- the n_q-point Gauss-Legendre rule mapped to [0,1]
   (Sec. 3.1, tensor-product quadrature built from a 1D rule).
+* ``gll_rule``    -- the n_q-point Gauss-Lobatto-Legendre rule on [0,1]
+  (the other 1D rule the library offers; the paper does not name its rule).
 * ``lagrange``    -- l_j(x) and l_j'(x) from the product formula.
 * ``tables_1d``   -- B_qi = l_i(chi_q), G_qi = l_i'(chi_q)  (Sec. 3.1, eq. eq_B_G_1D).
 * ``dense_tables``-- d wbar_i / d xbar_b at every tensor quadrature point as an
@@ -48,6 +50,27 @@ def gl_rule(nq):
     return 0.5 * (t + 1.0), 0.5 * w
 
 
+def gll_rule(nq):
+    """n_q-point Gauss-Lobatto-Legendre rule on [0,1] (n_q >= 2): the end points and
+    the roots of P_{n-1}', weights 2 / (n (n-1) P_{n-1}(t)^2) on [-1,1], halved."""
+    if nq < 2:
+        raise ValueError("a Gauss-Lobatto rule needs at least 2 points")
+    x = gll_nodes(nq - 1)
+    c = np.zeros(nq)
+    c[nq - 1] = 1.0
+    P = npleg.legval(2.0 * x - 1.0, c)
+    return x, 1.0 / (nq * (nq - 1.0) * P * P)
+
+
+def quad_rule(nq, rule="gl"):
+    """The 1D rule by name: "gl" (Gauss-Legendre) or "gll" (Gauss-Lobatto-Legendre)."""
+    if rule == "gl":
+        return gl_rule(nq)
+    if rule == "gll":
+        return gll_rule(nq)
+    raise ValueError("unknown quadrature rule %r" % (rule,))
+
+
 def lagrange(nodes, pts):
     """Values and derivatives of the Lagrange polynomials on ``nodes`` at ``pts``.
 
@@ -77,20 +100,20 @@ def lagrange(nodes, pts):
     return L, dL
 
 
-def tables_1d(p, nq):
-    """B (nq x (p+1)) and G (nq x (p+1)) at the Gauss-Legendre points."""
-    chi, _ = gl_rule(nq)
+def tables_1d(p, nq, rule="gl"):
+    """B (nq x (p+1)) and G (nq x (p+1)) at the points of the 1D rule."""
+    chi, _ = quad_rule(nq, rule)
     return lagrange(gll_nodes(p), chi)
 
 
-def dense_tables(dim, p, nq):
+def dense_tables(dim, p, nq, rule="gl"):
     """Weights w_q (N_q) and dphi[b, q, i] = d wbar_i/d xbar_b (dim x N_q x N_p).
 
     Quadrature points q = q1 + nq*q2 (+ nq^2*q3), nodes i = i1 + ni*i2 (+ ni^2*i3),
     both lexicographic with the first axis fastest.
     """
     ni = p + 1
-    chi, w1 = gl_rule(nq)
+    chi, w1 = quad_rule(nq, rule)
     B, G = lagrange(gll_nodes(p), chi)
     NQ = nq ** dim
     NP = ni ** dim
@@ -109,10 +132,10 @@ def dense_tables(dim, p, nq):
     return wq, dphi
 
 
-def dense_values(dim, p, nq):
+def dense_values(dim, p, nq, rule="gl"):
     """phi[q, i] = wbar_i(xbar_q) (N_q x N_p), same orderings as dense_tables."""
     ni = p + 1
-    chi, _ = gl_rule(nq)
+    chi, _ = quad_rule(nq, rule)
     B, _ = lagrange(gll_nodes(p), chi)
     NQ = nq ** dim
     NP = ni ** dim

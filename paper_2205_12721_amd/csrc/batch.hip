@@ -586,6 +586,10 @@ static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH 
     s.dim = d;
     s.p = p;
     s.nq = prm->nq1d;
+    if (prm->quad_rule != TMOP_QUAD_GL) {
+        why = "pooled solves use Gauss-Legendre quadrature (quad_rule = TMOP_QUAD_GL)";
+        return TMOP_ERR_UNSUPPORTED;
+    }
     s.storage = prm->hess_storage == TMOP_HESS_COMPACT ? 1 : 0;
     s.prec = prm->precision == TMOP_MIXED ? 1 : 0;
     const long ne = (long)m->nx * m->ny * (d == 3 ? m->nz : 1);

@@ -87,6 +87,19 @@ void gauss_legendre01(int n, double *x, double *w)
     }
 }
 
+// n-point Gauss-Lobatto-Legendre rule on [0,1]: the GLL nodes of order n-1
+// and weights 2 / (n (n-1) P_{n-1}(t)^2) on [-1,1], halved.
+void gll_nodes01(int p, double *x);
+void gauss_lobatto01(int n, double *x, double *w)
+{
+    gll_nodes01(n - 1, x);
+    for (int k = 0; k < n; ++k) {
+        double P, dP;
+        legendre(n - 1, 2.0 * x[k] - 1.0, P, dP);
+        w[k] = 1.0 / (n * (n - 1.0) * P * P);
+    }
+}
+
 void gll_nodes01(int p, double *x)
 {
     x[0] = 0.0;
@@ -152,12 +165,16 @@ namespace tmop {
 int tuned_tile(int dim, int p, int nq, int storage, int precision);
 void record_tile(int dim, int p, int nq, int storage, int precision, int t);
 
-int internal_tables(int p, int nq, Tables *tb)
+int internal_tables(int p, int nq, Tables *tb, int rule)
 {
     if (p < 1 || p >= MAXNI || nq < 1 || nq > MAXNQ) return TMOP_ERR_INVALID_ARG;
+    if (rule != TMOP_QUAD_GL && !(rule == TMOP_QUAD_GLL && nq >= 2)) return TMOP_ERR_INVALID_ARG;
     double xi[MAXNI], chi[MAXNQ], w[MAXNQ];
     gll_nodes01(p, xi);
-    gauss_legendre01(nq, chi, w);
+    if (rule == TMOP_QUAD_GLL)
+        gauss_lobatto01(nq, chi, w);
+    else
+        gauss_legendre01(nq, chi, w);
     std::memset(tb, 0, sizeof(*tb));
     lagrange_tables(p, nq, xi, chi, tb->B, tb->G);
     for (int q = 0; q < nq; ++q) tb->w[q] = w[q];
@@ -389,7 +406,10 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     g.ess_mode = m->ess_mode;
     g.ess = m->ess_mask;
 
-    internal_tables(p, nq, &c->tb);
+    if (internal_tables(p, nq, &c->tb, prm->quad_rule) != TMOP_OK) {
+        delete c;
+        return fail(TMOP_ERR_INVALID_ARG, "quad_rule must be TMOP_QUAD_GL or TMOP_QUAD_GLL");
+    }
     if (internal_target(prm, d, &c->tg) != TMOP_OK) {
         delete c;
         return fail(TMOP_ERR_INVALID_ARG, "target W must have det > 0");

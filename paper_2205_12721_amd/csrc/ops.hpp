@@ -92,7 +92,7 @@ inline void fill_tiles_kb2(BOps &o)
 
 // Host-side 1D tables (GLL basis at Gauss-Legendre points) and constant
 // target of a (p, n_q) / params pair; defined in capi.hip.
-int internal_tables(int p, int nq, Tables *tb);
+int internal_tables(int p, int nq, Tables *tb, int rule = 0);
 int internal_target(const tmop_params *prm, int dim, Target *tg);
 
 // Tile shapes of the Hessian action chosen by the autotuner, per class

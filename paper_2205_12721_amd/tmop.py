@@ -42,7 +42,10 @@ class MeshDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int), ("nq1d", ctypes.c_int), ("has_W", ctypes.c_int),
                 ("W", ctypes.c_double * 9), ("precision", ctypes.c_int),
-                ("hess_storage", ctypes.c_int)]
+                ("hess_storage", ctypes.c_int), ("quad_rule", ctypes.c_int)]
+
+
+QUAD_RULES = {"gl": 0, "gll": 1}   # TMOP_QUAD_GL, TMOP_QUAD_GLL
 
 
 class SolveParams(ctypes.Structure):
@@ -175,7 +178,7 @@ class Context:
 
     def __init__(self, dim, n=None, p=1, nq1d=None, metric=None, precision="fp64", W=None,
                  ess="boundary", elem_to_node=None, num_nodes=None, stream=None,
-                 storage="tensor"):
+                 storage="tensor", quad="gl"):
         import torch
         self._torch = torch
         self.dim, self.p = dim, p
@@ -214,6 +217,7 @@ class Context:
                 prm.W[k] = v
         prm.precision = {"fp64": TMOP_FP64, "mixed": TMOP_MIXED}[precision]
         prm.hess_storage = {"tensor": HESS_TENSOR, "compact": HESS_COMPACT}[storage]
+        prm.quad_rule = QUAD_RULES[quad]
         self.storage = storage
         self._md, self._prm = md, prm
         s = stream if stream is not None else torch.cuda.current_stream()

@@ -44,8 +44,9 @@ def test_binding_struct_layouts():
     assert tmop.MeshDesc.elem_to_node.offset == 32
     assert tmop.MeshDesc.ess_mask.offset == 48
     assert tmop.Params.W.offset == 16
-    assert ctypes.sizeof(tmop.Params) == 16 + 72 + 8
+    assert ctypes.sizeof(tmop.Params) == 16 + 72 + 16
     assert tmop.Params.hess_storage.offset == 92
+    assert tmop.Params.quad_rule.offset == 96
     assert ctypes.sizeof(tmop.SolveParams) == 40
     assert ctypes.sizeof(tmop.SolveReport) == 16 + 10 * 8 + 8
 
@@ -76,3 +77,16 @@ def test_basis_nodes_match_oracle():
     from paper_2205_12721_amd.tmop import basis_nodes
     for p in range(1, 5):
         assert np.allclose(basis_nodes(p), basis.gll_nodes(p), atol=1e-15, rtol=0)
+
+
+def test_pool_rejects_gauss_lobatto_on_host():
+    """Pooled solves take the Gauss-Legendre rule only (host-side request check)."""
+    from paper_2205_12721_amd import tmop
+    lib = tmop.lib()
+    md = tmop.MeshDesc(dim=3, order_p=2, nx=4, ny=4, nz=4)
+    prm = tmop.Params(metric=303, nq1d=4, quad_rule=1)
+    b = ctypes.c_size_t()
+    assert lib.tmop_pool_request_bytes(ctypes.byref(md), ctypes.byref(prm), ctypes.byref(b)) != 0
+    assert "Gauss-Legendre" in lib.tmop_pool_last_error().decode()
+    prm.quad_rule = 0
+    assert lib.tmop_pool_request_bytes(ctypes.byref(md), ctypes.byref(prm), ctypes.byref(b)) == 0

@@ -19,23 +19,24 @@ pytestmark = pytest.mark.gpu
 NS = (6, 2, 2)
 
 
-def _problem(p):
+def _problem(p, quad="gl"):
     mask = inputs.sliding_mask(NS, p)
     e2n, nx = oracle.mesh.box_topology(3, NS, p)
-    pb = oracle.Problem(3, p, 9, e2n, nx, ess=mask.astype(bool))
+    pb = oracle.Problem(3, p, 9, e2n, nx, ess=mask.astype(bool), quad=quad)
     x = inputs.kershaw_nodes(NS, p, basis.gll_nodes(p), 0.3, 0.3)
     assert pb.min_det(x) > 0
     return pb, x, mask
 
 
+@pytest.mark.parametrize("quad", ["gl", "gll"])
 @pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("p", [1, 2, 3])
-def test_kershaw_operators(p, storage):
+def test_kershaw_operators(p, storage, quad):
     import torch
     from paper_2205_12721_amd.tmop import Context
-    pb, x, mask = _problem(p)
+    pb, x, mask = _problem(p, quad)
     v = inputs.gaussian_vector(pb.ndof, 5, pb.ess)
-    ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda(), storage=storage)
+    ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda(), storage=storage, quad=quad)
     xd = to_dev(x)
     assert abs(ctx.energy(xd) - pb.energy(x)) <= TOL64 * pb.energy(x)
     assert rel(to_host(ctx.gradient(xd)), pb.gradient(x)) <= TOL64
@@ -63,3 +64,35 @@ def test_kershaw_solve_reaches_uniform_grid(p, jacobi):
     assert rel(to_host(xd), xo) <= TOLX
     assert np.abs(to_host(xd) - xu).max() < 1e-6
     assert abs(rg["F"] - pb.energy(xu)) <= 1e-10 * rg["F0"]
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_kershaw_gauss_lobatto_solve(p):
+    """The unpreconditioned solve with the 9-point Gauss-Lobatto rule (the det test
+    then covers the element vertices) reaches the uniform grid, as the oracle's does."""
+    import torch
+    from paper_2205_12721_amd.tmop import Context
+    pb, x, mask = _problem(p, "gll")
+    xo, ro = oracle.newton_solve(pb, x, rel_grad_tol=1e-10, max_newton=200, jacobi=False)
+    ctx = Context(3, NS, p, 9, ess=torch.as_tensor(mask).cuda(), quad="gll")
+    xd = to_dev(x)
+    rg = ctx.solve(xd, rel_grad_tol=1e-10, max_newton=200, jacobi=False)
+    ctx.close()
+    xu = inputs.uniform_nodes(NS, p, basis.gll_nodes(p))
+    log("kershaw gll p=%d oracle its %d | gpu its %d" % (p, ro["newton_its"], rg["newton_its"]))
+    assert rg["status"] == 0 and ro["status"] == 0
+    assert rel(to_host(xd), xo) <= TOLX
+    assert np.abs(to_host(xd) - xu).max() < 1e-6
+
+
+def test_quad_rule_argument_checked():
+    import torch
+    from paper_2205_12721_amd import tmop
+    from paper_2205_12721_amd.tmop import Context, TmopError
+    tmop.QUAD_RULES["bogus"] = 7
+    try:
+        with pytest.raises(TmopError):
+            Context(3, NS, 1, 3, quad="bogus")
+    finally:
+        del tmop.QUAD_RULES["bogus"]
+    torch.cuda.synchronize()

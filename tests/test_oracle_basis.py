@@ -124,3 +124,39 @@ def test_boundary_mask():
     one = m[:9]
     assert one.sum() == 8 and not one[4]
     assert np.array_equal(m[9:], one)
+
+
+# Gauss-Lobatto-Legendre rule on [0,1]: textbook closed forms for n = 2, 3, 4
+# (trapezoid, Simpson, and the four-point Lobatto rule with interior nodes at
+# (1 -+ 1/sqrt(5))/2 and weights 1/12, 5/12), end points included, exact for
+# polynomials of degree <= 2n-3 and not for x^(2n-2).
+def test_gauss_lobatto_closed_forms():
+    x, w = basis.gll_rule(2)
+    assert np.allclose(x, [0.0, 1.0], atol=1e-16) and np.allclose(w, [0.5, 0.5], atol=1e-16)
+    x, w = basis.gll_rule(3)
+    assert np.allclose(x, [0.0, 0.5, 1.0], atol=1e-16)
+    assert np.allclose(w, [1 / 6, 2 / 3, 1 / 6], atol=1e-15)
+    x, w = basis.gll_rule(4)
+    r = 1.0 / np.sqrt(5.0)
+    assert np.allclose(x, [0.0, (1 - r) / 2, (1 + r) / 2, 1.0], atol=1e-15)
+    assert np.allclose(w, [1 / 12, 5 / 12, 5 / 12, 1 / 12], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 9, 10])
+def test_gauss_lobatto_exactness(n):
+    x, w = basis.gll_rule(n)
+    assert x[0] == 0.0 and x[-1] == 1.0
+    assert abs(w.sum() - 1.0) < 1e-14 and (w > 0).all()
+    for k in range(2 * n - 2):
+        assert abs((w * x ** k).sum() - 1.0 / (k + 1)) < 1e-13
+    k = 2 * n - 2
+    assert abs((w * x ** k).sum() - 1.0 / (k + 1)) > 1e-12
+
+
+def test_quad_rule_names():
+    assert np.array_equal(basis.quad_rule(5, "gl")[0], basis.gl_rule(5)[0])
+    assert np.array_equal(basis.quad_rule(5, "gll")[1], basis.gll_rule(5)[1])
+    with pytest.raises(ValueError):
+        basis.quad_rule(5, "uniform")
+    with pytest.raises(ValueError):
+        basis.gll_rule(1)
