@@ -34,7 +34,7 @@ namespace tmop {
 
 // vector ids inside SlotDev::vec
 enum {
-    BX, BXT, BG, BGT, BDX, BR1, BR2, BHV, BV, BW, BW1, BW2, BMINV, BDIAG, BY, BNV
+    BX, BXT, BG, BGT, BDX, BR1, BR2, BZ1, BZ0, BW, BW1, BW2, BMINV, BDIAG, BY, BNV
 };
 static_assert(BNV <= NVEC, "too many vectors per slot");
 
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
     const double b1 = sqrt(fmax(bb, 0.0));
     const double *y = S.vec[BY];
     // z_{-1} = M^{-1} b, unscaled (the first Lanczos vector is z_{-1} / beta1)
-    double *v = S.vec[BV], *x = S.vec[BDX], *w = S.vec[BW], *w1 = S.vec[BW1], *w2 = S.vec[BW2];
+    double *v = S.vec[BZ0], *x = S.vec[BDX], *w = S.vec[BW], *w1 = S.vec[BW1], *w2 = S.vec[BW2];
     for (int i = i0; i < i1; i += VB) {
         v[i] = y[i];
         x[i] = 0.0;
@@ -887,8 +887,8 @@ static int read_sc(tmop_pool *P)
 static const int MR_W[3][3] = {{BW, BW1, BW2}, {BW1, BW2, BW}, {BW2, BW, BW1}};
 static int mr_r1(int k) { return (k & 1) ? BR2 : BR1; }
 static int mr_r2(int k) { return (k & 1) ? BR1 : BR2; }
-static int mr_zc(int k) { return (k & 1) ? BHV : BV; }
-static int mr_zp(int k) { return (k & 1) ? BV : BHV; }
+static int mr_zc(int k) { return (k & 1) ? BZ1 : BZ0; }
+static int mr_zp(int k) { return (k & 1) ? BZ0 : BZ1; }
 
 // one lockstep MINRES iteration for all running slots (see vec.hip for the
 // recurrences; here the update of iteration j - 1 runs in position j's gather)

@@ -176,23 +176,4 @@ __device__ inline void gather_node(const Geom &g, const int32_t *__restrict__ pt
     for (int c = 0; c < DIM; ++c) a[c] = fixed[c] ? 0.0 : (double)s[c];
 }
 
-// Assembled value of entry idx = c*nx + node; *fixed tells whether the DoF is
-// fixed (then the value is meaningless).
-template <int DIM, typename ET>
-__device__ inline double gather_entry(const Geom &g, const int32_t *__restrict__ ptr,
-                                      const int32_t *__restrict__ ent, const ET *__restrict__ eV,
-                                      int idx, bool *fixed)
-{
-    const int c = idx / g.nx;
-    const int node = idx - c * g.nx;
-    if (ptr) {
-        *fixed = is_fixed(g, c, node, -1, -1, -1);
-        return *fixed ? 0.0 : (double)gather_csr_node<DIM, ET>(g, ptr, ent, eV, c, node);
-    }
-    int gc[3];
-    box_coords<DIM>(g, node, gc);
-    *fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
-    return *fixed ? 0.0 : (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
-}
-
 }  // namespace tmop

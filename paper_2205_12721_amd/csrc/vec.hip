@@ -284,7 +284,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_init(long n, const double *__rest
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// beta1 from the partials; st[0] initial state; v = y / beta1; x = w = w1 = w2 = 0.
+// beta1 from the partials; st[0] and st[1] the initial state; x = w = w1 = w2 = 0;
+// v = y / beta1 when v is given (the solver here keeps y unscaled instead).
 __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, double rtol,
                                                      const double *__restrict__ part, int nb,
                                                      const double *__restrict__ y,
