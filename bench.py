@@ -261,7 +261,8 @@ def precision_leg(cfg, x0, v_host, y_oracle, max_newton=100):
             out["hvp_rel_err_vs_oracle"]["%s_%s" % (storage, prec)] = float(
                 np.linalg.norm(y - yo) / np.linalg.norm(yo))
     sol = {}
-    for storage, prec in (("tensor", "fp64"), ("compact", "fp64"), ("compact", "mixed")):
+    for storage, prec in (("tensor", "fp64"), ("tensor", "mixed"), ("compact", "fp64"),
+                          ("compact", "mixed")):
         c = Context(dim, n, p, nq, precision=prec, storage=storage)
         x = x0.clone()
         torch.cuda.synchronize()
