@@ -34,15 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "a62bc80f4a987480636e0c589c1ba24664a70d9d10c9c3e5c2cb3477e656b348"
+_SHA_C2 = "4118b74f1f33b6a6e837a57ce67638a671c6f7767a76799f684a00a0963f4c0d"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 721306302, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 721378345, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366061442, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 366506683, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 246733886, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 246737593, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135284420, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135307956, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
