@@ -146,8 +146,8 @@ __global__ __launch_bounds__(VB) void kv_step(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     const double a = sc[t.slot * NSC + SC_ALPHA];
-    const double *x = S.vec[BX], *dx = S.vec[BDX];
-    double *xt = S.vec[BXT];
+    const double *__restrict__ x = S.vec[BX], *__restrict__ dx = S.vec[BDX];
+    double *__restrict__ xt = S.vec[BXT];
     for (int i = i0; i < i1; i += VB) xt[i] = x[i] - a * dx[i];
 }
 
@@ -156,8 +156,8 @@ __global__ __launch_bounds__(VB) void kv_copy(const VTile *__restrict__ vt,
                                               const int *__restrict__ gate, int vs, int vd)
 {
     VT_PROLOGUE
-    const double *a = S.vec[vs];
-    double *b = S.vec[vd];
+    const double *__restrict__ a = S.vec[vs];
+    double *__restrict__ b = S.vec[vd];
     for (int i = i0; i < i1; i += VB) b[i] = a[i];
 }
 
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(VB) void kv_dot(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     __shared__ double red[VB / 64];
-    const double *a = S.vec[va], *b = S.vec[vb];
+    const double *__restrict__ a = S.vec[va], *__restrict__ b = S.vec[vb];
     double s = 0.0;
     for (int i = i0; i < i1; i += VB) s += a[i] * b[i];
     s = block_sum(s, red);
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(VB) void kv_absmax(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     __shared__ double red[VB / 64];
-    const double *a = S.vec[va];
+    const double *__restrict__ a = S.vec[va];
     double s = 0.0;
     for (int i = i0; i < i1; i += VB) s = fmax(s, fabs(a[i]));
     s = -block_min(-s, red);
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(VB) void kv_jacobi(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     const double floor = 1e-14 * sc[t.slot * NSC + SC_DMAX];
-    const double *d = S.vec[BDIAG];
-    double *m = S.vec[BMINV];
+    const double *__restrict__ d = S.vec[BDIAG];
+    double *__restrict__ m = S.vec[BMINV];
     for (int i = i0; i < i1; i += VB) {
         const double a = fmax(fabs(d[i]), floor);
         m[i] = a > 0.0 ? 1.0 / a : 1.0;
@@ -213,9 +213,9 @@ __global__ __launch_bounds__(VB) void kv_gather(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     const Geom &g = S.g;
-    const ET *eV = (const ET *)S.eV;
-    double *out = S.vec[vout];
-    const double *src = S.vec[vsrc];
+    const ET *__restrict__ eV = (const ET *)S.eV;
+    double *__restrict__ out = S.vec[vout];
+    const double *__restrict__ src = S.vec[vsrc];
     for (int i = i0; i < i1; i += VB) {
         const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
         const int node = i - c * g.nx;
@@ -244,8 +244,9 @@ __global__ __launch_bounds__(VB) void kv_mr_init(const VTile *__restrict__ vt,
     VT_PROLOGUE
     __shared__ double red[VB / 64];
     const bool useM = jac[t.slot] != 0;
-    const double *b = S.vec[BG], *m = S.vec[BMINV];
-    double *r1 = S.vec[BR1], *r2 = S.vec[BR2], *y = S.vec[BY];
+    const double *__restrict__ b = S.vec[BG], *__restrict__ m = S.vec[BMINV];
+    double *__restrict__ r1 = S.vec[BR1], *__restrict__ r2 = S.vec[BR2];
+    double *__restrict__ y = S.vec[BY];
     double s = 0.0;
     for (int i = i0; i < i1; i += VB) {
         const double bi = b[i];
@@ -273,9 +274,11 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
     const SlotRange r = rg[t.slot];
     const double bb = seg_sum(part, r.vbegin, r.vcount, red);
     const double b1 = sqrt(fmax(bb, 0.0));
-    const double *y = S.vec[BY];
+    const double *__restrict__ y = S.vec[BY];
     // z_{-1} = M^{-1} b, unscaled (the first Lanczos vector is z_{-1} / beta1)
-    double *v = S.vec[BZ0], *x = S.vec[BDX], *w = S.vec[BW], *w1 = S.vec[BW1], *w2 = S.vec[BW2];
+    double *__restrict__ v = S.vec[BZ0], *__restrict__ x = S.vec[BDX];
+    double *__restrict__ w = S.vec[BW];
+    double *__restrict__ w1 = S.vec[BW1], *__restrict__ w2 = S.vec[BW2];
     for (int i = i0; i < i1; i += VB) {
         v[i] = y[i];
         x[i] = 0.0;
@@ -374,12 +377,14 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     }
     if (!upd && !gat) return;
     const Geom &g = S.g;
-    const ET *eV = (const ET *)S.eV;
+    const ET *__restrict__ eV = (const ET *)S.eV;
     const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
     const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;
     const double cr = u.o.j >= 1 ? u.o.beta / u.o.oldb : 0.0;
-    const double *zc = S.vec[vzc], *zp = S.vec[vzp], *w1 = S.vec[vw1], *w2 = S.vec[vw2];
-    double *r1 = S.vec[vr1], *x = S.vec[BDX], *wo = S.vec[vwout];
+    const double *__restrict__ zc = S.vec[vzc], *__restrict__ zp = S.vec[vzp];
+    const double *__restrict__ w1 = S.vec[vw1], *__restrict__ w2 = S.vec[vw2];
+    double *__restrict__ r1 = S.vec[vr1], *__restrict__ x = S.vec[BDX];
+    double *__restrict__ wo = S.vec[vwout];
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
         if (upd) {
@@ -422,8 +427,8 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
     const double alpha = seg_sum(part1, r.vbegin, r.vcount, red);
     const double c = alpha / s.beta;
     const bool useM = jac[t.slot] != 0;
-    const double *m = S.vec[BMINV], *r2 = S.vec[vr2];
-    double *hv = S.vec[vhv], *z = S.vec[vz];
+    const double *__restrict__ m = S.vec[BMINV], *__restrict__ r2 = S.vec[vr2];
+    double *__restrict__ hv = S.vec[vhv], *__restrict__ z = S.vec[vz];
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
         const double h = hv[i] - c * r2[i];
@@ -463,8 +468,9 @@ __global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
     const BUpd u = bs_update(sp, alpha, bb);
     if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = u.o;
     const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
-    const double *zp = S.vec[vzp], *w1 = S.vec[vw1], *w2 = S.vec[vw2];
-    double *x = S.vec[BDX], *wo = S.vec[vwout];
+    const double *__restrict__ zp = S.vec[vzp];
+    const double *__restrict__ w1 = S.vec[vw1], *__restrict__ w2 = S.vec[vw2];
+    double *__restrict__ x = S.vec[BDX], *__restrict__ wo = S.vec[vwout];
     for (int i = i0; i < i1; i += VB) {
         const double wn = (sprev * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
         wo[i] = wn;
