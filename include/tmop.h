@@ -220,6 +220,17 @@ int tmop_newton_step(tmop_ctx *ctx, double *x_dev_inout, int n_minres, int jacob
 int tmop_minres(tmop_ctx *ctx, const double *b_dev, double *dx_dev, int max_its, double rtol,
                 int jacobi, int *its);
 
+/* MINRES (Paige and Saunders' recurrences, Sec. 2.3) forms its solution as a
+ * combination of the preconditioned Lanczos vectors.  When max_its + 1 of them
+ * (each N_dof doubles, rounded up to 256 bytes) fit in max_bytes and in free
+ * device memory, and max_its <= 255, tmop_minres, tmop_solve and
+ * tmop_newton_step keep them resident in a buffer the context owns (grown on
+ * demand, freed by tmop_destroy) and form dx once after the loop; otherwise
+ * every iteration updates dx with the three-term recurrence.  Both give the
+ * same iterates up to rounding.  Default: no limit; 0 always selects the
+ * three-term update.  Takes effect on the next solve. */
+int tmop_set_lanczos_bank_limit(tmop_ctx *ctx, size_t max_bytes);
+
 /* ---------------------------------------------------------------------- */
 /* Batched and served solves                                               */
 /* ---------------------------------------------------------------------- */

@@ -258,6 +258,13 @@ struct tmop_ctx {
     double *sv[SV_COUNT] = {};
     MinresState *mst = nullptr;
     MinresState *hmst = nullptr;
+    // resident Lanczos vectors (bank_cap of them, bank_stride doubles apart)
+    // and the per-update scalars; bank_limit caps the bank's bytes
+    double *bank = nullptr;
+    int bank_cap = 0;
+    long bank_stride = 0;
+    size_t bank_limit = SIZE_MAX;
+    MrHist *mhist = nullptr;
     // HIP-event timing of the Hessian actions inside MINRES
     bool timing = false;
     std::vector<hipEvent_t> tev;
@@ -343,6 +350,8 @@ static void free_ctx(tmop_ctx *c)
     hipFree(c->x0buf);
     for (auto &v : c->sv) hipFree(v);
     hipFree(c->mst);
+    hipFree(c->bank);
+    hipFree(c->mhist);
     if (c->hmst) hipHostFree(c->hmst);
     delete c;
 }
@@ -431,6 +440,7 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     ALLOC(c->diag, sizeof(double) * c->ndof);
     ALLOC(c->minv, sizeof(double) * c->ndof);
     ALLOC(c->mst, 2 * sizeof(MinresState));
+    ALLOC(c->mhist, MR_MAX_BASIS * sizeof(MrHist));
 #undef ALLOC
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscal, sizeof(double) * 64, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmst, 2 * sizeof(MinresState), 0);
@@ -685,39 +695,103 @@ static void make_jacobi(tmop_ctx *c)
     c->have_diag = true;
 }
 
-// MINRES on H_c dx = b.  Buffers from the solver pool; device state
-// double-buffered in c->mst[0..1] (see vec.hip for the recurrences).
-static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
-                       bool jacobi, int check_every, int *its_out)
+// Room for nvec resident Lanczos vectors, within bank_limit.  False (and
+// nothing allocated) when they do not fit; the solve then takes the
+// three-term update on every iteration.
+static bool ensure_bank(tmop_ctx *c, int nvec)
 {
-    CHK(ensure_solver(c));
+    if (nvec > MR_MAX_BASIS) return false;
+    const long stride = ((long)c->ndof + 31) / 32 * 32;  // 256-byte aligned vectors
+    const size_t need = (size_t)nvec * stride * sizeof(double);
+    if (need > c->bank_limit) return false;
+    if (c->bank && c->bank_cap >= nvec) return true;
+    if (c->bank) {
+        // the previous solve's kernels may still read the old bank
+        if (hipStreamSynchronize(c->s) != hipSuccess) return false;
+        hipFree(c->bank);
+        c->bank = nullptr;
+        c->bank_cap = 0;
+    }
+    if (hipMalloc((void **)&c->bank, need) != hipSuccess) {
+        (void)hipGetLastError();  // out of memory is not an error here
+        c->bank = nullptr;
+        return false;
+    }
+    c->bank_cap = nvec;
+    c->bank_stride = stride;
+    return true;
+}
+
+// Iterations with the preconditioned Lanczos vectors resident in the bank:
+// z_j in bank vector j, the update scalars to mhist, dx formed once at the
+// end.  Returns the iterations run.
+static int minres_resident(tmop_ctx *c, const double *minv, double *R1, double *R2,
+                           double *const P1[2], double *P2, double *dx, int max_its,
+                           int check_every)
+{
     const long n = c->ndof;
+    const bool fp32 = c->precision == TMOP_MIXED;
+    int J = 0;
+    for (int j = 0; j < max_its; ++j) {
+        // S_{j-1} in mst[(j-1)&1], S_j to mst[j&1]
+        MinresState *sin = c->mst + ((j + 1) & 1), *sout = c->mst + (j & 1);
+        const double *zc = c->bank + (long)j * c->bank_stride;
+        double *znext = c->bank + (long)(j + 1) * c->bank_stride;
+        const bool rec = c->timing && c->tev_used + 3 <= (int)c->tev.size();
+        if (rec) (void)hipEventRecord(c->tev[c->tev_used], c->s);
+        apply_elem(c, zc);
+        if (rec) (void)hipEventRecord(c->tev[c->tev_used + 1], c->s);
+        // scalars of update j-1 to mhist, then G^T with the first Lanczos
+        // update into R1
+        mr_gather_upd(c->g, c->csr_ptr, c->csr_ent, c->eV, fp32, j, sin, sout, P1[(j + 1) & 1],
+                      P2, nullptr, zc, nullptr, nullptr, nullptr, nullptr, R1, P1[j & 1],
+                      c->mhist, c->s);
+        if (rec) {
+            (void)hipEventRecord(c->tev[c->tev_used + 2], c->s);
+            c->tev_used += 3;
+        }
+        mr_lanczos2(n, j, sout, P1[j & 1], R1, R2, minv, znext, P2, c->s);
+        std::swap(R1, R2);  // r1 <- r2, r2 <- hv
+        J = j + 1;
+        if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
+            (void)hipMemcpyAsync(c->hmst, sout, sizeof(MinresState), hipMemcpyDeviceToHost, c->s);
+            (void)hipStreamSynchronize(c->s);
+            if (c->hmst->stop != 0x7fffffff) break;
+        }
+    }
+    // the last update, then dx from the resident vectors (dx = 0 from the
+    // start when nothing ran)
+    if (J > 0)
+        mr_combine(n, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2,
+                   c->mhist, c->bank, c->bank_stride, dx, c->s);
+    // R1/R2 are scratch between calls; keep the pool's pointers as they were
+    return J;
+}
+
+// Iterations with the three-term solution update in every gather (the
+// Lanczos vectors ping-pong between two buffers).  Returns the iterations run.
+static int minres_three_term(tmop_ctx *c, const double *minv, double *const P1[2], double *P2,
+                             double *dx, int max_its, int check_every)
+{
+    const long n = c->ndof;
+    const bool fp32 = c->precision == TMOP_MIXED;
     // R1: r1, overwritten in place by hv; R2: r2; ZC: z_{j-1} (the element
     // kernel's input, v_j = z_{j-1} / beta_j); ZP: z_{j-2}, then z_j
     double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *ZC = c->sv[SV_Y], *ZP = c->sv[SV_V];
     double *W = c->sv[SV_W], *W1 = c->sv[SV_W1], *W2 = c->sv[SV_W2];
-    // part1 alternates between iterations (iteration j reads j-1's while writing its own)
-    double *P1[2] = {c->part, c->part + 2048};
-    double *P2 = c->part + 1024;
-    const double *minv = jacobi ? c->minv : nullptr;
-    const bool fp32 = c->precision == TMOP_MIXED;
-    // z_{-1} = M^{-1} b goes to ZC; no separate v
-    mr_init(n, b, minv, R1, R2, ZC, nullptr, dx, W, W1, W2, P1[0], c->mst, rtol, c->s);
-    c->tev_used = 0;
-    int J = 0;  // iterations run
+    int J = 0;
     for (int j = 0; j < max_its; ++j) {
-        // S_{j-1} in mst[(j-1)&1], S_j to mst[j&1]
         MinresState *sin = c->mst + ((j + 1) & 1), *sout = c->mst + (j & 1);
         const bool rec = c->timing && c->tev_used + 3 <= (int)c->tev.size();
-        if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used], c->s));
+        if (rec) (void)hipEventRecord(c->tev[c->tev_used], c->s);
         apply_elem(c, ZC);
-        if (rec) HIPCHK(hipEventRecord(c->tev[c->tev_used + 1], c->s));
+        if (rec) (void)hipEventRecord(c->tev[c->tev_used + 1], c->s);
         // deferred update of iteration j-1 (formula's w1, w2 = buffers W2, W;
         // new w into W1), then G^T with the first Lanczos update into R1
         mr_gather_upd(c->g, c->csr_ptr, c->csr_ent, c->eV, fp32, j, sin, sout, P1[(j + 1) & 1],
-                      P2, ZP, ZC, W2, W, W1, dx, R1, P1[j & 1], c->s);
+                      P2, ZP, ZC, W2, W, W1, dx, R1, P1[j & 1], nullptr, c->s);
         if (rec) {
-            HIPCHK(hipEventRecord(c->tev[c->tev_used + 2], c->s));
+            (void)hipEventRecord(c->tev[c->tev_used + 2], c->s);
             c->tev_used += 3;
         }
         // z_j into ZP (z_{j-2} is dead after the update above)
@@ -732,8 +806,8 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
         }
         J = j + 1;
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
-            HIPCHK(hipMemcpyAsync(c->hmst, sout, sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
+            (void)hipMemcpyAsync(c->hmst, sout, sizeof(MinresState), hipMemcpyDeviceToHost, c->s);
+            (void)hipStreamSynchronize(c->s);
             if (c->hmst->stop != 0x7fffffff) break;
         }
     }
@@ -746,17 +820,46 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
         W2 = oW;
         W = oW1;
     }
+    // keep the rotated pointers consistent for the next call
     c->sv[SV_Y] = ZC;
     c->sv[SV_V] = ZP;
-    // keep the rotated pointers consistent for the next call
     c->sv[SV_R1] = R1;
     c->sv[SV_R2] = R2;
     c->sv[SV_W] = W;
     c->sv[SV_W1] = W1;
     c->sv[SV_W2] = W2;
+    return J;
+}
+
+// MINRES on H_c dx = b, x_0 = 0.  Device state double-buffered in
+// c->mst[0..1] (see vec.hip for the recurrences).  When the max_its + 1
+// preconditioned Lanczos vectors fit in the bank they stay resident and dx
+// is formed once after the loop; otherwise every iteration takes the
+// three-term solution update.
+static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, double rtol,
+                       bool jacobi, int check_every, int *its_out)
+{
+    CHK(ensure_solver(c));
+    const long n = c->ndof;
+    // part1 alternates between iterations (iteration j reads j-1's while writing its own)
+    double *const P1[2] = {c->part, c->part + 2048};
+    double *P2 = c->part + 1024;
+    const double *minv = jacobi ? c->minv : nullptr;
+    const bool resident = ensure_bank(c, max_its + 1);
+    c->tev_used = 0;
+    if (resident) {
+        // z_{-1} = M^{-1} b is bank vector 0; no w vectors
+        mr_init(n, b, minv, c->sv[SV_R1], c->sv[SV_R2], c->bank, nullptr, dx, nullptr, nullptr,
+                nullptr, P1[0], c->mst, rtol, c->s);
+        minres_resident(c, minv, c->sv[SV_R1], c->sv[SV_R2], P1, P2, dx, max_its, check_every);
+    } else {
+        mr_init(n, b, minv, c->sv[SV_R1], c->sv[SV_R2], c->sv[SV_Y], nullptr, dx, c->sv[SV_W],
+                c->sv[SV_W1], c->sv[SV_W2], P1[0], c->mst, rtol, c->s);
+        minres_three_term(c, minv, P1, P2, dx, max_its, check_every);
+    }
+    HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->hmst, c->mst, 2 * sizeof(MinresState), hipMemcpyDeviceToHost, c->s));
     HIPCHK(hipStreamSynchronize(c->s));
-    HIPCHK(hipGetLastError());
     const MinresState &fin = c->hmst[0].its >= c->hmst[1].its ? c->hmst[0] : c->hmst[1];
     if (its_out) *its_out = fin.its;
     // every recorded action is counted (the element kernel runs even after
@@ -1035,6 +1138,19 @@ extern "C" int tmop_set_timing(tmop_ctx *c, int enable)
     if (c->timing && c->tev.empty()) {
         c->tev.resize(3 * 256);
         for (auto &e : c->tev) HIPCHK(hipEventCreate(&e));
+    }
+    return TMOP_OK;
+}
+
+extern "C" int tmop_set_lanczos_bank_limit(tmop_ctx *c, size_t max_bytes)
+{
+    if (!c) return fail(TMOP_ERR_INVALID_ARG, "null context");
+    c->bank_limit = max_bytes;
+    if (c->bank && (size_t)c->bank_cap * c->bank_stride * sizeof(double) > max_bytes) {
+        HIPCHK(hipStreamSynchronize(c->s));
+        HIPCHK(hipFree(c->bank));
+        c->bank = nullptr;
+        c->bank_cap = 0;
     }
     return TMOP_OK;
 }

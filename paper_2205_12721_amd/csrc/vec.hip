@@ -284,8 +284,9 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_init(long n, const double *__rest
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// beta1 from the partials; st[0] and st[1] the initial state; x = w = w1 = w2 = 0;
-// v = y / beta1 when v is given (the solver here keeps y unscaled instead).
+// beta1 from the partials; st[0] and st[1] the initial state; x = 0, and
+// w = w1 = w2 = 0 when w is given (the three-term update); v = y / beta1 when
+// v is given (the solver here keeps y unscaled instead).
 __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, double rtol,
                                                      const double *__restrict__ part, int nb,
                                                      const double *__restrict__ y,
@@ -302,9 +303,11 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, do
     for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
         if (v) v[i] = s * y[i];
         x[i] = 0.0;
-        w[i] = 0.0;
-        w1[i] = 0.0;
-        w2[i] = 0.0;
+        if (w) {
+            w[i] = 0.0;
+            w1[i] = 0.0;
+            w2[i] = 0.0;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         MinresState &o = st[0];
@@ -379,6 +382,9 @@ __device__ inline MrUpd mr_scalars(const MinresState &sin, int jm, double alpha,
 //     w' = (z_{j-2}/beta_{j-1} - oldeps w1 - delta w2) / gamma;  x += phi w'
 //   then hv = G^T eV / beta_j (fixed DoFs: v_j) - (beta_j/beta_{j-1}) r1, in
 //   place of r1;  part1 = <v_j, hv>.
+// With hist given (the Lanczos vectors kept resident) the update's scalars go
+// to hist[j-1] instead and w, x are not touched: the solution is formed once
+// after the loop (k_mr_combine).
 template <int DIM, typename ET>
 __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
     Geom g, const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
     const double *__restrict__ p2prev, int nb, const double *__restrict__ zp,
     const double *__restrict__ zc, const double *__restrict__ w1, const double *__restrict__ w2,
     double *__restrict__ wout, double *__restrict__ x, double *__restrict__ r1hv,
-    double *__restrict__ part)
+    double *__restrict__ part, MrHist *__restrict__ hist)
 {
     __shared__ double red[VBLOCK / 64];
     const MinresState S = *sin;
@@ -399,10 +405,14 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
         const double bb = sum_partials(p2prev, nb, red);
         u = mr_scalars(S, j - 1, alpha, bb);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *sout = u.o;
-    const bool gat = j <= u.o.stop;
-    if (!upd && !gat) return;
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;      // v_{j-1} = sp z_{j-2}
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *sout = u.o;
+        if (hist && upd) hist[j - 1] = MrHist{u.ig, u.oldeps, u.delta, u.phi, sp, {}};
+    }
+    const bool gat = j <= u.o.stop;
+    const bool vupd = upd && !hist;
+    if (!vupd && !gat) return;
     const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;  // v_j = sc z_{j-1}
     const double cr = j >= 1 ? u.o.beta / u.o.oldb : 0.0;
     double s = 0.0;
@@ -415,7 +425,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t idx = (size_t)c * g.nx + node;
-            if (upd) {
+            if (vupd) {
                 const double wn = (sp * zp[idx] - u.oldeps * w1[idx] - u.delta * w2[idx]) * u.ig;
                 wout[idx] = wn;
                 x[idx] += u.phi * wn;
@@ -464,6 +474,86 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
     }
 }
 
+// The solution from the resident Lanczos vectors, once after the loop.  The
+// last update (jm) is taken here from its partials as in k_mr_finish; then
+// x = sum_m phi_m w_m with every w_m a combination of v_0..v_m, so
+// x = sum_i c_i v_i where lane i runs the three-term recurrence of the w's
+// on their i-th coefficients:  W_m[i] = (delta_{mi} - oldeps_m W_{m-2}[i]
+// - delta_m W_{m-1}[i]) ig_m,  c_i = sum_{m>=i} phi_m W_m[i].  Every block
+// forms the same coefficients in the same order.  bank holds z_0..z_{K-1}
+// with the given stride (v_i = sv_i z_i).
+__global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
+                                                       const MinresState *__restrict__ sin,
+                                                       MinresState *__restrict__ sout,
+                                                       const double *__restrict__ p1,
+                                                       const double *__restrict__ p2, int nb,
+                                                       MrHist *__restrict__ hist,
+                                                       const double *__restrict__ bank,
+                                                       long stride, double *__restrict__ x)
+{
+    static_assert(MR_MAX_BASIS <= VBLOCK, "one lane per coefficient");
+    __shared__ double red[VBLOCK / 64];
+    __shared__ double hig[MR_MAX_BASIS], hoe[MR_MAX_BASIS], hde[MR_MAX_BASIS],
+        hph[MR_MAX_BASIS], coef[MR_MAX_BASIS];
+    const MinresState S = *sin;
+    const bool last = jm >= 0 && jm <= S.stop;
+    // updates taken: 0..K-1 (the earlier ones by the gathers)
+    const int K = last ? jm + 1 : (S.stop < jm ? S.stop + 1 : (jm > 0 ? jm : 0));
+    MrUpd u{};
+    u.o = S;
+    if (last) {
+        const double alpha = sum_partials(p1, nb, red);
+        const double bb = sum_partials(p2, nb, red);
+        u = mr_scalars(S, jm, alpha, bb);
+    }
+    const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *sout = u.o;
+        if (last) hist[jm] = MrHist{u.ig, u.oldeps, u.delta, u.phi, sp, {}};
+    }
+    const int t = threadIdx.x;
+    double svt = 0.0;
+    if (t < K) {
+        MrHist h;
+        if (last && t == jm)
+            h = MrHist{u.ig, u.oldeps, u.delta, u.phi, sp, {}};
+        else
+            h = hist[t];
+        hig[t] = h.ig;
+        hoe[t] = h.oldeps;
+        hde[t] = h.delta;
+        hph[t] = h.phi;
+        svt = h.sv;
+    }
+    __syncthreads();
+    if (t < K) {
+        double a2 = 0.0, a1 = 0.0, c = 0.0;
+        for (int m = t; m < K; ++m) {
+            const double wn = ((m == t ? 1.0 : 0.0) - hoe[m] * a2 - hde[m] * a1) * hig[m];
+            c += hph[m] * wn;
+            a2 = a1;
+            a1 = wn;
+        }
+        coef[t] = c * svt;
+    }
+    __syncthreads();
+    for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
+        double acc = 0.0;
+        int m = 0;
+        for (; m + 4 <= K; m += 4) {
+            const double z0 = bank[(long)m * stride + i], z1 = bank[(long)(m + 1) * stride + i];
+            const double z2 = bank[(long)(m + 2) * stride + i];
+            const double z3 = bank[(long)(m + 3) * stride + i];
+            acc += coef[m] * z0;
+            acc += coef[m + 1] * z1;
+            acc += coef[m + 2] * z2;
+            acc += coef[m + 3] * z3;
+        }
+        for (; m < K; ++m) acc += coef[m] * bank[(long)m * stride + i];
+        x[i] = acc;
+    }
+}
+
 __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresState *__restrict__ st,
                                                   const double *__restrict__ part1, int nb,
                                                   double *__restrict__ hv,
@@ -502,14 +592,14 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
                    bool fp32, int j, const MinresState *sin, MinresState *sout,
                    const double *p1prev, const double *p2prev, const double *zp, const double *zc,
                    const double *w1, const double *w2, double *wout, double *x, double *r1hv,
-                   double *part, hipStream_t s)
+                   double *part, MrHist *hist, hipStream_t s)
 {
     // the partials of every kernel of the iteration use the same block count
     const int nb = reduce_blocks((long)g.dim * g.nx);
 #define TMOP_G(D, T)                                                                           \
     hipLaunchKernelGGL((k_mr_gather_upd<D, T>), dim3(nb), dim3(VBLOCK), 0, s, g, csr_ptr,      \
                        csr_ent, (const T *)eV, j, sin, sout, p1prev, p2prev, nb, zp, zc, w1, w2, \
-                       wout, x, r1hv, part);
+                       wout, x, r1hv, part, hist);
     if (g.dim == 3) {
         if (fp32) {
             TMOP_G(3, float)
@@ -541,6 +631,15 @@ void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const 
     const int nb = reduce_blocks(n);
     hipLaunchKernelGGL(k_mr_finish, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, p2, nb, zp,
                        w1, w2, wout, x);
+}
+
+void mr_combine(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
+                const double *p2, MrHist *hist, const double *bank, long stride, double *x,
+                hipStream_t s)
+{
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_mr_combine, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, p2, nb,
+                       hist, bank, stride, x);
 }
 
 }  // namespace tmop

@@ -17,6 +17,17 @@ struct MinresState {
     int pad;
 };
 
+// Scalars of one MINRES update, kept when the Lanczos vectors stay resident
+// and the solution is formed once after the loop: the update m takes
+// w_m = (v_m - oldeps w_{m-2} - delta w_{m-1}) ig and x += phi w_m, with
+// v_m = sv z_m (z_m the unscaled preconditioned Lanczos vector).
+struct MrHist {
+    double ig, oldeps, delta, phi, sv;
+    double pad[3];
+};
+// Most updates one combination can take (one lane per coefficient).
+constexpr int MR_MAX_BASIS = 256;
+
 void launch_gather(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent, const void *eV,
                    bool fp32, double *out, int fix_mode, const double *src, hipStream_t s);
 void launch_reduce3(const double *part, int nb, double *out, hipStream_t s);
@@ -36,11 +47,14 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
                    bool fp32, int j, const MinresState *sin, MinresState *sout,
                    const double *p1prev, const double *p2prev, const double *zp, const double *zc,
                    const double *w1, const double *w2, double *wout, double *x, double *r1hv,
-                   double *part, hipStream_t s);
+                   double *part, MrHist *hist, hipStream_t s);
 void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, double *hv,
                  const double *r2, const double *minv, double *z, double *part2, hipStream_t s);
 void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
                const double *p2, const double *zp, const double *w1, const double *w2,
                double *wout, double *x, hipStream_t s);
+void mr_combine(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
+                const double *p2, MrHist *hist, const double *bank, long stride, double *x,
+                hipStream_t s);
 
 }  // namespace tmop

@@ -96,6 +96,7 @@ SIGNATURES = {
                     ctypes.POINTER(ctypes.c_int)],
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
+    "tmop_set_lanczos_bank_limit": [_P, ctypes.c_size_t],
     "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
     "tmop_autotune": [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "tmop_tile_epb": [_P, ctypes.POINTER(ctypes.c_int)],
@@ -325,6 +326,11 @@ class Context:
 
     def set_timing(self, enable=True):
         _check(lib().tmop_set_timing(self._h, int(bool(enable))))
+
+    def set_lanczos_bank_limit(self, max_bytes):
+        """Bytes the resident MINRES Lanczos vectors may take (0: three-term
+        solution update every iteration)."""
+        _check(lib().tmop_set_lanczos_bank_limit(self._h, int(max_bytes)))
 
     def time_apply(self, v, y, n):
         e, t = ctypes.c_double(), ctypes.c_double()

@@ -108,15 +108,17 @@ def test_solve_error_codes():
     ctx.close()
 
 
+@pytest.mark.parametrize("basis_mode", ["resident", "three_term"])
 @pytest.mark.parametrize("jacobi", [True, False])
 @pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("dim,ns,p,nq,its", [(3, (3, 3, 3), 2, 4, 12), (2, (5, 4), 3, 5, 12),
                                               (3, (2, 2, 2), 1, 3, 50)])
-def test_minres_matches_oracle(dim, ns, p, nq, its, storage, jacobi):
-    """Device MINRES (fused kernels, double-buffered state, the solution update deferred
-    to the next iteration) vs the oracle's MINRES on the same operator, with and without
-    the Jacobi preconditioner; the last case converges in fewer than max_its iterations,
-    so the early-exit path of the device kernels is exercised."""
+def test_minres_matches_oracle(dim, ns, p, nq, its, storage, jacobi, basis_mode):
+    """Device MINRES (fused kernels, double-buffered state) vs the oracle's MINRES on the
+    same operator, with and without the Jacobi preconditioner, with the solution formed
+    once from the resident Lanczos vectors or by the three-term update deferred to the
+    next iteration; the last case converges in fewer than max_its iterations, so the
+    early-exit path of the device kernels is exercised."""
     from oracle import solver
     from paper_2205_12721_amd.tmop import Context
     pb, x = make_case(dim, ns, p, nq, seed=61)
@@ -125,9 +127,42 @@ def test_minres_matches_oracle(dim, ns, p, nq, its, storage, jacobi):
     pre = (lambda r: minv * r) if jacobi else None
     xo, ito, _ = solver.minres(lambda v: pb.hvp(x, v), g, pre, rtol=1e-12, maxit=its)
     ctx = Context(dim, ns, p, nq, storage=storage)
+    if basis_mode == "three_term":
+        ctx.set_lanczos_bank_limit(0)
     ctx.hessian_setup(to_dev(x))
     dx, itg = ctx.minres(to_dev(g), max_its=its, rtol=1e-12, jacobi=jacobi)
-    log("minres", dim, ns, p, nq, storage, "its oracle", ito, "gpu", itg, "rel", rel(to_host(dx), xo))
+    log("minres", dim, ns, p, nq, storage, basis_mode, "its oracle", ito, "gpu", itg, "rel",
+        rel(to_host(dx), xo))
     assert itg == ito
     assert rel(to_host(dx), xo) <= 1e-9
     ctx.close()
+
+
+def test_minres_basis_modes_agree():
+    """The resident-basis and three-term MINRES give the same dx to rounding, across calls
+    that grow the bank (5, then 30 iterations), shrink the limit below the need (falls back
+    to three-term) and run no iteration at all (dx = 0)."""
+    from paper_2205_12721_amd.tmop import Context
+    pb, x = make_case(3, (3, 3, 3), 2, 4, seed=62)
+    g = to_dev(pb.gradient(x))
+    a = Context(3, (3, 3, 3), 2, 4)
+    b = Context(3, (3, 3, 3), 2, 4)
+    b.set_lanczos_bank_limit(0)
+    for ctx in (a, b):
+        ctx.hessian_setup(to_dev(x))
+    for its in (5, 30, 7):
+        da, ia = a.minres(g, max_its=its, rtol=1e-14, jacobi=True)
+        db, ib = b.minres(g, max_its=its, rtol=1e-14, jacobi=True)
+        log("basis modes", its, ia, ib, rel(to_host(da), to_host(db)))
+        assert ia == ib
+        assert rel(to_host(da), to_host(db)) <= 1e-12
+    # a limit below 8 vectors: this call takes the three-term update
+    a.set_lanczos_bank_limit(8 * 8 * (3 * 7 ** 3) - 1)
+    da, ia = a.minres(g, max_its=7, rtol=1e-14, jacobi=True)
+    db, ib = b.minres(g, max_its=7, rtol=1e-14, jacobi=True)
+    assert ia == ib and rel(to_host(da), to_host(db)) <= 1e-15
+    for ctx in (a, b):
+        d0, i0 = ctx.minres(g, max_its=0, rtol=1e-14, jacobi=True)
+        assert i0 == 0 and not np.any(to_host(d0))
+    a.close()
+    b.close()
