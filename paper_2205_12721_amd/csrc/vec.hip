@@ -251,16 +251,26 @@ void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hi
 // residual estimate drops below rtol*beta1 or the Lanczos vector vanishes).
 // ------------------------------------------------------------------------
 
-// Sum of part[0..nb) in a fixed order, identical in every workgroup.
-__device__ inline double sum_partials(const double *__restrict__ part, int nb, double *red)
+// Sum of part[0..nb) in every lane, without a barrier: each wave reads all
+// partials (lane l adds l, l+64, ... in that order, 16 loads in flight) and
+// reduces them by butterfly, which leaves the same bits in every lane, wave
+// and workgroup.  Loads the caller issued before stay in flight meanwhile.
+__device__ inline double sum_partials(const double *__restrict__ part, int nb)
 {
+    constexpr int RU = 16;
+    const int l = threadIdx.x & 63;
     double s = 0.0;
-    for (int k = threadIdx.x; k < nb; k += VBLOCK) s += part[k];
-    s = block_sum(s, red);
-    __shared__ double bcast;
-    if (threadIdx.x == 0) bcast = s;
-    __syncthreads();
-    return bcast;
+    for (int k0 = 0; k0 < nb; k0 += 64 * RU) {
+        double t[RU];
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+            const int k = k0 + r * 64 + l;
+            t[r] = k < nb ? part[k] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < RU; ++r) s += t[r];
+    }
+    return wave_sum(s);
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_mr_init(long n, const double *__restrict__ b,
@@ -296,8 +306,7 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, do
                                                      double *__restrict__ w1,
                                                      double *__restrict__ w2)
 {
-    __shared__ double red[VBLOCK / 64];
-    const double bb = sum_partials(part, nb, red);
+    const double bb = sum_partials(part, nb);
     const double b1 = sqrt(fmax(bb, 0.0));
     const double s = b1 > 0.0 ? 1.0 / b1 : 0.0;
     for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
@@ -398,11 +407,28 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
     __shared__ double red[VBLOCK / 64];
     const MinresState S = *sin;
     const bool upd = j >= 1 && j - 1 <= S.stop;
+    const int nstride = gridDim.x * VBLOCK;
+    const int node0 = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x;
+    // The first node's loads go out before the partial sums.  The update of
+    // j-1 can end the gather only by setting stop = j-1, so j <= S.stop
+    // covers every gather that runs.
+    const bool pre = j <= S.stop && node0 < g.nx;
+    double a0[DIM], z0[DIM], q0[DIM];
+    bool f0[DIM];
+    if (pre) {
+        gather_node<DIM, ET>(g, ptr, ent, eV, node0, a0, f0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t idx = (size_t)c * g.nx + node0;
+            z0[c] = zc[idx];
+            q0[c] = j >= 1 ? r1hv[idx] : 0.0;
+        }
+    }
     MrUpd u{};
     u.o = S;
     if (upd) {
-        const double alpha = sum_partials(p1prev, nb, red);
-        const double bb = sum_partials(p2prev, nb, red);
+        const double alpha = sum_partials(p1prev, nb);
+        const double bb = sum_partials(p2prev, nb);
         u = mr_scalars(S, j - 1, alpha, bb);
     }
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;      // v_{j-1} = sp z_{j-2}
@@ -417,11 +443,26 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
     const double cr = j >= 1 ? u.o.beta / u.o.oldb : 0.0;
     double s = 0.0;
     // one lane per node, all components
-    for (int node = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x; node < g.nx;
-         node += gridDim.x * VBLOCK) {
-        double a[DIM];
+    for (int node = node0; node < g.nx; node += nstride) {
+        double a[DIM], zv[DIM], qv[DIM];
         bool fixed[DIM];
-        if (gat) gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
+        if (node == node0 && pre) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                a[c] = a0[c];
+                fixed[c] = f0[c];
+                zv[c] = z0[c];
+                qv[c] = q0[c];
+            }
+        } else if (gat) {
+            gather_node<DIM, ET>(g, ptr, ent, eV, node, a, fixed);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const size_t idx = (size_t)c * g.nx + node;
+                zv[c] = zc[idx];
+                qv[c] = j >= 1 ? r1hv[idx] : 0.0;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const size_t idx = (size_t)c * g.nx + node;
@@ -431,9 +472,9 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
                 x[idx] += u.phi * wn;
             }
             if (gat) {
-                const double vi = sc * zc[idx];
+                const double vi = sc * zv[c];
                 double h = fixed[c] ? vi : sc * a[c];
-                if (j >= 1) h -= cr * r1hv[idx];
+                if (j >= 1) h -= cr * qv[c];
                 r1hv[idx] = h;
                 s += vi * h;
             }
@@ -456,14 +497,13 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
                                                       double *__restrict__ wout,
                                                       double *__restrict__ x)
 {
-    __shared__ double red[VBLOCK / 64];
     const MinresState S = *sin;
     if (jm < 0 || jm > S.stop) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *sout = S;
         return;
     }
-    const double alpha = sum_partials(p1, nb, red);
-    const double bb = sum_partials(p2, nb, red);
+    const double alpha = sum_partials(p1, nb);
+    const double bb = sum_partials(p2, nb);
     const MrUpd u = mr_scalars(S, jm, alpha, bb);
     if (blockIdx.x == 0 && threadIdx.x == 0) *sout = u.o;
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
@@ -492,7 +532,6 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
                                                        long stride, double *__restrict__ x)
 {
     static_assert(MR_MAX_BASIS <= VBLOCK, "one lane per coefficient");
-    __shared__ double red[VBLOCK / 64];
     __shared__ double hig[MR_MAX_BASIS], hoe[MR_MAX_BASIS], hde[MR_MAX_BASIS],
         hph[MR_MAX_BASIS], coef[MR_MAX_BASIS];
     const MinresState S = *sin;
@@ -502,8 +541,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
     MrUpd u{};
     u.o = S;
     if (last) {
-        const double alpha = sum_partials(p1, nb, red);
-        const double bb = sum_partials(p2, nb, red);
+        const double alpha = sum_partials(p1, nb);
+        const double bb = sum_partials(p2, nb);
         u = mr_scalars(S, jm, alpha, bb);
     }
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
@@ -564,10 +603,33 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresSta
 {
     if (j > st->stop) return;
     __shared__ double red[VBLOCK / 64];
-    const double alpha = sum_partials(part1, nb, red);
+    // this lane's first RU entries are loaded before alpha is summed
+    constexpr int RU = 8;
+    const long stride = (long)gridDim.x * VBLOCK;
+    const long i0 = blockIdx.x * (long)VBLOCK + threadIdx.x;
+    double hr[RU], rr[RU], mr[RU];
+#pragma unroll
+    for (int k = 0; k < RU; ++k) {
+        const long i = i0 + k * stride;
+        hr[k] = i < n ? hv[i] : 0.0;
+        rr[k] = i < n ? r2[i] : 0.0;
+        mr[k] = i < n && minv ? minv[i] : 1.0;
+    }
+    const double alpha = sum_partials(part1, nb);
     const double c = alpha / st->beta;
     double s = 0.0;
-    for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
+#pragma unroll
+    for (int k = 0; k < RU; ++k) {
+        const long i = i0 + k * stride;
+        if (i < n) {
+            const double h = hr[k] - c * rr[k];
+            hv[i] = h;
+            const double zi = minv ? mr[k] * h : h;
+            z[i] = zi;
+            s += h * zi;
+        }
+    }
+    for (long i = i0 + RU * stride; i < n; i += stride) {
         const double h = hv[i] - c * r2[i];
         hv[i] = h;
         const double zi = minv ? minv[i] * h : h;
