@@ -429,7 +429,7 @@ extern "C" int tmop_create(tmop_ctx **out, const tmop_mesh_desc *m, const tmop_p
     const size_t tbytes = c->precision == TMOP_MIXED ? 4 : 8;
     c->H_bytes = (size_t)ne * qdata_stride(S, nqe, (int)tbytes) * tbytes;
     c->eV_bytes = (size_t)ne * d * np * 8;
-    c->part_len = 3 * std::max(c->grid, 1024) + 64;
+    c->part_len = std::max(3 * std::max(c->grid, 1024), 2 * MR_MAX_PARTIALS + 1024) + 64;
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, bytes)                                       \
     if (e == hipSuccess) e = hipMalloc((void **)&(ptr), (bytes));
@@ -731,6 +731,7 @@ static int minres_resident(tmop_ctx *c, const double *minv, double *R1, double *
 {
     const long n = c->ndof;
     const bool fp32 = c->precision == TMOP_MIXED;
+    const int nbg = mr_gather_grid(c->g);
     int J = 0;
     for (int j = 0; j < max_its; ++j) {
         // S_{j-1} in mst[(j-1)&1], S_j to mst[j&1]
@@ -750,7 +751,7 @@ static int minres_resident(tmop_ctx *c, const double *minv, double *R1, double *
             (void)hipEventRecord(c->tev[c->tev_used + 2], c->s);
             c->tev_used += 3;
         }
-        mr_lanczos2(n, j, sout, P1[j & 1], R1, R2, minv, znext, P2, c->s);
+        mr_lanczos2(n, nbg, j, sout, P1[j & 1], R1, R2, minv, znext, P2, c->s);
         std::swap(R1, R2);  // r1 <- r2, r2 <- hv
         J = j + 1;
         if (check_every > 0 && (j + 1) % check_every == 0 && j + 1 < max_its) {
@@ -762,7 +763,7 @@ static int minres_resident(tmop_ctx *c, const double *minv, double *R1, double *
     // the last update, then dx from the resident vectors (dx = 0 from the
     // start when nothing ran)
     if (J > 0)
-        mr_combine(n, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2,
+        mr_combine(n, nbg, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2,
                    c->mhist, c->bank, c->bank_stride, dx, c->s);
     // R1/R2 are scratch between calls; keep the pool's pointers as they were
     return J;
@@ -775,6 +776,7 @@ static int minres_three_term(tmop_ctx *c, const double *minv, double *const P1[2
 {
     const long n = c->ndof;
     const bool fp32 = c->precision == TMOP_MIXED;
+    const int nbg = mr_gather_grid(c->g);
     // R1: r1, overwritten in place by hv; R2: r2; ZC: z_{j-1} (the element
     // kernel's input, v_j = z_{j-1} / beta_j); ZP: z_{j-2}, then z_j
     double *R1 = c->sv[SV_R1], *R2 = c->sv[SV_R2], *ZC = c->sv[SV_Y], *ZP = c->sv[SV_V];
@@ -795,7 +797,7 @@ static int minres_three_term(tmop_ctx *c, const double *minv, double *const P1[2
             c->tev_used += 3;
         }
         // z_j into ZP (z_{j-2} is dead after the update above)
-        mr_lanczos2(n, j, sout, P1[j & 1], R1, R2, minv, ZP, P2, c->s);
+        mr_lanczos2(n, nbg, j, sout, P1[j & 1], R1, R2, minv, ZP, P2, c->s);
         std::swap(R1, R2);  // r1 <- r2, r2 <- hv
         std::swap(ZP, ZC);  // z_{j-1}, z_j
         if (j >= 1) {
@@ -813,8 +815,8 @@ static int minres_three_term(tmop_ctx *c, const double *minv, double *const P1[2
     }
     // the update of the last iteration run
     if (J > 0) {
-        mr_finish(n, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2, ZP, W2,
-                  W, W1, dx, c->s);
+        mr_finish(n, nbg, J - 1, c->mst + ((J - 1) & 1), c->mst + (J & 1), P1[(J - 1) & 1], P2,
+                  ZP, W2, W, W1, dx, c->s);
         double *oW = W, *oW1 = W1, *oW2 = W2;
         W1 = oW2;
         W2 = oW;
@@ -842,8 +844,9 @@ static int minres_impl(tmop_ctx *c, const double *b, double *dx, int max_its, do
     CHK(ensure_solver(c));
     const long n = c->ndof;
     // part1 alternates between iterations (iteration j reads j-1's while writing its own)
-    double *const P1[2] = {c->part, c->part + 2048};
-    double *P2 = c->part + 1024;
+    // alpha partials (one per gather workgroup), double-buffered, then beta^2
+    double *const P1[2] = {c->part, c->part + MR_MAX_PARTIALS};
+    double *P2 = c->part + 2 * MR_MAX_PARTIALS;
     const double *minv = jacobi ? c->minv : nullptr;
     const bool resident = ensure_bank(c, max_its + 1);
     c->tev_used = 0;

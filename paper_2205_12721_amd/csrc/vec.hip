@@ -251,11 +251,9 @@ void launch_jacobi(long n, const double *d, const double *dmax, double *minv, hi
 // residual estimate drops below rtol*beta1 or the Lanczos vector vanishes).
 // ------------------------------------------------------------------------
 
-// Sum of part[0..nb) in every lane, without a barrier: each wave reads all
-// partials (lane l adds l, l+64, ... in that order, 16 loads in flight) and
-// reduces them by butterfly, which leaves the same bits in every lane, wave
-// and workgroup.  Loads the caller issued before stay in flight meanwhile.
-__device__ inline double sum_partials(const double *__restrict__ part, int nb)
+// Sum of part[0..nb) by one wave (lane l adds l, l+64, ... in that order,
+// 16 loads in flight, then a butterfly): the same bits in every workgroup.
+__device__ inline double wave_sum_partials(const double *__restrict__ part, int nb)
 {
     constexpr int RU = 16;
     const int l = threadIdx.x & 63;
@@ -271,6 +269,26 @@ __device__ inline double sum_partials(const double *__restrict__ part, int nb)
         for (int r = 0; r < RU; ++r) s += t[r];
     }
     return wave_sum(s);
+}
+
+// Sums of pa[0..na) (wave 0) and, when pb is given, pb[0..nb) (wave 1), to
+// every thread of the workgroup after one barrier.  Called at most once per
+// kernel, by every thread.
+__device__ inline void sum_partials(const double *__restrict__ pa, int na,
+                                    const double *__restrict__ pb, int nb, double &a, double &b)
+{
+    __shared__ double sh[2];
+    const int w = threadIdx.x >> 6;
+    if (w == 0) {
+        const double t = wave_sum_partials(pa, na);
+        if (threadIdx.x == 0) sh[0] = t;
+    } else if (w == 1 && pb) {
+        const double t = wave_sum_partials(pb, nb);
+        if (threadIdx.x == 64) sh[1] = t;
+    }
+    __syncthreads();
+    a = sh[0];
+    b = pb ? sh[1] : 0.0;
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_mr_init(long n, const double *__restrict__ b,
@@ -306,7 +324,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_start(long n, MinresState *st, do
                                                      double *__restrict__ w1,
                                                      double *__restrict__ w2)
 {
-    const double bb = sum_partials(part, nb);
+    double bb, unused;
+    sum_partials(part, nb, nullptr, 0, bb, unused);
     const double b1 = sqrt(fmax(bb, 0.0));
     const double s = b1 > 0.0 ? 1.0 / b1 : 0.0;
     for (long i = blockIdx.x * (long)VBLOCK + threadIdx.x; i < n; i += (long)gridDim.x * VBLOCK) {
@@ -398,21 +417,18 @@ template <int DIM, typename ET>
 __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
     Geom g, const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
     const ET *__restrict__ eV, int j, const MinresState *__restrict__ sin,
-    MinresState *__restrict__ sout, const double *__restrict__ p1prev,
-    const double *__restrict__ p2prev, int nb, const double *__restrict__ zp,
+    MinresState *__restrict__ sout, const double *__restrict__ p1prev, int nb1,
+    const double *__restrict__ p2prev, int nb2, const double *__restrict__ zp,
     const double *__restrict__ zc, const double *__restrict__ w1, const double *__restrict__ w2,
     double *__restrict__ wout, double *__restrict__ x, double *__restrict__ r1hv,
     double *__restrict__ part, MrHist *__restrict__ hist)
 {
     __shared__ double red[VBLOCK / 64];
-    const MinresState S = *sin;
-    const bool upd = j >= 1 && j - 1 <= S.stop;
     const int nstride = gridDim.x * VBLOCK;
     const int node0 = xcd_block(blockIdx.x, gridDim.x) * VBLOCK + threadIdx.x;
-    // The first node's loads go out before the partial sums.  The update of
-    // j-1 can end the gather only by setting stop = j-1, so j <= S.stop
-    // covers every gather that runs.
-    const bool pre = j <= S.stop && node0 < g.nx;
+    // The first node's loads go out before the state and the partial sums
+    // are read (they are in bounds whether or not the gather runs).
+    const bool pre = node0 < g.nx;
     double a0[DIM], z0[DIM], q0[DIM];
     bool f0[DIM];
     if (pre) {
@@ -424,11 +440,13 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
             q0[c] = j >= 1 ? r1hv[idx] : 0.0;
         }
     }
+    const MinresState S = *sin;
+    const bool upd = j >= 1 && j - 1 <= S.stop;
     MrUpd u{};
     u.o = S;
     if (upd) {
-        const double alpha = sum_partials(p1prev, nb);
-        const double bb = sum_partials(p2prev, nb);
+        double alpha, bb;
+        sum_partials(p1prev, nb1, p2prev, nb2, alpha, bb);
         u = mr_scalars(S, j - 1, alpha, bb);
     }
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;      // v_{j-1} = sp z_{j-2}
@@ -489,8 +507,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_gather_upd(
 __global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
                                                       const MinresState *__restrict__ sin,
                                                       MinresState *__restrict__ sout,
-                                                      const double *__restrict__ p1,
-                                                      const double *__restrict__ p2, int nb,
+                                                      const double *__restrict__ p1, int nb1,
+                                                      const double *__restrict__ p2, int nb2,
                                                       const double *__restrict__ zp,
                                                       const double *__restrict__ w1,
                                                       const double *__restrict__ w2,
@@ -502,8 +520,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
         if (blockIdx.x == 0 && threadIdx.x == 0) *sout = S;
         return;
     }
-    const double alpha = sum_partials(p1, nb);
-    const double bb = sum_partials(p2, nb);
+    double alpha, bb;
+    sum_partials(p1, nb1, p2, nb2, alpha, bb);
     const MrUpd u = mr_scalars(S, jm, alpha, bb);
     if (blockIdx.x == 0 && threadIdx.x == 0) *sout = u.o;
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
@@ -525,8 +543,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_finish(long n, int jm,
 __global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
                                                        const MinresState *__restrict__ sin,
                                                        MinresState *__restrict__ sout,
-                                                       const double *__restrict__ p1,
-                                                       const double *__restrict__ p2, int nb,
+                                                       const double *__restrict__ p1, int nb1,
+                                                       const double *__restrict__ p2, int nb2,
                                                        MrHist *__restrict__ hist,
                                                        const double *__restrict__ bank,
                                                        long stride, double *__restrict__ x)
@@ -541,8 +559,8 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
     MrUpd u{};
     u.o = S;
     if (last) {
-        const double alpha = sum_partials(p1, nb);
-        const double bb = sum_partials(p2, nb);
+        double alpha, bb;
+        sum_partials(p1, nb1, p2, nb2, alpha, bb);
         u = mr_scalars(S, jm, alpha, bb);
     }
     const double sp = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
@@ -594,16 +612,16 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_combine(long n, int jm,
 }
 
 __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresState *__restrict__ st,
-                                                  const double *__restrict__ part1, int nb,
+                                                  const double *__restrict__ part1, int nb1,
                                                   double *__restrict__ hv,
                                                   const double *__restrict__ r2,
                                                   const double *__restrict__ minv,
                                                   double *__restrict__ z,
                                                   double *__restrict__ part2)
 {
-    if (j > st->stop) return;
     __shared__ double red[VBLOCK / 64];
-    // this lane's first RU entries are loaded before alpha is summed
+    // this lane's first RU entries are loaded before the state is read and
+    // alpha summed
     constexpr int RU = 8;
     const long stride = (long)gridDim.x * VBLOCK;
     const long i0 = blockIdx.x * (long)VBLOCK + threadIdx.x;
@@ -615,7 +633,9 @@ __global__ __launch_bounds__(VBLOCK) void k_mr_l2(long n, int j, const MinresSta
         rr[k] = i < n ? r2[i] : 0.0;
         mr[k] = i < n && minv ? minv[i] : 1.0;
     }
-    const double alpha = sum_partials(part1, nb);
+    if (j > st->stop) return;
+    double alpha, unused;
+    sum_partials(part1, nb1, nullptr, 0, alpha, unused);
     const double c = alpha / st->beta;
     double s = 0.0;
 #pragma unroll
@@ -656,12 +676,13 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
                    const double *w1, const double *w2, double *wout, double *x, double *r1hv,
                    double *part, MrHist *hist, hipStream_t s)
 {
-    // the partials of every kernel of the iteration use the same block count
-    const int nb = reduce_blocks((long)g.dim * g.nx);
-#define TMOP_G(D, T)                                                                           \
-    hipLaunchKernelGGL((k_mr_gather_upd<D, T>), dim3(nb), dim3(VBLOCK), 0, s, g, csr_ptr,      \
-                       csr_ent, (const T *)eV, j, sin, sout, p1prev, p2prev, nb, zp, zc, w1, w2, \
-                       wout, x, r1hv, part, hist);
+    // one node per lane up to 2048 workgroups; its partials (alpha) number
+    // nb1, those of the vector kernels (beta^2) nb2
+    const int nb1 = mr_gather_grid(g), nb2 = reduce_blocks((long)g.dim * g.nx);
+#define TMOP_G(D, T)                                                                          \
+    hipLaunchKernelGGL((k_mr_gather_upd<D, T>), dim3(nb1), dim3(VBLOCK), 0, s, g, csr_ptr,    \
+                       csr_ent, (const T *)eV, j, sin, sout, p1prev, nb1, p2prev, nb2, zp, zc, \
+                       w1, w2, wout, x, r1hv, part, hist);
     if (g.dim == 3) {
         if (fp32) {
             TMOP_G(3, float)
@@ -678,30 +699,32 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
 #undef TMOP_G
 }
 
-void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, double *hv,
+int mr_gather_grid(const Geom &g) { return vgrid((long)g.nx, 2048); }
+
+void mr_lanczos2(long n, int nb1, int j, const MinresState *st, const double *part1, double *hv,
                  const double *r2, const double *minv, double *z, double *part2, hipStream_t s)
 {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mr_l2, dim3(nb), dim3(VBLOCK), 0, s, n, j, st, part1, nb, hv, r2, minv, z,
-                       part2);
+    hipLaunchKernelGGL(k_mr_l2, dim3(nb), dim3(VBLOCK), 0, s, n, j, st, part1, nb1, hv, r2, minv,
+                       z, part2);
 }
 
-void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
-               const double *p2, const double *zp, const double *w1, const double *w2,
-               double *wout, double *x, hipStream_t s)
+void mr_finish(long n, int nb1, int jm, const MinresState *sin, MinresState *sout,
+               const double *p1, const double *p2, const double *zp, const double *w1,
+               const double *w2, double *wout, double *x, hipStream_t s)
 {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mr_finish, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, p2, nb, zp,
-                       w1, w2, wout, x);
+    hipLaunchKernelGGL(k_mr_finish, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, nb1, p2,
+                       nb, zp, w1, w2, wout, x);
 }
 
-void mr_combine(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
-                const double *p2, MrHist *hist, const double *bank, long stride, double *x,
-                hipStream_t s)
+void mr_combine(long n, int nb1, int jm, const MinresState *sin, MinresState *sout,
+                const double *p1, const double *p2, MrHist *hist, const double *bank, long stride,
+                double *x, hipStream_t s)
 {
     const int nb = reduce_blocks(n);
-    hipLaunchKernelGGL(k_mr_combine, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, p2, nb,
-                       hist, bank, stride, x);
+    hipLaunchKernelGGL(k_mr_combine, dim3(nb), dim3(VBLOCK), 0, s, n, jm, sin, sout, p1, nb1, p2,
+                       nb, hist, bank, stride, x);
 }
 
 }  // namespace tmop

@@ -48,13 +48,17 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
                    const double *p1prev, const double *p2prev, const double *zp, const double *zc,
                    const double *w1, const double *w2, double *wout, double *x, double *r1hv,
                    double *part, MrHist *hist, hipStream_t s);
-void mr_lanczos2(long n, int j, const MinresState *st, const double *part1, double *hv,
+// Workgroups of mr_gather_upd, i.e. the count of its partials (nb1 below);
+// at most MR_MAX_PARTIALS.
+int mr_gather_grid(const Geom &g);
+constexpr int MR_MAX_PARTIALS = 2048;
+void mr_lanczos2(long n, int nb1, int j, const MinresState *st, const double *part1, double *hv,
                  const double *r2, const double *minv, double *z, double *part2, hipStream_t s);
-void mr_finish(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
-               const double *p2, const double *zp, const double *w1, const double *w2,
-               double *wout, double *x, hipStream_t s);
-void mr_combine(long n, int jm, const MinresState *sin, MinresState *sout, const double *p1,
-                const double *p2, MrHist *hist, const double *bank, long stride, double *x,
-                hipStream_t s);
+void mr_finish(long n, int nb1, int jm, const MinresState *sin, MinresState *sout,
+               const double *p1, const double *p2, const double *zp, const double *w1,
+               const double *w2, double *wout, double *x, hipStream_t s);
+void mr_combine(long n, int nb1, int jm, const MinresState *sin, MinresState *sout,
+                const double *p1, const double *p2, MrHist *hist, const double *bank, long stride,
+                double *x, hipStream_t s);
 
 }  // namespace tmop
