@@ -290,6 +290,17 @@ int tmop_pool_info(tmop_pool *pool, size_t *used_bytes, size_t *budget_bytes, in
 /* Enable (default) or disable HIP-graph replay of the MINRES iterations. */
 int tmop_pool_set_graph(tmop_pool *pool, int enable);
 
+/* Enable or disable (default) resident MINRES Lanczos vectors for solves
+ * admitted later (as tmop_set_lanczos_bank_limit for a context): an admitted
+ * solve whose region plus (max_minres + 1) N_dof vectors (each rounded up to
+ * 256 bytes) and 16 KB of scalars fits the free budget keeps them and forms
+ * dx once per MINRES call; otherwise it takes the three-term update.
+ * tmop_pool_request_bytes reports the size without them, so a budget sized
+ * from it may admit fewer solves at once with this enabled.
+ * tmop_batch_solve enables it and sizes its pool to hold them.  Same
+ * iterates up to rounding. */
+int tmop_pool_set_lanczos_bank(tmop_pool *pool, int enable);
+
 /* Autotuner of the pool: for every kernel class with resident meshes, time
  * the batched Hessian action of each tile shape (as tmop_autotune) over
  * `reps` launches on the pool's stream, keep the fastest for the class and

@@ -279,12 +279,17 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
     double *__restrict__ v = S.vec[BZ0], *__restrict__ x = S.vec[BDX];
     double *__restrict__ w = S.vec[BW];
     double *__restrict__ w1 = S.vec[BW1], *__restrict__ w2 = S.vec[BW2];
+    double *__restrict__ zb = S.bank;  // bank vector 0 = z_{-1}
     for (int i = i0; i < i1; i += VB) {
         v[i] = y[i];
         x[i] = 0.0;
-        w[i] = 0.0;
-        w1[i] = 0.0;
-        w2[i] = 0.0;
+        if (zb) {
+            zb[i] = y[i];
+        } else {
+            w[i] = 0.0;
+            w1[i] = 0.0;
+            w2[i] = 0.0;
+        }
     }
     if (t.start == 0 && threadIdx.x == 0) {
         BState o;
@@ -349,7 +354,8 @@ __device__ inline BUpd bs_update(const BState &si, double alpha, double bb)
 // then, while the slot runs, hv = G^T eV / beta_j (fixed DoFs: v_j)
 // - (beta_j/beta_{j-1}) r1 in place of r1 and the partials of <v_j, hv>.
 // Every iterating slot writes its state (carried forward when nothing runs)
-// and its run flag.
+// and its run flag.  A slot with resident Lanczos vectors records the
+// update's scalars instead of applying it (kv_mr_finish forms dx).
 template <int DIM, typename ET>
 __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     const VTile *__restrict__ vt, const SlotDev *__restrict__ slots, const int *__restrict__ gate,
@@ -371,14 +377,24 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     }
     u.o.first = 0;
     const bool gat = !bs_skip(u.o);
+    const bool res = S.bank != nullptr;
+    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
     if (t.start == 0 && threadIdx.x == 0) {
         st[2 * t.slot + par] = u.o;
         run[t.slot] = gat ? 1 : 0;
+        if (upd && res) {
+            double *h = S.hist + 8 * sp.j;
+            h[0] = u.ig;
+            h[1] = u.oldeps;
+            h[2] = u.delta;
+            h[3] = u.phi;
+            h[4] = sprev;
+        }
     }
-    if (!upd && !gat) return;
+    const bool vupd = upd && !res;
+    if (!vupd && !gat) return;
     const Geom &g = S.g;
     const ET *__restrict__ eV = (const ET *)S.eV;
-    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
     const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;
     const double cr = u.o.j >= 1 ? u.o.beta / u.o.oldb : 0.0;
     const double *__restrict__ zc = S.vec[vzc], *__restrict__ zp = S.vec[vzp];
@@ -387,7 +403,7 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     double *__restrict__ wo = S.vec[vwout];
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
-        if (upd) {
+        if (vupd) {
             const double wn = (sprev * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
             wo[i] = wn;
             x[i] += u.phi * wn;
@@ -429,12 +445,15 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
     const bool useM = jac[t.slot] != 0;
     const double *__restrict__ m = S.vec[BMINV], *__restrict__ r2 = S.vec[vr2];
     double *__restrict__ hv = S.vec[vhv], *__restrict__ z = S.vec[vz];
+    // z_j also to bank vector j + 1 (j < maxit here, and the bank holds maxit + 1)
+    double *__restrict__ zb = S.bank ? S.bank + (long)(s.j + 1) * S.bstride : nullptr;
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
         const double h = hv[i] - c * r2[i];
         hv[i] = h;
         const double zi = useM ? m[i] * h : h;
         z[i] = zi;
+        if (zb) zb[i] = zi;
         acc += h * zi;
     }
     acc = block_sum(acc, red);
@@ -444,6 +463,9 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
 // The deferred update of the last iteration of every slot still running
 // after the lockstep loop (state st[par] -> st[par^1]); every slot's run flag
 // is cleared (the element kernels of later MINRES calls are gated by it).
+// A slot with resident Lanczos vectors then forms dx = sum_m c_m z_m from
+// the recorded scalars: lane m runs the three-term w recurrence on the m-th
+// coefficients (as k_mr_combine), every tile of the slot alike.
 __global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
                                                    const SlotDev *__restrict__ slots,
                                                    const int *__restrict__ gate,
@@ -456,18 +478,69 @@ __global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
 {
     VT_PROLOGUE
     __shared__ double red[VB / 64];
+    static_assert(MR_MAX_BASIS <= VB, "one lane per coefficient");
+    __shared__ double hig[MR_MAX_BASIS], hoe[MR_MAX_BASIS], hde[MR_MAX_BASIS],
+        hph[MR_MAX_BASIS], coef[MR_MAX_BASIS];
     const BState sp = st[2 * t.slot + par];
     if (t.start == 0 && threadIdx.x == 0) run[t.slot] = 0;
-    if (sp.first || bs_skip(sp)) {
+    const bool res = S.bank != nullptr;
+    const bool last = !sp.first && !bs_skip(sp);
+    if (!last) {
         if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = sp;
+        if (!res || sp.first) return;
+    }
+    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
+    BUpd u{};
+    u.o = sp;
+    if (last) {
+        const SlotRange r = rg[t.slot];
+        const double alpha = seg_sum(p1, r.vbegin, r.vcount, red);
+        const double bb = seg_sum(p2, r.vbegin, r.vcount, red);
+        u = bs_update(sp, alpha, bb);
+        if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = u.o;
+    }
+    if (res) {
+        // updates 0..K-1 taken (the last one here when `last`)
+        const int K = last ? sp.j + 1 : sp.j;
+        const int tm = threadIdx.x;
+        double svt = 0.0;
+        if (tm < K) {
+            if (last && tm == sp.j) {
+                hig[tm] = u.ig;
+                hoe[tm] = u.oldeps;
+                hde[tm] = u.delta;
+                hph[tm] = u.phi;
+                svt = sprev;
+            } else {
+                const double *h = S.hist + 8 * tm;
+                hig[tm] = h[0];
+                hoe[tm] = h[1];
+                hde[tm] = h[2];
+                hph[tm] = h[3];
+                svt = h[4];
+            }
+        }
+        __syncthreads();
+        if (tm < K) {
+            double a2 = 0.0, a1 = 0.0, cf = 0.0;
+            for (int m = tm; m < K; ++m) {
+                const double wn = ((m == tm ? 1.0 : 0.0) - hoe[m] * a2 - hde[m] * a1) * hig[m];
+                cf += hph[m] * wn;
+                a2 = a1;
+                a1 = wn;
+            }
+            coef[tm] = cf * svt;
+        }
+        __syncthreads();
+        const double *__restrict__ zb = S.bank;
+        double *__restrict__ x = S.vec[BDX];
+        for (int i = i0; i < i1; i += VB) {
+            double acc = 0.0;
+            for (int m = 0; m < K; ++m) acc += coef[m] * zb[(long)m * S.bstride + i];
+            x[i] = acc;
+        }
         return;
     }
-    const SlotRange r = rg[t.slot];
-    const double alpha = seg_sum(p1, r.vbegin, r.vcount, red);
-    const double bb = seg_sum(p2, r.vbegin, r.vcount, red);
-    const BUpd u = bs_update(sp, alpha, bb);
-    if (t.start == 0 && threadIdx.x == 0) st[2 * t.slot + (par ^ 1)] = u.o;
-    const double sprev = sp.beta > 0.0 ? 1.0 / sp.beta : 0.0;
     const double *__restrict__ zp = S.vec[vzp];
     const double *__restrict__ w1 = S.vec[vw1], *__restrict__ w2 = S.vec[vw2];
     double *__restrict__ x = S.vec[BDX], *__restrict__ wo = S.vec[vwout];
@@ -617,6 +690,16 @@ static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH 
 }
 
 
+// Bytes of a slot's resident Lanczos vectors (max_minres + 1 of them) and
+// per-update scalars; 0 when MINRES may run more updates than one
+// combination takes.
+static size_t bank_bytes_of(int ndof, int max_minres)
+{
+    const int kb = max_minres + 1;
+    if (kb < 1 || kb > MR_MAX_BASIS) return 0;
+    return (size_t)kb * up256((size_t)ndof * 8) + up256((size_t)MR_MAX_BASIS * 64);
+}
+
 struct tmop_pool {
     hipStream_t s = nullptr;
     size_t budget = 0, used = 0;
@@ -646,6 +729,9 @@ struct tmop_pool {
     int vt_range[4][2] = {};  // [dim3 fp64, dim3 mixed, dim2 fp64, dim2 mixed] -> [begin, count]
     int epart = 0;            // element partials (3 planes per class)
     bool dirty = true;
+    // resident MINRES Lanczos vectors for slots whose region fits the budget
+    // (opt-in: such a slot takes more of the budget)
+    bool use_bank = false;
     // graph of six MINRES iterations
     bool use_graph = true;
     bool graph_ok = false;
@@ -1248,8 +1334,19 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
             break;
         }
     size_t off = 0;
-    if (si < 0 || !pool_alloc_region(P, s.bytes, &off))
-        return pfail(TMOP_ERR_BUSY, "pool full (slots or HBM budget); retry after a release");
+    // with room, the slot also keeps its max_minres + 1 Lanczos vectors and
+    // the per-update scalars (else the three-term update)
+    const size_t base_bytes = s.bytes;
+    const int kb = sp->max_minres + 1;
+    size_t bank_bytes = P->use_bank ? bank_bytes_of(s.ndof, sp->max_minres) : 0;
+    if (si >= 0 && bank_bytes && base_bytes + bank_bytes <= P->budget &&
+        pool_alloc_region(P, base_bytes + bank_bytes, &off)) {
+        s.bytes = base_bytes + bank_bytes;
+    } else {
+        bank_bytes = 0;
+        if (si < 0 || !pool_alloc_region(P, s.bytes, &off))
+            return pfail(TMOP_ERR_BUSY, "pool full (slots or HBM budget); retry after a release");
+    }
     Tables tb;
     Target tg;
     if (internal_tables(s.p, s.nq, &tb) != TMOP_OK ||
@@ -1289,6 +1386,16 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     s.dev.H = base + o;
     o += up256((size_t)s.ne * qdata_stride(s.S, s.nqe, s.prec ? 4 : 8) * (s.prec ? 4 : 8));
     s.dev.eV = base + o;
+    o += up256((size_t)s.ne * s.dim * s.np * 8);
+    s.dev.bank = nullptr;
+    s.dev.hist = nullptr;
+    s.dev.bstride = 0;
+    if (bank_bytes) {
+        s.dev.bstride = (long)(up256((size_t)s.ndof * 8) / 8);
+        s.dev.bank = (double *)(base + o);
+        o += (size_t)kb * up256((size_t)s.ndof * 8);
+        s.dev.hist = (double *)(base + o);
+    }
     // copy the caller's nodes after the caller's stream has produced them
     hipEvent_t ev;
     PHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1426,6 +1533,13 @@ extern "C" int tmop_pool_autotune(tmop_pool *P, int reps)
     return TMOP_OK;
 }
 
+extern "C" int tmop_pool_set_lanczos_bank(tmop_pool *P, int enable)
+{
+    if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
+    P->use_bank = enable != 0;
+    return TMOP_OK;
+}
+
 extern "C" int tmop_pool_set_graph(tmop_pool *P, int enable)
 {
     if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
@@ -1442,14 +1556,18 @@ extern "C" int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const t
 {
     if (count <= 0 || !meshes || !prms || !x_devs || !sps || !reps)
         return pfail(TMOP_ERR_INVALID_ARG, "bad batch arguments");
+    // every mesh's region with its resident Lanczos vectors
     size_t total = 0;
     for (int k = 0; k < count; ++k) {
-        size_t b = 0;
-        PCHK(tmop_pool_request_bytes(meshes + k, prms + k, &b));
-        total += b;
+        SlotH s;
+        std::string why;
+        const int r = request_sizes(meshes + k, prms + k, s, why);
+        if (r != TMOP_OK) return pfail(r, why);
+        total += s.bytes + bank_bytes_of(s.ndof, sps[k].max_minres);
     }
     tmop_pool *P = nullptr;
     PCHK(tmop_pool_create(&P, total, count, stream));
+    P->use_bank = true;
     std::vector<int> slot(count, -1);
     int r = TMOP_OK;
     for (int k = 0; k < count && r == TMOP_OK; ++k)

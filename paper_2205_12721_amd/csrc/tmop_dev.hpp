@@ -163,6 +163,12 @@ struct SlotDev {
     double *vec[NVEC];
     void *H;
     void *eV;
+    // resident MINRES Lanczos vectors (bank vector m at bank + m * bstride)
+    // and the scalars of each update (8 doubles per update); null when the
+    // slot takes the three-term update
+    double *bank;
+    double *hist;
+    long bstride;
 };
 
 // Symmetric packing of a d^2 x d^2 tensor: entry (r, s), r <= s, row-major

@@ -41,10 +41,10 @@ def _percentiles(lat):
 
 
 def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="compact",
-          rel_grad_tol=1e-8, max_newton=50, max_minres=50, graph=True):
+          rel_grad_tol=1e-8, max_newton=50, max_minres=50, graph=True, lanczos_bank=False):
     """Run the stream through a pool; returns a summary dict and per-request records."""
     import torch
-    pool = Pool(hbm_budget, max_slots, graph=graph)
+    pool = Pool(hbm_budget, max_slots, graph=graph, lanczos_bank=lanczos_bank)
     sp = solve_params(rel_grad_tol=rel_grad_tol, max_newton=max_newton, max_minres=max_minres)
     n = len(reqs)
     pending = []            # arrived, not admitted (FIFO)

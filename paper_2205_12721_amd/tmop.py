@@ -97,6 +97,7 @@ SIGNATURES = {
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
     "tmop_set_lanczos_bank_limit": [_P, ctypes.c_size_t],
+    "tmop_pool_set_lanczos_bank": [_P, ctypes.c_int],
     "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
     "tmop_autotune": [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "tmop_tile_epb": [_P, ctypes.POINTER(ctypes.c_int)],
@@ -405,7 +406,7 @@ def request_bytes(md, prm):
 class Pool:
     """Many solves advanced together (see tmop_pool_* in include/tmop.h)."""
 
-    def __init__(self, hbm_budget, max_slots, graph=True):
+    def __init__(self, hbm_budget, max_slots, graph=True, lanczos_bank=False):
         import torch
         self._torch = torch
         h = ctypes.c_void_p()
@@ -414,6 +415,8 @@ class Pool:
         self._keep = {}
         if not graph:
             _pcheck(lib().tmop_pool_set_graph(h, 0))
+        if lanczos_bank:
+            _pcheck(lib().tmop_pool_set_lanczos_bank(h, 1))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -58,11 +58,13 @@ def test_batch_matches_single_solves():
         assert abs(rb["F"] - ra["F"]) <= 1e-10 * ra["F0"]
 
 
-def _pool_run(cases, graph=True, budget=None, extra=None):
+def _pool_run(cases, graph=True, budget=None, extra=None, bank=False):
     from paper_2205_12721_amd.tmop import Pool, request_bytes, solve_params
     reqs = [_req(c) for c in cases]
     total = sum(request_bytes(*r) for r in reqs)
-    pool = Pool(budget or total, len(cases), graph=graph)
+    if bank and budget is None:
+        budget = 8 * total  # room for every slot's Lanczos vectors
+    pool = Pool(budget or total, len(cases), graph=graph, lanczos_bank=bank)
     xs = [to_dev(_mesh(c)[1]) if extra is None or k not in extra else to_dev(extra[k])
           for k, c in enumerate(cases)]
     slots = [pool.admit(md, prm, solve_params(rel_grad_tol=1e-10), x) for (md, prm), x in zip(reqs, xs)]
@@ -88,6 +90,29 @@ def test_pool_alone_equals_mix_bitwise():
     assert alone[1]["minres_its_total"] == mix[1][1]["minres_its_total"]
     alone2 = _pool_run([MIX[2]])[0]
     assert np.array_equal(alone2[0], mix[3][0])
+
+
+def test_pool_lanczos_bank():
+    """Slots with resident Lanczos vectors: bitwise alone vs in a mix and with vs without
+    graph replay; the same optimum as the three-term update (nodes within 1e-9, same
+    Newton and MINRES counts).  A budget with no room for the vectors admits the request
+    with the three-term update, bitwise equal to a pool without them."""
+    alone = _pool_run([MIX[0]], bank=True)[0]
+    alone_nog = _pool_run([MIX[0]], graph=False, bank=True)[0]
+    mix = _pool_run([MIX[3], MIX[0], MIX[1], MIX[2]], bank=True)
+    plain = _pool_run([MIX[3], MIX[0], MIX[1], MIX[2]])
+    assert np.array_equal(alone[0], mix[1][0])
+    assert np.array_equal(alone[0], alone_nog[0])
+    for (xb, rb), (xp, rp) in zip(mix, plain):
+        log("bank", rb["newton_its"], rb["minres_its_total"], "three-term", rp["newton_its"],
+            rp["minres_its_total"], "x rel %.2e" % rel(xb, xp))
+        assert rb["status"] == 0 and rp["status"] == 0
+        assert rb["newton_its"] == rp["newton_its"]
+        assert rb["minres_its_total"] == rp["minres_its_total"]
+        assert rel(xb, xp) <= TOLX
+    from paper_2205_12721_amd.tmop import request_bytes
+    tight = _pool_run([MIX[0]], bank=True, budget=request_bytes(*_req(MIX[0])))[0]
+    assert np.array_equal(tight[0], plain[1][0])
 
 
 def test_tangled_request_fails_alone():
