@@ -81,3 +81,24 @@ def test_config3_sampled_parity(name, storage):
     log(name, "mixed hvp rel err (sampled) %.3e" % err)
     assert err <= 2e-6
     ctx.close()
+
+
+def test_config2_minres_full():
+    """24^3 Q3, FP64 tensor storage: 20 Jacobi-MINRES iterations on H_c dx = g (the
+    bench's Newton step; the Lanczos vectors resident) against the oracle's MINRES on
+    the same operator, in full."""
+    from oracle import solver
+    from paper_2205_12721_amd.tmop import Context
+    c, pb, x, _ = _config("c2")
+    g = pb.gradient(x)
+    minv = solver.jacobi_inverse(pb.diag(x), pb.ess)
+    xo, ito, _ = solver.minres(lambda w: pb.hvp(x, w), g, lambda r: minv * r, rtol=1e-12,
+                               maxit=20)
+    ctx = Context(3, c["n"], c["p"], c["nq"])
+    ctx.hessian_setup(to_dev(x))
+    dx, itg = ctx.minres(to_dev(g), max_its=20, rtol=1e-12, jacobi=True)
+    e = rel(to_host(dx), xo)
+    log("c2 minres its oracle", ito, "gpu", itg, "rel %.3e" % e)
+    assert itg == ito == 20
+    assert e <= 1e-9
+    ctx.close()
