@@ -240,14 +240,35 @@ def cpu_baseline(cfg, x, v, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    cores = oracle.num_threads()
+    # the same oracle on one thread, two actions
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    for _ in range(2):
+        pb.hvp(x, v)
+    t1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
     return {
         "value": round(pb.ndof * reps / el / 1e9, 6),
         "unit": "GDoF/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": "%d Hessian actions of the FP64 oracle (direct, not sum-factorized) on the "
                   "same mesh and vector, %.1f s" % (reps, el),
+        "one_thread_value": round(pb.ndof * 2 / t1 / 1e9, 6),
+        "cpu_model": cpu_model(),
     }, y
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def precision_leg(cfg, x0, v_host, y_oracle, max_newton=100):
