@@ -36,7 +36,11 @@ namespace tmop {
 enum {
     BX, BXT, BG, BGT, BDX, BR1, BR2, BZ1, BZ0, BW, BW1, BW2, BMINV, BDIAG, BY, BNV
 };
-static_assert(BNV <= NVEC, "too many vectors per slot");
+// not allocated: the MINRES input of the element kernels (the current
+// preconditioned Lanczos vector, in the bank or in BZ0/BZ1), set on the
+// device by kv_mr_start and kv_mr_l2
+constexpr int BZIN = BNV;
+static_assert(BNV < NVEC, "too many vectors per slot");
 
 constexpr int VB = 256;      // threads per vector block
 constexpr int VCH = 8 * VB;  // DoFs per vector tile
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
                                                   const double *__restrict__ part,
                                                   const int *__restrict__ maxit, double rtol,
                                                   BState *__restrict__ st,
-                                                  int *__restrict__ run)
+                                                  int *__restrict__ run, SlotDev *wslots)
 {
     VT_PROLOGUE
     __shared__ double red[VB / 64];
@@ -279,13 +283,13 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
     double *__restrict__ v = S.vec[BZ0], *__restrict__ x = S.vec[BDX];
     double *__restrict__ w = S.vec[BW];
     double *__restrict__ w1 = S.vec[BW1], *__restrict__ w2 = S.vec[BW2];
-    double *__restrict__ zb = S.bank;  // bank vector 0 = z_{-1}
+    double *__restrict__ zb = S.bank;  // bank vector 0 = z_{-1}, else BZ0
     for (int i = i0; i < i1; i += VB) {
-        v[i] = y[i];
         x[i] = 0.0;
         if (zb) {
             zb[i] = y[i];
         } else {
+            v[i] = y[i];
             w[i] = 0.0;
             w1[i] = 0.0;
             w2[i] = 0.0;
@@ -311,6 +315,7 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
         st[2 * t.slot] = o;
         st[2 * t.slot + 1] = o;
         run[t.slot] = bs_skip(o) ? 0 : 1;
+        wslots[t.slot].vec[BZIN] = zb ? zb : v;
     }
 }
 
@@ -397,7 +402,9 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     const ET *__restrict__ eV = (const ET *)S.eV;
     const double sc = u.o.beta > 0.0 ? 1.0 / u.o.beta : 0.0;
     const double cr = u.o.j >= 1 ? u.o.beta / u.o.oldb : 0.0;
-    const double *__restrict__ zc = S.vec[vzc], *__restrict__ zp = S.vec[vzp];
+    // the element kernel's input, z_{j-1} (vzc names its buffer when the
+    // slot has no bank)
+    const double *__restrict__ zc = S.vec[BZIN], *__restrict__ zp = S.vec[vzp];
     const double *__restrict__ w1 = S.vec[vw1], *__restrict__ w2 = S.vec[vw2];
     double *__restrict__ r1 = S.vec[vr1], *__restrict__ x = S.vec[BDX];
     double *__restrict__ wo = S.vec[vwout];
@@ -433,7 +440,8 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
                                                const int *__restrict__ jac,
                                                const BState *__restrict__ st, int par,
                                                const double *__restrict__ part1, int vhv, int vr2,
-                                               int vz, double *__restrict__ part2)
+                                               int vz, double *__restrict__ part2,
+                                               SlotDev *wslots)
 {
     VT_PROLOGUE
     const BState &s = st[2 * t.slot + par];
@@ -444,16 +452,17 @@ __global__ __launch_bounds__(VB) void kv_mr_l2(const VTile *__restrict__ vt,
     const double c = alpha / s.beta;
     const bool useM = jac[t.slot] != 0;
     const double *__restrict__ m = S.vec[BMINV], *__restrict__ r2 = S.vec[vr2];
-    double *__restrict__ hv = S.vec[vhv], *__restrict__ z = S.vec[vz];
-    // z_j also to bank vector j + 1 (j < maxit here, and the bank holds maxit + 1)
-    double *__restrict__ zb = S.bank ? S.bank + (long)(s.j + 1) * S.bstride : nullptr;
+    // z_j to bank vector j + 1 (j < maxit here, and the bank holds maxit + 1),
+    // else to the buffer vz; it is the next element kernel's input
+    double *__restrict__ z = S.bank ? S.bank + (long)(s.j + 1) * S.bstride : S.vec[vz];
+    double *__restrict__ hv = S.vec[vhv];
+    if (t.start == 0 && threadIdx.x == 0) wslots[t.slot].vec[BZIN] = z;
     double acc = 0.0;
     for (int i = i0; i < i1; i += VB) {
         const double h = hv[i] - c * r2[i];
         hv[i] = h;
         const double zi = useM ? m[i] * h : h;
         z[i] = zi;
-        if (zb) zb[i] = zi;
         acc += h * zi;
     }
     acc = block_sum(acc, red);
@@ -534,9 +543,20 @@ __global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
         __syncthreads();
         const double *__restrict__ zb = S.bank;
         double *__restrict__ x = S.vec[BDX];
+        const long bs = S.bstride;
         for (int i = i0; i < i1; i += VB) {
+            // four vectors' loads in flight per step, summed in the order of m
             double acc = 0.0;
-            for (int m = 0; m < K; ++m) acc += coef[m] * zb[(long)m * S.bstride + i];
+            int m = 0;
+            for (; m + 4 <= K; m += 4) {
+                const double z0 = zb[(long)m * bs + i], z1 = zb[(long)(m + 1) * bs + i];
+                const double z2 = zb[(long)(m + 2) * bs + i], z3 = zb[(long)(m + 3) * bs + i];
+                acc += coef[m] * z0;
+                acc += coef[m + 1] * z1;
+                acc += coef[m + 2] * z2;
+                acc += coef[m + 3] * z3;
+            }
+            for (; m < K; ++m) acc += coef[m] * zb[(long)m * bs + i];
             x[i] = acc;
         }
         return;
@@ -991,7 +1011,7 @@ static void minres_iter(tmop_pool *P, int k)
     const int par = k & 1;
     double *p1 = vpart1_at(P, par);
     const double *p1prev = vpart1_at(P, par ^ 1);
-    launch_elem(P, 3, P->d_run, zc);
+    launch_elem(P, 3, P->d_run, BZIN);
     for (int grp = 0; grp < 4; ++grp) {
         const int b = P->vt_range[grp][0], n = P->vt_range[grp][1];
         if (!n) continue;
@@ -1013,7 +1033,7 @@ static void minres_iter(tmop_pool *P, int k)
     }
     const int n = nvt_all(P);
     // hv -> r2 of the next position (in place in r1); z_j into zp
-    hipLaunchKernelGGL(kv_mr_l2, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_jac, P->d_st, par, p1, r1, r2, zp, vpart2(P));
+    hipLaunchKernelGGL(kv_mr_l2, dim3(n), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, P->d_jac, P->d_st, par, p1, r1, r2, zp, vpart2(P), P->d_slots);
 }
 
 static int run_minres(tmop_pool *P, int maxj)
@@ -1023,7 +1043,7 @@ static int run_minres(tmop_pool *P, int maxj)
     double rtol = 1e-12;
     for (auto &s : P->slots)
         if (s.used && s.phase == PH_ITER) rtol = s.sp.minres_rtol;
-    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, rtol, P->d_st, P->d_run);
+    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, rtol, P->d_st, P->d_run, P->d_slots);
     int j = 0;
     while (j < maxj) {
         if (P->use_graph && maxj - j >= 6) {
