@@ -115,6 +115,40 @@ def test_pool_lanczos_bank():
     assert np.array_equal(tight[0], plain[1][0])
 
 
+def test_pool_bank_and_three_term_slots_together():
+    """Two copies of one request in a pool whose budget holds the Lanczos vectors of only
+    the first: the first slot runs with them (its region is larger by exactly their
+    size), the second with the three-term update, in the same launches.  The second is
+    bitwise equal to a pool without vectors; the first reaches the same optimum with the
+    same iteration counts."""
+    from paper_2205_12721_amd.tmop import Pool, request_bytes, solve_params
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    ndof = 3 * 7 ** 3  # MIX[0]: 3x3x3 hexes of order 2
+    bank = 51 * up(8 * ndof) + up(256 * 64)  # max_minres 50 (the default) + 1 vectors
+    md, prm = _req(MIX[0])
+    base = request_bytes(md, prm)
+    x0 = _mesh(MIX[0])[1]
+    pool = Pool(2 * base + bank, 2, lanczos_bank=True)
+    xs = [to_dev(x0), to_dev(x0)]
+    slots = [pool.admit(md, prm, solve_params(rel_grad_tol=1e-10), x) for x in xs]
+    assert pool.info()["used"] == 2 * base + bank
+    while pool.step() > 0:
+        pass
+    both = []
+    for sl, x in zip(slots, xs):
+        done, rep = pool.poll(sl)
+        assert done
+        pool.result(sl, x)
+        both.append((to_host(x), rep))
+    pool.close()
+    plain = _pool_run([MIX[0], MIX[0]])
+    log("bank + three-term slots: x rel %.2e" % rel(both[0][0], plain[0][0]))
+    assert np.array_equal(both[1][0], plain[1][0])
+    assert both[0][1]["newton_its"] == plain[0][1]["newton_its"]
+    assert both[0][1]["minres_its_total"] == plain[0][1]["minres_its_total"]
+    assert rel(both[0][0], plain[0][0]) <= TOLX
+
+
 def test_tangled_request_fails_alone():
     from paper_2205_12721_amd.tmop import ERR_INVERTED
     c = MIX[0]
