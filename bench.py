@@ -34,15 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "1e9c466c372a7cde6c09a6535c5daf8527f1a1ec04d1e74c7b307667c4d3079a"
+_SHA_C2 = "51e2152862bb56a4180418879eb416b85e791b7bda4b85aac0bf3e895f4c4e1c"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 720989888, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 720835530, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366467950, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 366402918, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 246731636, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 246732089, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135277864, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135270218, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
