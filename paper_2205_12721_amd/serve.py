@@ -47,6 +47,9 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
     pool = Pool(hbm_budget, max_slots, graph=graph, lanczos_bank=lanczos_bank)
     sp = solve_params(rel_grad_tol=rel_grad_tol, max_newton=max_newton, max_minres=max_minres)
     n = len(reqs)
+    # every request's nodes are on the device when it arrives
+    xds = [torch.as_tensor(x).cuda() for x in xs_host]
+    torch.cuda.synchronize()
     pending = []            # arrived, not admitted (FIFO)
     resident = {}           # slot -> (request index, device tensor)
     rec = [None] * n
@@ -63,7 +66,7 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
             k = pending[0]
             r = reqs[k]
             md, prm = request(r["dim"], r["n"], r["p"], r["nq"], precision=precision, storage=storage)
-            xd = torch.as_tensor(xs_host[k]).cuda()
+            xd = xds[k]
             try:
                 slot = pool.admit(md, prm, sp, xd)
             except TmopError as e:
@@ -108,13 +111,15 @@ def sequential(reqs, xs_host, rel_grad_tol=1e-8, max_newton=50, max_minres=50):
     import torch
     n = len(reqs)
     rec = [None] * n
+    xds = [torch.as_tensor(x).cuda() for x in xs_host]
+    torch.cuda.synchronize()
     t0 = time.monotonic()
     for k, r in enumerate(reqs):
         now = time.monotonic() - t0
         if r["t_arrive"] > now:
             time.sleep(r["t_arrive"] - now)
         ctx = Context(r["dim"], r["n"], r["p"], r["nq"])
-        xd = torch.as_tensor(xs_host[k]).cuda()
+        xd = xds[k]
         rep = ctx.solve(xd, rel_grad_tol=rel_grad_tol, max_newton=max_newton, max_minres=max_minres)
         torch.cuda.synchronize()
         ctx.close()

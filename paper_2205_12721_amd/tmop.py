@@ -131,6 +131,12 @@ def lib():
     if _lib_handle is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libtmop_hip.so is not built; run python -m paper_2205_12721_amd.build")
+        # torch's GPU runtime comes up before the library's first HIP call:
+        # the binding hands torch tensors and streams to the library, and
+        # torch initialised after the library has failed to find the device
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         h = ctypes.CDLL(LIB_PATH)
         for name, args in SIGNATURES.items():
             f = getattr(h, name)
