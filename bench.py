@@ -466,8 +466,9 @@ def main():
     ap.add_argument("--no-kershaw", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md); use --gpus 1",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a mesh would shard by element slabs with one interface exchange per "
+              "action, independent meshes by HBM budget); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
