@@ -166,3 +166,26 @@ def test_minres_basis_modes_agree():
         assert i0 == 0 and not np.any(to_host(d0))
     a.close()
     b.close()
+
+
+def test_minres_basis_cap():
+    """At most 255 iterations keep the Lanczos vectors resident (one lane per coefficient
+    in the combination); max_its = 300 takes the three-term update, bitwise equal to a
+    context that never keeps them, and max_its = 255 the resident form, equal to rounding."""
+    from paper_2205_12721_amd.tmop import Context
+    pb, x = make_case(3, (2, 2, 2), 1, 3, seed=63)
+    g = to_dev(pb.gradient(x))
+    a = Context(3, (2, 2, 2), 1, 3)
+    b = Context(3, (2, 2, 2), 1, 3)
+    b.set_lanczos_bank_limit(0)
+    for ctx in (a, b):
+        ctx.hessian_setup(to_dev(x))
+    da, ia = a.minres(g, max_its=300, rtol=1e-14, jacobi=True)
+    db, ib = b.minres(g, max_its=300, rtol=1e-14, jacobi=True)
+    assert ia == ib and np.array_equal(to_host(da), to_host(db))
+    da, ia = a.minres(g, max_its=255, rtol=1e-14, jacobi=True)
+    db, ib = b.minres(g, max_its=255, rtol=1e-14, jacobi=True)
+    log("basis cap", ia, ib, rel(to_host(da), to_host(db)))
+    assert ia == ib and rel(to_host(da), to_host(db)) <= 1e-12
+    a.close()
+    b.close()
