@@ -251,7 +251,10 @@ int tmop_set_lanczos_bank_limit(tmop_ctx *ctx, size_t max_bytes);
 typedef struct tmop_pool tmop_pool;
 
 /* Create a pool with an arena of hbm_budget bytes and up to max_slots
- * concurrent solves.  Errors: INVALID_ARG, OOM. */
+ * concurrent solves.  The pool's work runs on hip_stream when it is not
+ * NULL (the caller keeps it alive until tmop_pool_destroy), else on a
+ * non-blocking stream the pool creates and destroys.  Errors: INVALID_ARG,
+ * OOM. */
 int tmop_pool_create(tmop_pool **out, size_t hbm_budget, int max_slots, void *hip_stream);
 int tmop_pool_destroy(tmop_pool *pool);
 
@@ -260,7 +263,10 @@ int tmop_pool_destroy(tmop_pool *pool);
 int tmop_pool_request_bytes(const tmop_mesh_desc *mesh, const tmop_params *prm, size_t *bytes);
 
 /* Admit one solve: copies the caller's device nodes x_dev (d*N_x doubles,
- * read after the work queued on src_stream) into the pool.  Returns the slot
+ * read after the work queued on src_stream) into the pool, and with
+ * ess_mode TMOP_ESS_MASK also the mask (d*N_x bytes, counted in the slot's
+ * region), so neither buffer is needed after the call.  Each solve keeps its
+ * own solve parameters (MINRES cap and tolerance included).  Returns the slot
  * index.  Errors: BUDGET (the request alone exceeds the budget), BUSY (no
  * free slot or no free arena region now: retry after a release),
  * UNSUPPORTED, INVALID_ARG.  Does not run any solver work. */
@@ -278,8 +284,34 @@ int tmop_pool_step(tmop_pool *pool, int *n_active);
  * since admission. */
 int tmop_pool_poll(tmop_pool *pool, int slot, int *done, tmop_solve_report *rep);
 
-/* Copy a slot's current nodes to the caller's device buffer (synchronises). */
+/* Copy a slot's current nodes to the caller's device buffer.  The copy runs
+ * on the pool's stream and has completed when the call returns, so x_dev
+ * may be used on any stream (dst_stream is not needed and may be NULL). */
 int tmop_pool_result(tmop_pool *pool, int slot, double *x_dev, void *dst_stream);
+
+/* Evaluate one slot's operators with the pool's own batched kernels (the
+ * launches of tmop_pool_step, gated to this slot), for checking a pooled
+ * solve against a plain evaluation; between steps only.
+ *   TMOP_EVAL_ENERGY:   F and min det A at in_dev = x (d*N_x doubles) to
+ *                       out_host[0..1]; TMOP_ERR_INVERTED (F = +inf) when
+ *                       min det <= 0 (Sec. 3.3, eq. D0_expression).
+ *   TMOP_EVAL_GRADIENT: g_c at in_dev = x to out_dev (Sec. 3.3, eq.
+ *                       eq_vm_pa_grad).
+ *   TMOP_EVAL_SETUP:    store the slot's quadrature data at in_dev = x
+ *                       (Sec. 3.4).
+ *   TMOP_EVAL_APPLY:    out_dev = H_c in_dev from the slot's last setup
+ *                       (Sec. 3.4, eq. eq_vm_pa_hess); FP32 element work for
+ *                       a mixed-precision slot.
+ *   TMOP_EVAL_DIAG:     out_dev = diagonal of H_c (fixed entries 1).
+ * Inputs are read after the work queued on `stream`; outputs are complete on
+ * return.  Overwrites only the slot's per-step scratch (trial nodes and
+ * gradient, MINRES work vectors, diagonal, quadrature data, element
+ * scratch), which the next tmop_pool_step recomputes.  Errors: INVALID_ARG,
+ * STATE (APPLY / DIAG before any setup of the slot), INVERTED. */
+enum { TMOP_EVAL_ENERGY = 0, TMOP_EVAL_GRADIENT = 1, TMOP_EVAL_SETUP = 2, TMOP_EVAL_APPLY = 3,
+       TMOP_EVAL_DIAG = 4 };
+int tmop_pool_evaluate(tmop_pool *pool, int slot, int what, const double *in_dev, double *out_dev,
+                       double *out_host, void *stream);
 
 /* Free a slot and its arena region. */
 int tmop_pool_release(tmop_pool *pool, int slot);

@@ -269,7 +269,8 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
                                                   const int *__restrict__ gate,
                                                   const SlotRange *__restrict__ rg,
                                                   const double *__restrict__ part,
-                                                  const int *__restrict__ maxit, double rtol,
+                                                  const int *__restrict__ maxit,
+                                                  const double *__restrict__ rtol,
                                                   BState *__restrict__ st,
                                                   int *__restrict__ run, SlotDev *wslots)
 {
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(VB) void kv_mr_start(const VTile *__restrict__ vt,
         o.phibar = b1;
         o.cs = -1.0;
         o.sn = 0.0;
-        o.rtol = rtol;
+        o.rtol = rtol[t.slot];
         o.j = 0;
         o.maxit = maxit[t.slot];
         o.stop = (b1 > 0.0 && bb >= 0.0) ? 0x7fffffff : -1;
@@ -648,6 +649,7 @@ struct SlotH {
     int status = TMOP_OK;
     double F = 0, F0 = 0, gn = 0, g0 = 0, alpha = 1.0;
     int newton_its = 0, minres_its = 0, halvings = 0;
+    bool h_ready = false;  // the slot's quadrature data holds a Hessian setup
     double t_start = 0, t_done = 0;
     int first_vt = 0, nvt = 0;
 };
@@ -706,6 +708,8 @@ static int request_sizes(const tmop_mesh_desc *m, const tmop_params *prm, SlotH 
     const size_t tb = s.prec ? 4 : 8;
     s.bytes = BNV * up256((size_t)s.ndof * 8) + up256((size_t)s.ne * qdata_stride(s.S, s.nqe, (int)tb) * tb) +
               up256((size_t)s.ne * d * s.np * 8);
+    // the pool keeps its own copy of a caller's mask of fixed DoFs
+    if (m->ess_mode == TMOP_ESS_MASK) s.bytes += up256((size_t)s.ndof);
     return TMOP_OK;
 }
 
@@ -722,6 +726,7 @@ static size_t bank_bytes_of(int ndof, int max_minres)
 
 struct tmop_pool {
     hipStream_t s = nullptr;
+    bool own_stream = false;  // the pool created s (else it is the caller's)
     size_t budget = 0, used = 0;
     int max_slots = 0;
     char *arena = nullptr;
@@ -738,8 +743,11 @@ struct tmop_pool {
     double *d_sc = nullptr;
     BState *d_st = nullptr;
     int *d_run = nullptr, *d_jac = nullptr, *d_maxit = nullptr;
-    int *d_gate[5] = {};
-    int *h_gate[5] = {};
+    double *d_rtol = nullptr, *h_rtol = nullptr;  // per-slot MINRES tolerance
+    // gates: 0 new slots, 1 iterating, 2 searching, 3 trial accepted so far,
+    // 4 host staging of the iteration caps, 5 tmop_pool_evaluate's one slot
+    int *d_gate[6] = {};
+    int *h_gate[6] = {};
     double *h_sc = nullptr;
     BState *h_st = nullptr;
     int *h_int = nullptr;
@@ -1040,10 +1048,8 @@ static int run_minres(tmop_pool *P, int maxj)
 {
     const int nv = nvt_all(P);
     hipLaunchKernelGGL(kv_mr_init, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_jac, vpart1(P));
-    double rtol = 1e-12;
-    for (auto &s : P->slots)
-        if (s.used && s.phase == PH_ITER) rtol = s.sp.minres_rtol;
-    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, rtol, P->d_st, P->d_run, P->d_slots);
+    // each slot's own iteration cap and tolerance (uploaded with the gates)
+    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, P->d_rtol, P->d_st, P->d_run, P->d_slots);
     int j = 0;
     while (j < maxj) {
         if (P->use_graph && maxj - j >= 6) {
@@ -1149,10 +1155,16 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
     if (nit) {
         PCHK(upload_gate(P, 1));
         PHIP(hipMemcpyAsync(P->d_jac, P->h_int, sizeof(int) * M, hipMemcpyHostToDevice, P->s));
-        for (int si = 0; si < M; ++si) P->h_gate[4][si] = P->slots[si].sp.max_minres;
+        for (int si = 0; si < M; ++si) {
+            P->h_gate[4][si] = P->slots[si].sp.max_minres;
+            P->h_rtol[si] = P->slots[si].sp.minres_rtol;
+        }
         PHIP(hipMemcpyAsync(P->d_maxit, P->h_gate[4], sizeof(int) * M, hipMemcpyHostToDevice, P->s));
+        PHIP(hipMemcpyAsync(P->d_rtol, P->h_rtol, sizeof(double) * M, hipMemcpyHostToDevice, P->s));
         const int *g1 = P->d_gate[1];
         launch_elem(P, 2, g1, BX);   // setup
+        for (int si = 0; si < M; ++si)
+            if (P->h_gate[1][si]) P->slots[si].h_ready = true;
         launch_elem(P, 4, g1, BX);   // diagonal
         launch_gather(P, g1, BDIAG, 1, BDIAG, false);
         const int nv = nvt_all(P);
@@ -1257,7 +1269,6 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
 
 extern "C" int tmop_pool_create(tmop_pool **out, size_t budget, int max_slots, void *stream)
 {
-    (void)stream;
     if (!out || budget == 0 || max_slots <= 0 || max_slots > 65536)
         return pfail(TMOP_ERR_INVALID_ARG, "bad pool arguments");
     *out = nullptr;
@@ -1265,7 +1276,13 @@ extern "C" int tmop_pool_create(tmop_pool **out, size_t budget, int max_slots, v
     P->budget = budget;
     P->max_slots = max_slots;
     P->slots.resize(max_slots);
-    hipError_t e = hipStreamCreateWithFlags(&P->s, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
+    if (stream) {
+        P->s = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreateWithFlags(&P->s, hipStreamNonBlocking);
+        P->own_stream = e == hipSuccess;
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&P->arena, budget);
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_slots, sizeof(SlotDev) * max_slots);
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_rg, sizeof(SlotRange) * max_slots);
@@ -1274,7 +1291,9 @@ extern "C" int tmop_pool_create(tmop_pool **out, size_t budget, int max_slots, v
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_run, sizeof(int) * max_slots);
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_jac, sizeof(int) * max_slots);
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_maxit, sizeof(int) * max_slots);
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_rtol, sizeof(double) * max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_rtol, sizeof(double) * max_slots, 0);
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
         e = hipMalloc((void **)&P->d_gate[k], sizeof(int) * max_slots);
         if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_gate[k], sizeof(int) * max_slots, 0);
     }
@@ -1312,14 +1331,16 @@ extern "C" int tmop_pool_destroy(tmop_pool *P)
     hipFree(P->d_run);
     hipFree(P->d_jac);
     hipFree(P->d_maxit);
-    for (int k = 0; k < 5; ++k) {
+    hipFree(P->d_rtol);
+    if (P->h_rtol) hipHostFree(P->h_rtol);
+    for (int k = 0; k < 6; ++k) {
         hipFree(P->d_gate[k]);
         if (P->h_gate[k]) hipHostFree(P->h_gate[k]);
     }
     if (P->h_sc) hipHostFree(P->h_sc);
     if (P->h_st) hipHostFree(P->h_st);
     if (P->h_int) hipHostFree(P->h_int);
-    if (P->s) hipStreamDestroy(P->s);
+    if (P->s && P->own_stream) hipStreamDestroy(P->s);
     delete P;
     return TMOP_OK;
 }
@@ -1392,7 +1413,7 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     set_divisors(g);
     g.e2n = nullptr;
     g.ess_mode = m->ess_mode;
-    g.ess = m->ess_mask;
+    g.ess = nullptr;  // a mask is copied into the slot's region below
     g.x0 = nullptr;  // pooled solves have no limiting term
     g.lim = 0.0;
     s.dev.tg = tg;
@@ -1407,6 +1428,12 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     o += up256((size_t)s.ne * qdata_stride(s.S, s.nqe, s.prec ? 4 : 8) * (s.prec ? 4 : 8));
     s.dev.eV = base + o;
     o += up256((size_t)s.ne * s.dim * s.np * 8);
+    uint8_t *mask = nullptr;
+    if (m->ess_mode == TMOP_ESS_MASK) {
+        mask = (uint8_t *)(base + o);
+        g.ess = mask;
+        o += up256((size_t)s.ndof);
+    }
     s.dev.bank = nullptr;
     s.dev.hist = nullptr;
     s.dev.bstride = 0;
@@ -1416,15 +1443,23 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
         o += (size_t)kb * up256((size_t)s.ndof * 8);
         s.dev.hist = (double *)(base + o);
     }
-    // copy the caller's nodes after the caller's stream has produced them
-    hipEvent_t ev;
-    PHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    PHIP(hipEventRecord(ev, (hipStream_t)src_stream));
-    PHIP(hipStreamWaitEvent(P->s, ev, 0));
-    PHIP(hipMemcpyAsync(s.dev.vec[BX], x_dev, sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s));
-    PHIP(hipMemcpyAsync(P->d_slots + si, &s.dev, sizeof(SlotDev), hipMemcpyHostToDevice, P->s));
-    PHIP(hipStreamSynchronize(P->s));
-    hipEventDestroy(ev);
+    // copy the caller's nodes (and mask) after the caller's stream has produced them
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)src_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(P->s, ev, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.dev.vec[BX], x_dev, sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s);
+    if (e == hipSuccess && mask)
+        e = hipMemcpyAsync(mask, m->ess_mask, (size_t)s.ndof, hipMemcpyDeviceToDevice, P->s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P->d_slots + si, &s.dev, sizeof(SlotDev), hipMemcpyHostToDevice, P->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->s);
+    if (ev) hipEventDestroy(ev);
+    if (e != hipSuccess) {
+        pool_free_region(P, off, s.bytes);
+        return pfail(TMOP_ERR_HIP, std::string("pool admission: ") + hipGetErrorString(e));
+    }
     P->slots[si] = s;
     P->used += s.bytes;
     P->dirty = true;
@@ -1467,6 +1502,79 @@ extern "C" int tmop_pool_result(tmop_pool *P, int slot, double *x_dev, void *dst
     PHIP(hipMemcpyAsync(x_dev, s.dev.vec[BX], sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s));
     PHIP(hipStreamSynchronize(P->s));
     (void)dst_stream;
+    return TMOP_OK;
+}
+
+extern "C" int tmop_pool_evaluate(tmop_pool *P, int slot, int what, const double *in_dev,
+                                  double *out_dev, double *out_host, void *stream)
+{
+    if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].used)
+        return pfail(TMOP_ERR_INVALID_ARG, "bad slot");
+    if (what < TMOP_EVAL_ENERGY || what > TMOP_EVAL_DIAG)
+        return pfail(TMOP_ERR_INVALID_ARG, "unknown evaluation");
+    SlotH &s = P->slots[slot];
+    const bool need_in = what != TMOP_EVAL_DIAG;
+    const bool need_out = what == TMOP_EVAL_GRADIENT || what == TMOP_EVAL_APPLY || what == TMOP_EVAL_DIAG;
+    if ((need_in && !in_dev) || (need_out && !out_dev) || (what == TMOP_EVAL_ENERGY && !out_host))
+        return pfail(TMOP_ERR_INVALID_ARG, "null argument");
+    if ((what == TMOP_EVAL_APPLY || what == TMOP_EVAL_DIAG) && !s.h_ready)
+        return pfail(TMOP_ERR_STATE, "no Hessian setup for this slot yet");
+    if (P->dirty) PCHK(pool_rebuild(P));
+    for (int k = 0; k < P->max_slots; ++k) P->h_gate[5][k] = k == slot ? 1 : 0;
+    PCHK(upload_gate(P, 5));
+    const int *ge = P->d_gate[5];
+    const size_t nb = sizeof(double) * (size_t)s.ndof;
+    // read the caller's input after the caller's stream has produced it
+    hipEvent_t ev;
+    PHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    PHIP(hipEventRecord(ev, (hipStream_t)stream));
+    PHIP(hipStreamWaitEvent(P->s, ev, 0));
+    hipEventDestroy(ev);
+    int status = TMOP_OK;
+    switch (what) {
+    case TMOP_EVAL_ENERGY: {
+        PHIP(hipMemcpyAsync(s.dev.vec[BXT], in_dev, nb, hipMemcpyDeviceToDevice, P->s));
+        energy_to_sc(P, ge, BXT);
+        PCHK(read_sc(P));
+        const double *sc = P->h_sc + slot * NSC;
+        const bool bad = sc[SC_BAD] > 0.0 || !(sc[SC_MD] > 0.0);
+        out_host[0] = bad ? INFINITY : sc[SC_F];
+        out_host[1] = sc[SC_MD];
+        if (bad) status = TMOP_ERR_INVERTED;
+        break;
+    }
+    case TMOP_EVAL_GRADIENT:
+        PHIP(hipMemcpyAsync(s.dev.vec[BXT], in_dev, nb, hipMemcpyDeviceToDevice, P->s));
+        gradient_to(P, ge, BXT, BGT);
+        PHIP(hipMemcpyAsync(out_dev, s.dev.vec[BGT], nb, hipMemcpyDeviceToDevice, P->s));
+        break;
+    case TMOP_EVAL_SETUP:
+        PHIP(hipMemcpyAsync(s.dev.vec[BXT], in_dev, nb, hipMemcpyDeviceToDevice, P->s));
+        launch_elem(P, 2, ge, BXT);
+        s.h_ready = true;
+        break;
+    case TMOP_EVAL_APPLY: {
+        // the element kernels read the action's input through the slot's
+        // BZIN pointer (set by MINRES on the device); point it at BZ0
+        PHIP(hipMemcpyAsync(s.dev.vec[BZ0], in_dev, nb, hipMemcpyDeviceToDevice, P->s));
+        double *const zin = s.dev.vec[BZ0];
+        PHIP(hipMemcpyAsync(&P->d_slots[slot].vec[BZIN], &zin, sizeof(double *), hipMemcpyHostToDevice, P->s));
+        PHIP(hipStreamSynchronize(P->s));
+        launch_elem(P, 3, ge, BZIN);
+        // fixed DoFs: y = v (H_c = P H P + I - P); mixed slots' E-vectors are FP32
+        launch_gather(P, ge, BY, 2, BZ0, true);
+        PHIP(hipMemcpyAsync(out_dev, s.dev.vec[BY], nb, hipMemcpyDeviceToDevice, P->s));
+        break;
+    }
+    case TMOP_EVAL_DIAG:
+        launch_elem(P, 4, ge, BX);
+        launch_gather(P, ge, BDIAG, 1, BDIAG, false);
+        PHIP(hipMemcpyAsync(out_dev, s.dev.vec[BDIAG], nb, hipMemcpyDeviceToDevice, P->s));
+        break;
+    }
+    PHIP(hipStreamSynchronize(P->s));
+    PHIP(hipGetLastError());
+    if (status != TMOP_OK) return pfail(status, "det A <= 0 at a quadrature point");
     return TMOP_OK;
 }
 

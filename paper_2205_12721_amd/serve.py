@@ -8,7 +8,11 @@ resident solve by one Newton iteration per tick (one batched launch per kernel
 class and phase), and retires finished solves as soon as their tick ends, which
 frees their slot and memory for waiting requests.  Latency runs from the
 request's arrival time to the end of the tick in which it finished (host
-monotonic clock).
+monotonic clock).  Percentiles count every request: one that fails (line
+search, iteration cap) or is rejected enters with the time at which its
+result was known, so failures cannot make the latency look better; the
+summaries also give the solved count and the percentiles over solved
+requests alone.
 
 ``sequential`` runs the same stream one request at a time through a plain FP64
 context (``Context.solve``), the reference the served form is compared with.
@@ -22,26 +26,57 @@ from .tmop import (ERR_BUSY, Context, Pool, TmopError, basis_nodes, request, req
                    solve_params)
 
 
-def make_inputs(reqs, amp=0.05):
-    """Host node vectors of a request stream (seeded, smooth + jitter recipe)."""
-    out = []
-    for r in reqs:
-        x, _ = inputs.perturbed_box(r["dim"], r["n"], r["p"], basis_nodes(r["p"]), r["seed"],
-                                    recipe="smooth", amp=amp)
-        out.append(x)
+def make_inputs(reqs, amp=0.05, validate=True):
+    """Host node vectors of a request stream (seeded, smooth + jitter recipe).
+
+    With ``validate`` a draw with det A <= 0 at a quadrature point is redrawn
+    from the continuing stream of its seed, the library deciding on the GPU
+    (one context per mesh size, compact mixed storage to keep it small);
+    ``redraws`` of each request are recorded in ``r["redraws"]``.
+    """
+    import torch
+    out = [None] * len(reqs)
+    groups = {}
+    for k, r in enumerate(reqs):
+        groups.setdefault((r["dim"], r["n"], r["p"], r["nq"]), []).append(k)
+    for (dim, n, p, nq), ks in groups.items():
+        ctx = Context(dim, n, p, nq, precision="mixed", storage="compact") if validate else None
+        ok = (lambda x: ctx.min_det(torch.as_tensor(x).cuda()) > 0.0) if validate else None
+        for k in ks:
+            r = reqs[k]
+            x, info = inputs.perturbed_box(dim, n, p, basis_nodes(p), r["seed"], recipe="smooth",
+                                           amp=amp, is_valid=ok)
+            r["redraws"] = info["tries"] - 1 if validate else 0
+            out[k] = x
+        if ctx is not None:
+            ctx.close()
     return out
 
 
-def _percentiles(lat):
+def _percentiles(lat, prefix=""):
     a = np.asarray(lat)
     if a.size == 0:
-        return dict(p50_ms=None, p99_ms=None, mean_ms=None)
-    return dict(p50_ms=float(np.percentile(a, 50)), p99_ms=float(np.percentile(a, 99)),
-                mean_ms=float(a.mean()))
+        return {prefix + "p50_ms": None, prefix + "p99_ms": None, prefix + "mean_ms": None}
+    return {prefix + "p50_ms": float(np.percentile(a, 50)),
+            prefix + "p99_ms": float(np.percentile(a, 99)), prefix + "mean_ms": float(a.mean())}
+
+
+def _summary(rec, wall):
+    """Latency over every request (failed and rejected ones at the time their
+    result was known) and over solved requests alone."""
+    n = len(rec)
+    lat_all = [r["latency_ms"] for r in rec if r and r.get("latency_ms") is not None]
+    lat_ok = [r["latency_ms"] for r in rec if r and r.get("latency_ms") is not None and r["status"] == 0]
+    ok = sum(1 for r in rec if r and r["status"] == 0)
+    out = dict(requests=n, solved=ok, failed=n - ok, wall_s=wall,
+               solves_per_s=ok / wall if wall > 0 else None)
+    out.update(_percentiles(lat_all))
+    out.update(_percentiles(lat_ok, "solved_"))
+    return out
 
 
 def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="compact",
-          rel_grad_tol=1e-8, max_newton=50, max_minres=50, graph=True, lanczos_bank=False):
+          rel_grad_tol=1e-8, max_newton=200, max_minres=50, graph=True, lanczos_bank=False):
     """Run the stream through a pool; returns a summary dict and per-request records."""
     import torch
     pool = Pool(hbm_budget, max_slots, graph=graph, lanczos_bank=lanczos_bank)
@@ -72,7 +107,8 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
             except TmopError as e:
                 if e.code == ERR_BUSY:
                     break
-                rec[k] = dict(status=e.code, latency_ms=None, rejected=True)
+                rec[k] = dict(status=e.code, rejected=True,
+                              latency_ms=(time.monotonic() - t0) * 1e3 - r["t_arrive"] * 1e3)
                 pending.pop(0)
                 continue
             pending.pop(0)
@@ -98,15 +134,12 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
                 time.sleep(min(wait, 0.01))
     wall = time.monotonic() - t0
     pool.close()
-    lat = [r["latency_ms"] for r in rec if r and r.get("latency_ms") is not None and r["status"] == 0]
-    ok = sum(1 for r in rec if r and r["status"] == 0)
-    out = dict(requests=n, solved=ok, wall_s=wall, solves_per_s=ok / wall if wall > 0 else None,
-               ticks=ticks, peak_bytes=peak_used)
-    out.update(_percentiles(lat))
+    out = _summary(rec, wall)
+    out.update(ticks=ticks, peak_bytes=peak_used)
     return out, rec
 
 
-def sequential(reqs, xs_host, rel_grad_tol=1e-8, max_newton=50, max_minres=50):
+def sequential(reqs, xs_host, rel_grad_tol=1e-8, max_newton=200, max_minres=50):
     """The same stream one request at a time through FP64 contexts (arrival-time aware)."""
     import torch
     n = len(reqs)
@@ -127,11 +160,7 @@ def sequential(reqs, xs_host, rel_grad_tol=1e-8, max_newton=50, max_minres=50):
         rec[k] = dict(status=rep["status"], latency_ms=tend - r["t_arrive"] * 1e3,
                       newton_its=rep["newton_its"], F=rep["F"], x=xd)
     wall = time.monotonic() - t0
-    lat = [r["latency_ms"] for r in rec if r["status"] == 0]
-    ok = sum(1 for r in rec if r["status"] == 0)
-    out = dict(requests=n, solved=ok, wall_s=wall, solves_per_s=ok / wall if wall > 0 else None)
-    out.update(_percentiles(lat))
-    return out, rec
+    return _summary(rec, wall), rec
 
 
 def budget_for(reqs, precision="mixed", storage="compact", factor=1.0, cap=None):

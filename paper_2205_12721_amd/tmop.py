@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libtmop_hip.so")
 TMOP_FP64, TMOP_MIXED = 0, 1
 HESS_TENSOR, HESS_COMPACT = 0, 1
 ESS_BOUNDARY, ESS_NONE, ESS_MASK = 0, 1, 2
+EVAL_ENERGY, EVAL_GRADIENT, EVAL_SETUP, EVAL_APPLY, EVAL_DIAG = 0, 1, 2, 3, 4
 
 STATUS = {
     0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_INVERTED",
@@ -111,6 +112,7 @@ SIGNATURES = {
     "tmop_pool_step": [_P, ctypes.POINTER(ctypes.c_int)],
     "tmop_pool_poll": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport)],
     "tmop_pool_result": [_P, ctypes.c_int, _P, _P],
+    "tmop_pool_evaluate": [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D, _P],
     "tmop_pool_release": [_P, ctypes.c_int],
     "tmop_pool_info": [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                        ctypes.POINTER(ctypes.c_int)],
@@ -384,7 +386,14 @@ def request(dim, n, p, nq1d=None, metric=None, precision="fp64", storage="tensor
     md.dim, md.order_p = dim, p
     md.nx, md.ny = ns[0], ns[1]
     md.nz = ns[2] if dim == 3 else 0
-    md.ess_mode = {"boundary": ESS_BOUNDARY, "none": ESS_NONE}[ess]
+    if isinstance(ess, str):
+        md.ess_mode = {"boundary": ESS_BOUNDARY, "none": ESS_NONE}[ess]
+    else:
+        # a device uint8 mask of fixed DoFs; tmop_pool_admit copies it, so it
+        # needs to live only until the request is admitted
+        import torch
+        md.ess_mode = ESS_MASK
+        md.ess_mask = _ptr(ess, dtype=torch.uint8).value
     prm = Params()
     prm.metric = metric if metric is not None else (2 if dim == 2 else 303)
     prm.nq1d = nq1d if nq1d is not None else p + 2
@@ -463,6 +472,42 @@ class Pool:
     def release(self, slot):
         _pcheck(lib().tmop_pool_release(self._h, int(slot)))
         self._keep.pop(slot, None)
+
+    # -- one slot's operators with the pool's batched kernels (between steps) --
+    def _eval(self, slot, what, x=None, out=None, host=None):
+        s = self._torch.cuda.current_stream().cuda_stream
+        xin = None if x is None else _ptr(x, dtype=self._torch.float64)
+        o = None if out is None else _ptr(out, dtype=self._torch.float64)
+        hp = None if host is None else host.ctypes.data_as(_D)
+        _pcheck(lib().tmop_pool_evaluate(self._h, int(slot), what, xin, o, hp, ctypes.c_void_p(s)))
+
+    def energy_mindet(self, slot, x):
+        """(F, min det A) of the slot's mesh at nodes x; F = inf if det <= 0."""
+        h = np.zeros(2)
+        try:
+            self._eval(slot, EVAL_ENERGY, x, host=h)
+        except TmopError as e:
+            if e.code != ERR_INVERTED:
+                raise
+        return float(h[0]), float(h[1])
+
+    def gradient(self, slot, x):
+        out = self._torch.empty_like(x)
+        self._eval(slot, EVAL_GRADIENT, x, out)
+        return out
+
+    def hessian_setup(self, slot, x):
+        self._eval(slot, EVAL_SETUP, x)
+
+    def hessian_apply(self, slot, v):
+        out = self._torch.empty_like(v)
+        self._eval(slot, EVAL_APPLY, v, out)
+        return out
+
+    def hessian_diag(self, slot, like):
+        out = self._torch.empty_like(like)
+        self._eval(slot, EVAL_DIAG, None, out)
+        return out
 
     def autotune(self, reps=5):
         """Pick the Hessian-action tile shape of every resident kernel class."""

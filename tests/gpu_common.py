@@ -13,10 +13,18 @@ TOLX = 1e-9     # relative, final node positions of a full solve
 
 
 def rel(a, b):
+    """Relative error of a against b: the larger of the l2 measure
+    |a - b|_2 / |b|_2 over all entries and the entrywise measure
+    max|a - b| / max|b|.  The second catches an error confined to a few
+    entries, which the l2 measure over millions of entries would dilute."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
+    d = a - b
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    e2 = np.linalg.norm(d) / (nb if nb > 0 else 1.0)
+    ei = (np.abs(d).max() if d.size else 0.0) / (mb if mb > 0 else 1.0)
+    return float(np.max([e2, ei]))  # NaN propagates
 
 
 def log(*a):

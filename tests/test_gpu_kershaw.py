@@ -1,7 +1,8 @@
 """Kershaw benchmark meshes (Sec. 4.1): 9^3 Gauss-Legendre points per element,
 mu_303, sliding boundary nodes (component normal to the face fixed).
 
-* every operator matches the oracle on a 6x2x2 Kershaw mesh (eps = 0.3), p = 1..3;
+* every operator matches the oracle on a 6x2x2 Kershaw mesh (eps = 0.3), p = 1..4
+  (every 9-point hex class the library instantiates);
 * the Newton-MINRES solve drives the deformed mesh to the uniform grid (the
   optimum: every element the same affine image of the reference cube) as the
   paper's benchmark does, and matches the oracle's solve.
@@ -30,7 +31,7 @@ def _problem(p, quad="gl"):
 
 @pytest.mark.parametrize("quad", ["gl", "gll"])
 @pytest.mark.parametrize("storage", ["tensor", "compact"])
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_kershaw_operators(p, storage, quad):
     import torch
     from paper_2205_12721_amd.tmop import Context

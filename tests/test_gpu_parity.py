@@ -1,9 +1,11 @@
 """GPU parity: every entry point of the HIP library against the FP64 oracle.
 
-Sizes span several workgroups with a ragged last workgroup (element counts
-not multiple of the elements-per-workgroup of each (p, n_q)), both
-dimensions, p = 1..4 and n_q = p+1..p+3.  Tolerance: 1e-11 relative (l2 over
-all DoFs) for FP64 energy, gradient, Hessian action and diagonal.
+Every (dim, p, n_q) class the library accepts is covered (both dimensions,
+p = 1..4, n_q = p+1..p+3 here, the 9-point hex classes in the Kershaw tests),
+at sizes that span several workgroups, with a ragged last workgroup where a
+workgroup holds several elements.  Tolerance: 1e-11 relative for FP64
+energy, gradient, Hessian action and diagonal, both as l2 over all DoFs and
+entrywise against the largest entry (``gpu_common.rel``).
 """
 import numpy as np
 import pytest
@@ -15,20 +17,33 @@ from tests.gpu_common import TOL64, log, make_case, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-# (dim, elements per axis, p, nq)
+# (dim, elements per axis, p, nq): every (dim, p, n_q) class with n_q = p+1..p+3
+# that tmop_create accepts (the 9-point hex classes are in test_gpu_kershaw).
+# Element counts give several workgroups (max(1, 256 / n_q^d) elements each)
+# and, where a workgroup holds more than one element, a ragged last one.
 CASES = [
-    (2, (8, 8), 2, 4),
+    (2, (11, 7), 1, 2),
     (2, (5, 7), 1, 3),
+    (2, (5, 7), 1, 4),
+    (2, (6, 7), 2, 3),
+    (2, (8, 8), 2, 4),
+    (2, (7, 5), 2, 5),
+    (2, (5, 4), 3, 4),
     (2, (3, 5), 3, 5),
+    (2, (4, 5), 3, 6),
+    (2, (3, 4), 4, 5),
     (2, (4, 3), 4, 6),
-    (2, (6, 5), 2, 5),
+    (2, (3, 4), 4, 7),
+    (3, (3, 4, 3), 1, 2),
     (3, (2, 3, 4), 1, 3),
-    (3, (2, 2, 3), 1, 2),
-    (3, (3, 3, 3), 2, 4),
+    (3, (3, 2, 3), 1, 4),
     (3, (3, 2, 2), 2, 3),
+    (3, (3, 3, 3), 2, 4),
+    (3, (3, 3, 3), 2, 5),
+    (3, (3, 3, 2), 3, 4),
     (3, (3, 3, 3), 3, 5),
-    (3, (2, 3, 2), 3, 4),
     (3, (2, 2, 3), 3, 6),
+    (3, (3, 3, 3), 4, 5),
     (3, (2, 2, 2), 4, 6),
     (3, (2, 2, 2), 4, 7),
 ]
