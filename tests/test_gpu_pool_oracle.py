@@ -9,13 +9,18 @@ slot by slot with the pool's own batched kernels (``tmop_pool_evaluate``):
   relative for FP64 slots and for the FP64 parts of mixed slots (energy,
   gradient), the FP32 bound for the mixed action and diagonal;
 * the first Newton step (the pool's lockstep MINRES, line search and update)
-  against the oracle's first Newton step: the same line-search decisions;
-  for FP64 slots the same MINRES count, the step x0 - x1 within 1e-9
-  relative (the single-context MINRES parity bound) and the new energy within
-  1e-10 of the initial one; for mixed slots, whose MINRES runs on an FP32
-  action, the step within 1e-4 (about sqrt of FP32 epsilon, the accuracy of
-  a Krylov solve with an operator perturbed at FP32 rounding) and the energy
-  within 1e-6;
+  against the oracle's first Newton step, with MINRES allowed 200 iterations
+  so that it stops at its tolerance: the same line-search decisions; for
+  FP64 slots MINRES counts within one (near the stop threshold rounding can
+  move the count), the step x0 - x1 within 1e-9 relative (the
+  single-context MINRES parity bound) and the new energy within 1e-10 of the
+  initial one.  A Krylov solve cut off by the iteration cap before it
+  converges is no parity case: on the 3x4 Q4 quad mesh, 50 iterations leave
+  the residual at 6e-5 and the oracle's own direction moves by 1e-5 when its
+  action is perturbed at 1e-16, so two correct FP64 runs need not agree;
+  for mixed slots, whose MINRES runs on an FP32 action, the step within
+  1e-4 (about sqrt of FP32 epsilon, the accuracy of a Krylov solve with an
+  operator perturbed at FP32 rounding) and the energy within 1e-6;
 * the solves to |g|/|g0| <= 1e-10 (the paper's eps) against the oracle's
   Newton solves: final nodes within 1e-9 relative, final energy within
   1e-10 of the initial one;
@@ -62,7 +67,8 @@ def _case(c):
     return pb, x, mdev
 
 
-def _admit_all(cases, rel_grad_tol=1e-10, max_newton=200, minres_rtol=1e-12, bank=False):
+def _admit_all(cases, rel_grad_tol=1e-10, max_newton=200, minres_rtol=1e-12, bank=False,
+               max_minres=50):
     from paper_2205_12721_amd.tmop import Pool, request, request_bytes, solve_params
     probs, reqs = [], []
     for c in cases:
@@ -76,7 +82,8 @@ def _admit_all(cases, rel_grad_tol=1e-10, max_newton=200, minres_rtol=1e-12, ban
     slots, xs = [], []
     for (md, prm, mdev), (pb, x) in zip(reqs, probs):
         xd = to_dev(x)
-        sp = solve_params(rel_grad_tol=rel_grad_tol, max_newton=max_newton, minres_rtol=minres_rtol)
+        sp = solve_params(rel_grad_tol=rel_grad_tol, max_newton=max_newton, minres_rtol=minres_rtol,
+                          max_minres=max_minres)
         slots.append(pool.admit(md, prm, sp, xd))
         xs.append(xd)
     return pool, probs, slots, xs
@@ -105,7 +112,7 @@ def test_pool_operators_match_oracle():
 
 
 def test_pool_first_newton_step_matches_oracle():
-    pool, probs, slots, xs = _admit_all(MIX, max_newton=1)
+    pool, probs, slots, xs = _admit_all(MIX, max_newton=1, max_minres=200)
     while pool.step() > 0:
         pass
     res = []
@@ -114,7 +121,7 @@ def test_pool_first_newton_step_matches_oracle():
         assert done and rep["newton_its"] == 1
         pool.result(sl, xd)
         x1 = to_host(xd)
-        xo, ro = oracle.newton_solve(pb, x0, rel_grad_tol=1e-10, max_newton=1)
+        xo, ro = oracle.newton_solve(pb, x0, rel_grad_tol=1e-10, max_newton=1, max_minres=200)
         assert ro["newton_its"] == 1
         e = rel(x0 - x1, x0 - xo)
         log("first step", c, "its", rep["minres_its_total"], ro["minres_its_total"],
@@ -126,7 +133,7 @@ def test_pool_first_newton_step_matches_oracle():
     for c, rep, ro, e, eF in res:
         assert rep["halvings_total"] == ro["halvings_total"]
         if c["precision"] == "fp64":
-            assert rep["minres_its_total"] == ro["minres_its_total"]
+            assert abs(rep["minres_its_total"] - ro["minres_its_total"]) <= 1
             assert e <= 1e-9 and eF <= 1e-10
         else:
             assert e <= 1e-4 and eF <= 1e-6
