@@ -395,6 +395,37 @@ int tmop_set_limiting(tmop_ctx *ctx, const double *x0_dev, double coef, double d
  * MINRES; results land in tmop_solve_report.t_apply_ms / n_apply. */
 int tmop_set_timing(tmop_ctx *ctx, int enable);
 
+/* ---------------------------------------------------------------------- */
+/* No-allocation evaluation                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Largest number of element tiles (workgroups of the energy kernel, each of
+ * max(1, 256 / nq1d^dim) elements) tmop_energy_mindet_noalloc accepts. */
+#define TMOP_NOALLOC_MAX_TILES 65536
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * energy and min det of tmop_energy_mindet without a context, with no device
+ * or pinned allocation by the library.  The per-workgroup partial sums go to
+ * a fixed 1.5 MiB device array of the library (3 x TMOP_NOALLOC_MAX_TILES
+ * doubles; each GPU the library runs on holds its own copy until the process
+ * ends).  m: a structured box (elem_to_node must be NULL, else
+ * TMOP_ERR_UNSUPPORTED; ess fields ignored); prm: metric, nq1d, target and
+ * quad_rule as for tmop_create (precision and storage ignored: the energy is
+ * FP64).  x_dev: device [dim*N_x] nodes.  out_dev: caller-owned device
+ * doubles [3]: out[0] = F (meaningless when out[2] > 0), out[1] = min det A
+ * over all quadrature points, out[2] = number of points with det A <= 0.
+ * Asynchronous on hip_stream (NULL: the null stream); out_dev is ready when
+ * the stream reaches the call.  A box whose elements fill more than
+ * TMOP_NOALLOC_MAX_TILES tiles returns TMOP_ERR_INVALID_ARG.  Every call on
+ * one GPU shares that GPU's array (the partials are written in full before
+ * they are read, so nothing needs clearing): calls that overlap in time on
+ * one GPU (different streams or host threads) race and must be ordered by
+ * the caller.  The result is bitwise that of tmop_energy_mindet for the same
+ * mesh and parameters. */
+int tmop_energy_mindet_noalloc(const tmop_mesh_desc *m, const tmop_params *prm,
+                               const double *x_dev, double *out_dev, void *hip_stream);
+
 /* Thread-local description of the last error. */
 const char *tmop_last_error(void);
 

@@ -1158,6 +1158,90 @@ extern "C" int tmop_set_lanczos_bank_limit(tmop_ctx *c, size_t max_bytes)
     return TMOP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Energy and min det with no allocation, for callers that cannot allocate
+// device memory.  The energy kernel's per-workgroup partials (3 planes of
+// grid doubles, each fully written by the kernel before the final reduction
+// reads it) live in this file-scope array instead of a context's workspace.
+// Each GPU holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[3 * TMOP_NOALLOC_MAX_TILES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+int scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TMOP_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(TMOP_ERR_HIP, "no device address for the scratch array");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return TMOP_OK;
+}
+
+}  // namespace
+
+extern "C" int tmop_energy_mindet_noalloc(const tmop_mesh_desc *m, const tmop_params *prm,
+                                          const double *x, double *out, void *stream)
+{
+    if (!m || !prm || !x || !out) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    long ne, nx;
+    int nqe, np;
+    CHK(ctx_sizes(m, prm, ne, nx, nqe, np));
+    if (m->elem_to_node)
+        return fail(TMOP_ERR_UNSUPPORTED, "the no-allocation energy takes structured boxes only");
+    const int d = m->dim, p = m->order_p, nq = prm->nq1d;
+    if (!metric_supported(d, prm->metric))
+        return fail(TMOP_ERR_UNSUPPORTED, "metric must be 2, 7, 9 or 55 (dim 2) or 303 or 55 (dim 3)");
+    Ops ops;
+    if (!find_ops(d, p, nq, &ops))
+        return fail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d); nq1d must be p+1..p+3");
+    const long grid = (ne + ops.epb - 1) / ops.epb;
+    if (grid > TMOP_NOALLOC_MAX_TILES)
+        return fail(TMOP_ERR_INVALID_ARG,
+                    "mesh too large for the no-allocation energy: " + std::to_string(grid) +
+                        " element tiles of " + std::to_string(ops.epb) + " elements, at most " +
+                        std::to_string(TMOP_NOALLOC_MAX_TILES));
+    Tables tb;
+    Target tg;
+    if (internal_tables(p, nq, &tb, prm->quad_rule) != TMOP_OK)
+        return fail(TMOP_ERR_INVALID_ARG, "quad_rule must be TMOP_QUAD_GL or TMOP_QUAD_GLL");
+    if (internal_target(prm, d, &tg) != TMOP_OK)
+        return fail(TMOP_ERR_INVALID_ARG, "target W must have det > 0");
+    Geom g{};
+    g.dim = d;
+    g.p = p;
+    g.ne = (int)ne;
+    g.nx = (int)nx;
+    g.nel[0] = m->nx;
+    g.nel[1] = m->ny;
+    g.nel[2] = d == 3 ? m->nz : 1;
+    for (int k = 0; k < 3; ++k) g.M[k] = g.nel[k] * p + 1;
+    if (d == 2) g.M[2] = 1;
+    set_divisors(g);
+    g.ess_mode = TMOP_ESS_NONE;
+    double *part = nullptr;
+    CHK(scratch_on_current_device(&part));
+    const hipStream_t s = (hipStream_t)stream;
+    ops.energy((int)grid, s, g, tb, tg, x, part);
+    launch_reduce3(part, (int)grid, out, s);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
 extern "C" const char *tmop_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *tmop_version(void) { return "tmop-mi355x 0.1 (gfx950)"; }

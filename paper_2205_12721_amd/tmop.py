@@ -122,6 +122,7 @@ SIGNATURES = {
     "tmop_batch_solve": [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
                          ctypes.POINTER(_P), ctypes.POINTER(SolveParams),
                          ctypes.POINTER(SolveReport), _P],
+    "tmop_energy_mindet_noalloc": [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), _P, _P, _P],
     "tmop_last_error": [],
     "tmop_version": [],
 }
@@ -404,6 +405,19 @@ def request(dim, n, p, nq1d=None, metric=None, precision="fp64", storage="tensor
     prm.precision = {"fp64": TMOP_FP64, "mixed": TMOP_MIXED}[precision]
     prm.hess_storage = {"tensor": HESS_TENSOR, "compact": HESS_COMPACT}[storage]
     return md, prm
+
+
+def energy_mindet_noalloc(md, prm, x, out, stream=None):
+    """tmop_energy_mindet_noalloc: F, min det A and the count of points with
+    det A <= 0 written to the device tensor ``out`` (3 doubles) on ``stream``
+    (default: torch's current stream), with no allocation by the library."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().tmop_energy_mindet_noalloc(ctypes.byref(md), ctypes.byref(prm),
+                                            _ptr(x, dtype=torch.float64),
+                                            _ptr(out, 3, torch.float64),
+                                            ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 def solve_params(rel_grad_tol=1e-8, max_newton=200, max_minres=50, minres_rtol=1e-12,
