@@ -7,13 +7,27 @@ diagonal, 20 Hessian actions inside Jacobi-preconditioned MINRES, line search
 and node update.  Every step restarts from the same initial mesh, so each
 does the same work.
 
-Reported metric: Hessian-action throughput in GDoF/s (unique DoFs d*N_x times
-actions, over the summed device time of the actions measured with HIP events
-on the library's stream inside the timed steps), FP64 and mixed precision,
-with the HBM roofline fraction of the action and the plain FP64 oracle timed
-on the host cores as a reference baseline.
+Reported metric (``value``): Hessian-action throughput in GDoF/s, the unique
+DoFs d*N_x over the median time of one standalone ``tmop_hessian_apply`` call
+(FP64, the paper's packed-tensor storage; 30 calls after one setup and 3
+warm-up actions, each call bracketed by HIP events recorded on the library's
+stream; the setup is not timed).  ``roofline`` is the same action's
+algorithmic HBM bytes over its mean time back to back; the mixed-precision and
+compact-storage variants, the 64^3 Q2 and 32^3 Q4 workloads, the batched and
+served forms and the Kershaw benchmark are reported beside it, and the plain
+FP64 oracle is timed on the host cores as a reference baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --apply-only [--workload c2] [--reps 10]
+           [--storage tensor|compact|both] [--precision fp64|mixed|both] [--copy-ref]
+           [--all-kernels]
+
+``--apply-only`` runs only the Hessian action, for profilers: one setup per
+variant on the workload's mesh, then 2 x reps actions back to back on the
+library's stream (``tmop_time_apply``), printing the mean device time per
+action; ``--copy-ref`` adds a plain 1 GiB device-to-device copy, a kernel of
+known traffic to scale hardware byte counters by; ``--all-kernels`` also runs
+the energy, gradient, setup and diagonal kernels reps times per variant.
 """
 import argparse
 import json
@@ -314,6 +328,112 @@ def precision_leg(cfg, x0, v_host, y_oracle, max_newton=100):
     return out
 
 
+def config3_leg(name, apply_reps, steps, n_minres, n_sample=400):
+    """The 6.44 M-DoF workloads (64^3 Q2 with 4^3 points, 32^3 Q4 with 6^3): every
+    action variant (tensor / compact storage x FP64 / mixed) timed as the headline
+    (autotuned tile, median single call, back-to-back mean and its HBM roofline), a
+    Newton step with n_minres MINRES iterations in FP64 and in mixed precision, and
+    solves to |g|/|g0| <= 1e-8 with each variant, whose final energy is compared with
+    the FP64 tensor solve's (bar: 1e-10 relative).  Returns the results, the host mesh
+    and vector, the sampled node ids and each variant's action at those DoFs (for the
+    oracle comparison in the CPU-baseline leg)."""
+    import numpy as np
+    import torch
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes
+    c = inputs.CONFIGS[name]
+    dim, n, p, nq = c["dim"], c["n"], c["p"], c["nq"]
+    ne, nqe, S = n ** dim, nq ** dim, dim * dim * (dim * dim + 1) // 2
+    probe = Context(dim, n, p, nq, precision="mixed", storage="compact")
+    buf = torch.empty(probe.ndof, dtype=torch.float64, device="cuda")
+
+    def valid(xh):
+        buf.copy_(torch.as_tensor(xh))
+        return probe.min_det(buf) > 0
+
+    xh, info = inputs.config_mesh(name, basis_nodes(p), is_valid=valid)
+    ndof = probe.ndof
+    probe.close()
+    del buf
+    x0 = torch.as_tensor(xh).cuda()
+    x = torch.empty_like(x0)
+    vh = inputs.gaussian_vector(ndof, c["vec_seed"])
+    v = torch.as_tensor(vh).cuda()
+    rng = np.random.default_rng(77)
+    nx = ndof // dim
+    nodes = np.sort(rng.choice(nx, size=n_sample, replace=False))
+    idx = np.concatenate([a * nx + nodes for a in range(dim)])
+    res = {"workload": "3D hex box %d^3, Q%d, %d^3 Gauss-Legendre points, mu_303" % (n, p, nq),
+           "dofs": ndof, "mesh_tries": info["tries"], "variants": {}}
+    sampled = {}
+    for storage in ("tensor", "compact"):
+        for prec in ("fp64", "mixed"):
+            key = "%s_%s" % (storage, prec)
+            cv = Context(dim, n, p, nq, precision=prec, storage=storage)
+            em, tm, eb, mm = time_actions(cv, x0, v, apply_reps)
+            y = torch.empty_like(v)
+            cv.hessian_apply(v, y)
+            sampled[key] = y.cpu().numpy()[idx]
+            sv = S if storage == "tensor" else 13
+            r = {"value": round(ndof / (mm / 1e3) / 1e9, 3), "unit": "GDoF/s",
+                 "elements_per_workgroup": eb,
+                 "roofline": roofline(ne, nqe, sv, ndof, 8 if prec == "fp64" else 4, em, tm)}
+            r["roofline"]["median_action_us"] = round(mm * 1e3, 2)
+            if storage == "tensor":
+                run_steps(cv, x, x0, 1, n_minres)
+                acc = run_steps(cv, x, x0, steps, n_minres)
+                r["newton_step_ms"] = round(acc["wall_s"] / steps * 1e3, 3)
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = cv.solve(x, rel_grad_tol=1e-8, max_newton=100)
+            torch.cuda.synchronize()
+            r["solve_to_1e-8"] = {"seconds": round(time.perf_counter() - t0, 4),
+                                  "status": rep["status_name"], "newton_its": rep["newton_its"],
+                                  "minres_its": rep["minres_its_total"], "F0": rep["F0"],
+                                  "F": rep["F"]}
+            r["_x"] = x.clone()
+            res["variants"][key] = r
+            cv.close()
+            log("[bench] %s %s %s: %.2f GDoF/s, frac %.3f" % (name, storage, prec, r["value"],
+                                                                r["roofline"]["frac"]))
+    ref = res["variants"]["tensor_fp64"]
+    worst = 0.0
+    for k, r in res["variants"].items():
+        sv = r["solve_to_1e-8"]
+        sv["rel_final_energy_diff_vs_tensor_fp64"] = abs(sv["F"] - ref["solve_to_1e-8"]["F"]) / abs(
+            ref["solve_to_1e-8"]["F"])
+        sv["rel_node_diff_vs_tensor_fp64"] = float((r["_x"] - ref["_x"]).norm() / ref["_x"].norm())
+        worst = max(worst, sv["rel_final_energy_diff_vs_tensor_fp64"])
+    for r in res["variants"].values():
+        del r["_x"]
+    res["max_rel_final_energy_diff"] = worst
+    res["final_energy_within_1e-10"] = bool(worst <= 1e-10)
+    return res, (name, xh, vh, nodes, idx, sampled)
+
+
+def config3_oracle_error(ref):
+    """CPU-baseline leg of a 6.44 M-DoF workload: the oracle's Hessian action at the
+    sampled DoFs (the oracle evaluates only the elements touching the sampled nodes,
+    whose entries equal the full operator's there) and each GPU variant's error
+    against it (relative l2 and max-entry measures over the sampled DoFs)."""
+    import numpy as np
+    import oracle
+    from paper_2205_12721_amd import inputs
+    name, xh, vh, nodes, idx, sampled = ref
+    c = inputs.CONFIGS[name]
+    pb = oracle.Problem.box(c["dim"], c["n"], c["p"], c["nq"])  # boundary fixed, as the GPU's
+    t0 = time.perf_counter()
+    sub = oracle.restrict_to_nodes(pb, nodes)
+    yo = sub.hvp(xh, vh)[idx]
+    out = {"sampled_nodes": int(nodes.size), "oracle_seconds": round(time.perf_counter() - t0, 2)}
+    for k, y in sampled.items():
+        d = y - yo
+        out[k] = {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(yo)),
+                  "rel_max": float(np.abs(d).max() / np.abs(yo).max())}
+    return out
+
+
 def batch_leg(count):
     """256 independent hex meshes (log-uniform sizes, p = 1..4, n_q = p+2, mu_303):
     one batched mixed-precision solve vs one-mesh-at-a-time FP64 solves."""
@@ -360,39 +480,41 @@ def batch_leg(count):
 SERVE_BUDGET_FACTOR = 4.0
 
 
-def serve_leg(rate, nreq):
-    """Poisson stream of mixed 2D/3D requests through the pool vs a sequential FP64 loop."""
+def serve_leg(rates, nreq):
+    """The served stream (Poisson arrivals of mixed 2D/3D requests, the same
+    requests at every rate, arrival times one unit-rate stream divided by the
+    rate) through the pool, and the same stream through a one-at-a-time FP64
+    loop, at every rate: p50/p99 latency (every request counted, a failed one at
+    the time its result was known) and solves/s of both."""
     from paper_2205_12721_amd import inputs, serve
-    reqs = inputs.serving_stream(rate, count=nreq, seed=6)
-    xs = serve.make_inputs(reqs)
-    budget = serve.budget_for(reqs, factor=SERVE_BUDGET_FACTOR, cap=64 << 30)
-    s, _ = serve.serve(reqs, xs, budget, max_slots=min(512, nreq), lanczos_bank=True)
-    q, _ = serve.sequential(reqs, xs)
+    base = inputs.serving_stream(1.0, count=nreq, seed=6, same_requests=True)
+    t0 = time.perf_counter()
+    xs = serve.make_inputs(base)
+    gen_s = time.perf_counter() - t0
+    budget = serve.budget_for(base, factor=SERVE_BUDGET_FACTOR, cap=64 << 30)
     r3 = lambda v: None if v is None else round(v, 3)  # noqa: E731
-    return {
-        "rate_per_s": rate, "requests": nreq,
-        "p50_ms": r3(s["p50_ms"]), "p99_ms": r3(s["p99_ms"]),
-        "solves_per_s": r3(s["solves_per_s"]), "solved": s["solved"], "budget_bytes": budget,
-        "sequential_fp64": {"p50_ms": r3(q["p50_ms"]), "p99_ms": r3(q["p99_ms"]),
-                            "solves_per_s": r3(q["solves_per_s"]), "solved": q["solved"]},
-    }
-
-
-def serve_sweep(rates, nreq):
-    """The served stream at several arrival rates (same seed and size mix): p50/p99
-    latency and throughput per rate."""
-    from paper_2205_12721_amd import inputs, serve
-    out = []
+    rows = []
     for rate in rates:
-        reqs = inputs.serving_stream(rate, count=nreq, seed=6)
-        xs = serve.make_inputs(reqs)
-        budget = serve.budget_for(reqs, factor=SERVE_BUDGET_FACTOR, cap=64 << 30)
+        reqs = [dict(r, t_arrive=r["t_arrive"] / rate) for r in base]
         s, _ = serve.serve(reqs, xs, budget, max_slots=min(512, nreq), lanczos_bank=True)
-        out.append({"rate_per_s": rate, "requests": nreq, "p50_ms": round(s["p50_ms"], 3),
-                    "p99_ms": round(s["p99_ms"], 3), "solves_per_s": round(s["solves_per_s"], 3),
-                    "solved": s["solved"], "ticks": s["ticks"]})
-        log("[bench] serve rate", rate, "p50", out[-1]["p50_ms"], "p99", out[-1]["p99_ms"])
-    return out
+        q, _ = serve.sequential(reqs, xs)
+        rows.append({
+            "rate_per_s": rate, "requests": nreq,
+            "p50_ms": r3(s["p50_ms"]), "p99_ms": r3(s["p99_ms"]),
+            "solves_per_s": r3(s["solves_per_s"]), "solved": s["solved"], "ticks": s["ticks"],
+            "solved_p99_ms": r3(s["solved_p99_ms"]),
+            "sequential_fp64": {"p50_ms": r3(q["p50_ms"]), "p99_ms": r3(q["p99_ms"]),
+                                "solves_per_s": r3(q["solves_per_s"]), "solved": q["solved"]},
+        })
+        log("[bench] serve rate", rate, "p50", rows[-1]["p50_ms"], "p99", rows[-1]["p99_ms"],
+            "sequential p50", rows[-1]["sequential_fp64"]["p50_ms"], "p99",
+            rows[-1]["sequential_fp64"]["p99_ms"])
+    return {"requests_per_rate": nreq, "budget_bytes": budget,
+            "redrawn_inputs": int(sum(r["redraws"] for r in base)),
+            "input_generation_s": round(gen_s, 2),
+            "latency_rule": "arrival to result-ready (end of the tick that finished the solve); "
+                            "every request counted, a failed one at the time its result was known",
+            "max_newton": 200, "rel_grad_tol": 1e-8, "sweep": rows}
 
 
 # Sec. 4.1, Table tab_kershaw_baseline: GPU runs on 4 V100s with (PA*) and without
@@ -441,6 +563,56 @@ def kershaw_leg(orders, storage="compact"):
     return res
 
 
+def apply_only(args):
+    """Only the Hessian action on a workload's mesh (for rocprofv3 runs)."""
+    import torch
+
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes
+    c = inputs.CONFIGS[args.workload]
+    dim, n, p, nq = c["dim"], c["n"], c["p"], c["nq"]
+    st = ["tensor", "compact"] if args.storage == "both" else [args.storage]
+    pr = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    probe = Context(dim, n, p, nq)
+    buf = torch.empty(probe.ndof, dtype=torch.float64, device="cuda")
+
+    def valid(xh):
+        buf.copy_(torch.as_tensor(xh))
+        return probe.min_det(buf) > 0
+
+    xh, _ = inputs.config_mesh(args.workload, basis_nodes(p), is_valid=valid)
+    probe.close()
+    x = torch.as_tensor(xh).cuda()
+    v = torch.as_tensor(inputs.gaussian_vector(x.numel(), c["vec_seed"])).cuda()
+    y = torch.empty_like(v)
+    out = {}
+    for s in st:
+        for q in pr:
+            ctx = Context(dim, n, p, nq, precision=q, storage=s)
+            ctx.hessian_setup(x)
+            ctx.hessian_apply(v, y)
+            if args.all_kernels:
+                # the other element kernels of the path, reps calls each
+                for _ in range(args.reps):
+                    ctx.energy(x)
+                    ctx.gradient(x, y)
+                    ctx.hessian_setup(x)
+                    ctx.hessian_diag(y)
+            elem, tot = ctx.time_apply(v, y, args.reps)
+            out["%s_%s" % (s, q)] = dict(elem_us=round(elem * 1e3, 2), total_us=round(tot * 1e3, 2),
+                                         elements_per_workgroup=ctx.tile_epb())
+            log("[apply-only]", s, q, out["%s_%s" % (s, q)])
+            ctx.close()
+    if args.copy_ref:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_ref_bytes_each_way"] = src.numel() * 8
+    print(json.dumps(dict(workload=args.workload, dofs=int(x.numel()), actions=out)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,14 +628,23 @@ def main():
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--batch-meshes", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-sweep", default="50,100,200,500,1000,2000",
-                    help="arrival rates (req/s) of the served-stream sweep; empty to skip")
-    ap.add_argument("--serve-sweep-requests", type=int, default=400)
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000",
+                    help="arrival rates (req/s) of the served stream")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--config3", default="c3a,c3b",
+                    help="6.44 M-DoF workloads to run beside the headline; empty to skip")
+    ap.add_argument("--config3-steps", type=int, default=3)
     ap.add_argument("--kershaw-orders", default="1,2,3,4")
     ap.add_argument("--no-kershaw", action="store_true")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="time only the Hessian action (for profilers); see the module docstring")
+    ap.add_argument("--reps", type=int, default=10, help="--apply-only: actions per timing")
+    ap.add_argument("--storage", default="both", choices=["tensor", "compact", "both"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--copy-ref", action="store_true")
+    ap.add_argument("--all-kernels", action="store_true",
+                    help="--apply-only: also run energy, gradient, setup and diagonal reps times")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -480,6 +661,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.apply_only:
+        apply_only(args)
+        return
     cfg = WORKLOADS[args.workload]
     cname, dim, n, p, nq = cfg
     S = dim * dim * (dim * dim + 1) // 2
@@ -578,14 +762,21 @@ def main():
         out[key]["roofline"]["median_action_us"] = round(mm * 1e3, 2)
         cv.close()
 
+    c3_refs = []
+    if args.config3:
+        out["config3"] = {}
+        for name in [w for w in args.config3.split(",") if w]:
+            out["config3"][name], r = config3_leg(name, args.apply_reps, args.config3_steps,
+                                                  args.minres)
+            c3_refs.append(r)
+            log("[bench] config3 %s done" % name)
+
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_meshes)
         log("[bench] batch leg done")
     if not args.no_serve:
-        out["serve"] = serve_leg(args.serve_rate, args.serve_requests)
-        if args.serve_sweep:
-            rates = [float(r) for r in args.serve_sweep.split(",") if r]
-            out["serve"]["sweep"] = serve_sweep(rates, args.serve_sweep_requests)
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        out["serve"] = serve_leg(rates, args.serve_requests)
         log("[bench] serve leg done")
 
     if not args.no_kershaw:
@@ -604,6 +795,9 @@ def main():
         if not args.no_precision:
             out["precision"] = precision_leg(cfg, x0, v, y_oracle)
             log("[bench] precision leg done")
+        for r in c3_refs:
+            out["config3"][r[0]]["hvp_err_vs_oracle_sampled"] = config3_oracle_error(r)
+            log("[bench] config3 %s oracle comparison done" % r[0])
 
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -166,18 +166,22 @@ def batch_specs(count=256, seed=5):
     return out
 
 
-def serving_stream(rate, count=2000, seed=6, max_n3=48):
+def serving_stream(rate, count=2000, seed=6, max_n3=48, same_requests=False):
     """Poisson arrival stream of mixed 2D/3D requests.
 
     Inter-arrival ~ Exp(rate); 50% 2D (mu_2) / 50% 3D (mu_303); element count
     lognormal with median 512 and sigma 1 (log space), truncated to
     [2^d, 48^3]; n = round(E^(1/d)); p ~ U{1..4}; n_q = p + 2.
+    With ``same_requests`` the draw does not depend on the rate: every rate
+    sees the same requests in the same order, with arrival times that are one
+    unit-rate Poisson stream divided by the rate.
     """
-    rng = np.random.default_rng([seed, int(rate)])
+    rng = np.random.default_rng([seed] if same_requests else [seed, int(rate)])
     t = 0.0
     reqs = []
     for k in range(count):
-        t += rng.exponential(1.0 / rate)
+        gap = rng.exponential(1.0) / rate if same_requests else rng.exponential(1.0 / rate)
+        t += gap
         dim = 2 if rng.uniform() < 0.5 else 3
         E = float(np.exp(rng.normal(math.log(512.0), 1.0)))
         E = min(max(E, 2.0 ** dim), float(max_n3) ** 3)
@@ -190,37 +194,42 @@ def serving_stream(rate, count=2000, seed=6, max_n3=48):
 
 
 # ---------------------------------------------------------------------------
-# Kershaw meshes (Sec. 4.1 and its appendix): the benchmark's analytic
-# deformation of a uniform hex mesh of [0,1]^3.  x is unchanged; [0,1] in x is
-# cut into six equal layers; in the first and last layers y (and z) are
-# compressed towards opposite corners by the piecewise-linear maps L and R
-# with slopes set by eps, and the middle layers blend between them with a
-# quintic smoothstep.  eps = 1 gives the uniform mesh.  Boundary faces map to
-# themselves, so boundary nodes only move tangentially.
+# Kershaw meshes (Sec. 4.1; the mesh is fixed by the generator the paper's
+# appendix lists, restated here): x is unchanged; y (and z) is moved by a map
+# that is piecewise linear in t with a kink at t = 1/2.  At the left end the
+# map L packs the elements towards t = 0 ... y-slope eps for t < 1/2 at the low
+# side of the box ... at the right end the mirror map R packs them at the
+# opposite corner, so the high-aspect-ratio elements (aspect 1/eps) sit in
+# opposite corners of the first and last of six equal layers in x.  In
+# between, the map blends the two with a weight s(x) made of clamped quintic
+# smoothsteps: 0 -> 1 across the second layer, back 1 -> 0 across the third
+# and fourth together, 0 -> 1 across the fifth.  eps = 1 gives the uniform
+# mesh; t = 0 and t = 1 stay put, so boundary nodes only move tangentially.
 # ---------------------------------------------------------------------------
 
-def _kershaw_R(eps, t):
-    return np.where(t <= 0.5, (2.0 - eps) * t, 1.0 + eps * (t - 1.0))
-
-
-def _kershaw_L(eps, t):
-    return 1.0 - _kershaw_R(eps, 1.0 - t)
-
-
-def _smoothstep(u):
+def _quintic_step(u):
+    """Smoothstep 10u^3 - 15u^4 + 6u^5 on [0, 1], clamped to 0 / 1 outside."""
     u = np.clip(u, 0.0, 1.0)
-    return u * u * u * (u * (6.0 * u - 15.0) + 10.0)
+    return u ** 3 * (10.0 - 15.0 * u + 6.0 * u * u)
+
+
+def kershaw_blend(x):
+    """Weight s(x) of the right-end map: 0 on the first layer, rising across the
+    second, falling across the third and fourth, rising across the fifth, 1 on
+    the sixth (layers of width 1/6 in x)."""
+    x = np.asarray(x, dtype=np.float64)
+    return _quintic_step(6.0 * x - 1.0) - _quintic_step(3.0 * x - 1.0) + _quintic_step(6.0 * x - 4.0)
 
 
 def kershaw_map(x, t, eps):
-    """Image of coordinate t (y or z) at abscissa x for anisotropy eps."""
-    layer = np.floor(6.0 * x).astype(int)
-    lam = 6.0 * x - layer
-    L, R = _kershaw_L(eps, t), _kershaw_R(eps, t)
-    blend = lambda a, b, u: a + (b - a) * _smoothstep(u)  # noqa: E731
-    return np.select([layer <= 0, (layer == 1) | (layer == 4), layer == 2, layer == 3],
-                     [L, blend(L, R, lam), blend(R, L, lam / 2.0), blend(R, L, (1.0 + lam) / 2.0)],
-                     default=R)
+    """Image of coordinate t (y or z) at abscissa x for anisotropy eps:
+    Y = L(t) + (R(t) - L(t)) s(x), with L and R the piecewise-linear maps of
+    [0, 1] onto itself through (1/2, eps/2) and (1/2, 1 - eps/2)."""
+    t = np.asarray(t, dtype=np.float64)
+    knots = [0.0, 0.5, 1.0]
+    L = np.interp(t, knots, [0.0, 0.5 * eps, 1.0])
+    R = np.interp(t, knots, [0.0, 1.0 - 0.5 * eps, 1.0])
+    return L + (R - L) * kershaw_blend(x)
 
 
 def kershaw_nodes(ns, p, nodes1d, eps_y=0.3, eps_z=0.3):

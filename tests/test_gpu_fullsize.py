@@ -102,3 +102,27 @@ def test_config2_minres_full():
     assert itg == ito == 20
     assert e <= 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["c3a", "c3b"])
+def test_config3_mixed_solve_final_energy(name):
+    """64^3 Q2 and 32^3 Q4: solves to |g|/|g0| <= 1e-8 with the FP32 action inside
+    MINRES (tensor and compact storage) end at the FP64 tensor solve's energy within
+    1e-10 relative."""
+    from paper_2205_12721_amd.tmop import Context
+    c = inputs.CONFIGS[name]
+    pb_full = oracle.Problem.box(3, c["n"], c["p"], c["nq"])
+    x, _ = inputs.config_mesh(name, basis.gll_nodes(c["p"]), is_valid=lambda x: pb_full.min_det(x) > 0)
+    res = {}
+    for storage, prec in (("tensor", "fp64"), ("tensor", "mixed"), ("compact", "mixed")):
+        ctx = Context(3, c["n"], c["p"], c["nq"], precision=prec, storage=storage)
+        xd = to_dev(x)
+        rep = ctx.solve(xd, rel_grad_tol=1e-8, max_newton=100)
+        ctx.close()
+        assert rep["status"] == 0, rep
+        res[(storage, prec)] = (rep["F"], to_host(xd), rep["newton_its"])
+    F64, x64, _ = res[("tensor", "fp64")]
+    for k, (F, xs, its) in res.items():
+        eF = abs(F - F64) / abs(F64)
+        log(name, k, "newton", its, "F rel diff %.2e" % eF, "x rel %.2e" % rel(xs, x64))
+        assert eF <= 1e-10

@@ -1,5 +1,7 @@
 """Serving loop (continuous batching over a pool): a small Poisson stream with a
-budget below the stream's total footprint, so requests wait for memory.
+budget below the stream's total footprint, so requests wait for memory.  The
+stream's sizes reach 16^3 elements (this draw holds 12^3 Q4, 14^3 Q3, 10^3 and
+9^3 hexes and 38^2 and 23^2 quads beside smaller meshes).
 
 * every request is solved, and its nodes are bitwise identical to the same
   request solved alone in its own pool (same arithmetic alone and in the mix);
@@ -15,7 +17,8 @@ pytestmark = pytest.mark.gpu
 
 def test_stream_alone_equals_mix():
     from paper_2205_12721_amd import inputs, serve
-    reqs = inputs.serving_stream(400.0, count=14, seed=16, max_n3=8)
+    reqs = inputs.serving_stream(400.0, count=14, seed=17, max_n3=16)
+    assert sum(1 for r in reqs if r["n"] ** r["dim"] > 8 ** 3) >= 5
     xs = serve.make_inputs(reqs)
     total = serve.budget_for(reqs)
     budget = serve.budget_for(reqs, factor=0.4)

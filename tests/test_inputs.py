@@ -28,6 +28,21 @@ def test_kershaw_hand_values(x, t, eps, expected):
     assert abs(v - expected) < 1e-14
 
 
+def test_kershaw_blend_weight():
+    """The right-end weight s(x): 0 on the first layer, 1 on the last, 1 at x = 1/3
+    and 0 at x = 2/3 (the third and fourth layers fall from 1 to 0 together),
+    continuous, and a quintic smoothstep across the second layer."""
+    s = inputs.kershaw_blend
+    assert np.all(s(np.linspace(0.0, 1.0 / 6.0, 11)) == 0.0)
+    assert np.allclose(s(np.linspace(5.0 / 6.0, 1.0, 11)), 1.0, atol=1e-15)
+    assert abs(s(1.0 / 3.0) - 1.0) < 1e-15 and abs(s(2.0 / 3.0)) < 1e-15
+    assert abs(s(0.5) - 0.5) < 1e-15          # middle of the falling double layer
+    u = 0.3
+    assert abs(s((1.0 + u) / 6.0) - (10 * u ** 3 - 15 * u ** 4 + 6 * u ** 5)) < 1e-15
+    xs = np.linspace(0.0, 1.0, 6001)
+    assert np.abs(np.diff(s(xs))).max() < 3e-3  # continuous (step 1/6000)
+
+
 def test_kershaw_properties():
     x = np.linspace(0, 1, 61)
     t = np.linspace(0, 1, 41)
