@@ -48,15 +48,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "51e2152862bb56a4180418879eb416b85e791b7bda4b85aac0bf3e895f4c4e1c"
+_SHA_C2 = "89a4952fede496624256444c7e6bc6140a33fef5551834276f196b44277106d5"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 720835530, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 719741919, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366402918, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 366610605, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 246732089, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 245084945, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135270218, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135357549, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
@@ -525,19 +525,23 @@ KERSHAW_PAPER = {
 }
 
 
-def kershaw_leg(orders, storage="compact"):
+def kershaw_leg(orders, storage="compact", cuts=()):
     """Kershaw benchmark (Sec. 4.1): 24^3 hexes, eps_y = eps_z = 0.3, 9^3 points per
     element, mu_303, at most 50 MINRES iterations per Newton step, with the Jacobi
     preconditioner ("PA*") and without ("PA"), stop at |g|/|g0| <= 1e-10; boundary nodes
     slide along their faces.  Gauss-Legendre points, and for the unpreconditioned solve
-    also the 9-point Gauss-Lobatto rule ("PA_gll").  Time to solution on one GPU, FP64,
-    next to the paper's 4-V100 numbers (context, not a like-for-like target)."""
+    also the 9-point Gauss-Lobatto rule ("PA_gll"); with ``cuts`` also the preconditioned
+    solve with MINRES cut at that many iterations per Newton step ("PA*_minresN").  Time to
+    solution on one GPU, FP64, next to the paper's 4-V100 numbers (context, not a
+    like-for-like target)."""
     import torch
     from paper_2205_12721_amd import inputs
     from paper_2205_12721_amd.tmop import Context, basis_nodes
     ns = (24, 24, 24)
     res = {"storage": storage}
-    for jac, key, quad in ((True, "PA*", "gl"), (False, "PA", "gl"), (False, "PA_gll", "gll")):
+    rows = [(True, "PA*", "gl", 50), (False, "PA", "gl", 50), (False, "PA_gll", "gll", 50)]
+    rows += [(True, "PA*_minres%d" % c, "gl", c) for c in cuts]
+    for jac, key, quad, max_minres in rows:
         res[key] = {}
         for p in orders:
             mask = torch.as_tensor(inputs.sliding_mask(ns, p)).cuda()
@@ -548,7 +552,7 @@ def kershaw_leg(orders, storage="compact"):
             x.copy_(x0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rep = ctx.solve(x, rel_grad_tol=1e-10, max_newton=300, max_minres=50, jacobi=jac)
+            rep = ctx.solve(x, rel_grad_tol=1e-10, max_newton=300, max_minres=max_minres, jacobi=jac)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ctx.close()
@@ -637,6 +641,8 @@ def main():
     ap.add_argument("--config3-steps", type=int, default=3)
     ap.add_argument("--kershaw-orders", default="1,2,3,4")
     ap.add_argument("--no-kershaw", action="store_true")
+    ap.add_argument("--kershaw-minres-cuts", default="20",
+                    help="MINRES iteration caps of extra preconditioned Kershaw rows; empty for none")
     ap.add_argument("--apply-only", action="store_true",
                     help="time only the Hessian action (for profilers); see the module docstring")
     ap.add_argument("--reps", type=int, default=10, help="--apply-only: actions per timing")
@@ -780,7 +786,8 @@ def main():
         log("[bench] serve leg done")
 
     if not args.no_kershaw:
-        out["kershaw"] = kershaw_leg([int(v) for v in args.kershaw_orders.split(",") if v])
+        out["kershaw"] = kershaw_leg([int(v) for v in args.kershaw_orders.split(",") if v],
+                                     cuts=[int(v) for v in args.kershaw_minres_cuts.split(",") if v])
         log("[bench] kershaw leg done")
 
     if not args.no_copy_bw:
