@@ -21,6 +21,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --apply-only [--workload c2] [--reps 10]
            [--storage tensor|compact|both] [--precision fp64|mixed|both] [--copy-ref]
            [--all-kernels]
+       python bench.py --batch-only [--batch-meshes 256]
 
 ``--apply-only`` runs only the Hessian action, for profilers: one setup per
 variant on the workload's mesh, then 2 x reps actions back to back on the
@@ -434,9 +435,10 @@ def config3_oracle_error(ref):
     return out
 
 
-def batch_leg(count):
+def batch_leg(count, sequential=True):
     """256 independent hex meshes (log-uniform sizes, p = 1..4, n_q = p+2, mu_303):
-    one batched mixed-precision solve vs one-mesh-at-a-time FP64 solves."""
+    one batched mixed-precision solve (one graph launch per Newton step) vs
+    one-mesh-at-a-time FP64 solves (skipped with sequential=False)."""
     import torch
     from paper_2205_12721_amd import inputs
     from paper_2205_12721_amd.tmop import Context, basis_nodes, batch_solve, request, solve_params
@@ -452,6 +454,10 @@ def batch_leg(count):
     reps = batch_solve(reqs, xd, sps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    if not sequential:
+        return {"meshes": count, "dofs_total": int(ndof), "batched_mixed_s": round(tb, 4),
+                "solved_batched": sum(1 for r in reps if r["status"] == 0),
+                "newton_its_batched": int(sum(r["newton_its"] for r in reps))}
     t0 = time.perf_counter()
     seq = []
     for s, x in zip(specs, xs):
@@ -649,6 +655,8 @@ def main():
     ap.add_argument("--storage", default="both", choices=["tensor", "compact", "both"])
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--copy-ref", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched solve (no sequential loop), for profilers")
     ap.add_argument("--all-kernels", action="store_true",
                     help="--apply-only: also run energy, gradient, setup and diagonal reps times")
     args = ap.parse_args()
@@ -669,6 +677,10 @@ def main():
     torch.cuda.set_device(0)
     if args.apply_only:
         apply_only(args)
+        return
+    if args.batch_only:
+        # the batched solve alone, for profilers
+        print(json.dumps(batch_leg(args.batch_meshes, sequential=False)), flush=True)
         return
     cfg = WORKLOADS[args.workload]
     cname, dim, n, p, nq = cfg

@@ -319,7 +319,19 @@ int tmop_pool_release(tmop_pool *pool, int slot);
 /* Bytes in use, budget, and occupied slots. */
 int tmop_pool_info(tmop_pool *pool, size_t *used_bytes, size_t *budget_bytes, int *slots_used);
 
-/* Enable (default) or disable HIP-graph replay of the MINRES iterations. */
+/* HIP-graph replay of the pool's Newton steps (Sec. 2.3):
+ *   0  no graphs: every launch issued by the host;
+ *   1  (default) a block of six lockstep MINRES iterations captured once and
+ *      replayed, the host checking every twelve iterations whether any slot
+ *      still iterates, and deciding each line-search round;
+ *   2  the whole Newton step captured once per pool layout and replayed once
+ *      per tmop_pool_step: setup, Jacobi diagonal, every MINRES iteration
+ *      (slots stop on the device), the first two line-search rounds and the
+ *      stop test, with accept / halve decided per slot on the device; the
+ *      host reads the per-slot state back once per step, and runs any further
+ *      line-search rounds one by one (a slot still halving after two).
+ * Every mode gives bitwise the same iterates.  Other values:
+ * TMOP_ERR_INVALID_ARG. */
 int tmop_pool_set_graph(tmop_pool *pool, int enable);
 
 /* Enable or disable (default) resident MINRES Lanczos vectors for solves
@@ -344,7 +356,9 @@ int tmop_pool_autotune(tmop_pool *pool, int reps);
 const char *tmop_pool_last_error(void);
 
 /* Solve count independent meshes together (a pool sized to fit them all,
- * Hessian-action tile shapes autotuned per kernel class after admission):
+ * resident Lanczos vectors, Hessian-action tile shapes autotuned per kernel
+ * class after admission, each Newton step one replay of a HIP graph as in
+ * tmop_pool_set_graph mode 2):
  * x_devs[k] holds mesh k's nodes on entry and the optimised nodes on return;
  * reps[k] its report.  Returns the first error, if any. */
 int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const tmop_params *prms,

@@ -572,6 +572,113 @@ __global__ __launch_bounds__(VB) void kv_mr_finish(const VTile *__restrict__ vt,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Newton step decisions on the device (Sec. 2.3), for the whole-step graph:
+// one thread per slot.  The host mirror of NState is uploaded before a step
+// and read back after it; in between the line search (accept a trial when
+// det A > 0 at every point, F_t < 1.2 F and |g_t| < 1.2 |g|, else halve
+// alpha) and the stop test run here, with the same comparisons the host
+// makes in the eager step.
+// ---------------------------------------------------------------------------
+struct NState {
+    double F, gn, g0, tol, alpha, Ft;
+    int newton_its, max_newton, minres_its, halvings, max_halvings, status, phase, searching;
+};
+enum { NS_ITER = 1, NS_DONE = 2 };
+
+// after MINRES: iteration count, breakdown check, alpha = 1 and the search gate
+__global__ __launch_bounds__(VB) void kn_after_minres(int M, const int *__restrict__ gate,
+                                                      const BState *__restrict__ st,
+                                                      NState *__restrict__ ns,
+                                                      int *__restrict__ search,
+                                                      double *__restrict__ sc)
+{
+    const int s = blockIdx.x * VB + threadIdx.x;
+    if (s >= M) return;
+    search[s] = 0;
+    if (!gate[s]) return;
+    const BState &a = st[2 * s], &b = st[2 * s + 1];
+    const BState &f = a.j >= b.j ? a : b;
+    NState &n = ns[s];
+    n.minres_its += f.j;
+    n.alpha = 1.0;
+    sc[s * NSC + SC_ALPHA] = 1.0;
+    if (f.indefinite) {
+        n.status = TMOP_ERR_NONFINITE;
+        n.phase = NS_DONE;
+        return;
+    }
+    n.searching = 1;
+    search[s] = 1;
+}
+
+// trial energy test: det A > 0 at every point and F_t < 1.2 F
+__global__ __launch_bounds__(VB) void kn_ls_trial(int M, const int *__restrict__ search,
+                                                  const double *__restrict__ sc,
+                                                  NState *__restrict__ ns, int *__restrict__ ftest)
+{
+    const int s = blockIdx.x * VB + threadIdx.x;
+    if (s >= M) return;
+    ftest[s] = 0;
+    if (!search[s]) return;
+    const double *c = sc + s * NSC;
+    NState &n = ns[s];
+    n.Ft = c[SC_F];
+    ftest[s] = (c[SC_BAD] == 0.0 && c[SC_MD] > 0.0 && c[SC_F] < 1.2 * n.F) ? 1 : 0;
+}
+
+// gradient test |g_t| < 1.2 |g| and the decision of round h: accept (the
+// copies x_t -> x, g_t -> g follow, gated by acc) or halve alpha; a slot out
+// of halvings ends with TMOP_ERR_LINESEARCH
+__global__ __launch_bounds__(VB) void kn_ls_decide(int M, int h, int *__restrict__ search,
+                                                   const int *__restrict__ ftest,
+                                                   double *__restrict__ sc, NState *__restrict__ ns,
+                                                   int *__restrict__ acc)
+{
+    const int s = blockIdx.x * VB + threadIdx.x;
+    if (s >= M) return;
+    acc[s] = 0;
+    if (!search[s]) return;
+    NState &n = ns[s];
+    if (ftest[s]) {
+        const double gtn = sqrt(sc[s * NSC + SC_DOT]);
+        if (gtn < 1.2 * n.gn) {
+            n.F = n.Ft;
+            n.gn = gtn;
+            n.newton_its++;
+            n.searching = 0;
+            search[s] = 0;
+            acc[s] = 1;
+            return;
+        }
+    }
+    n.halvings++;
+    n.alpha *= 0.5;
+    sc[s * NSC + SC_ALPHA] = n.alpha;
+    if (h >= n.max_halvings) {
+        n.searching = 0;
+        search[s] = 0;
+        n.status = TMOP_ERR_LINESEARCH;
+        n.phase = NS_DONE;
+    }
+}
+
+// stop test of the slots that finished their line search this step
+__global__ __launch_bounds__(VB) void kn_end(int M, const int *__restrict__ gate, NState *__restrict__ ns)
+{
+    const int s = blockIdx.x * VB + threadIdx.x;
+    if (s >= M || !gate[s]) return;
+    NState &n = ns[s];
+    if (n.phase != NS_ITER || n.searching) return;
+    if (n.F == 0.0 || n.gn <= n.tol * n.g0) {
+        n.status = TMOP_OK;
+        n.phase = NS_DONE;
+    } else if (n.newton_its >= n.max_newton) {
+        n.status = TMOP_ERR_NOT_CONVERGED;
+        n.phase = NS_DONE;
+    }
+}
+
 }  // namespace tmop
 
 // ===========================================================================
@@ -760,12 +867,27 @@ struct tmop_pool {
     // resident MINRES Lanczos vectors for slots whose region fits the budget
     // (opt-in: such a slot takes more of the budget)
     bool use_bank = false;
-    // graph of six MINRES iterations
-    bool use_graph = true;
+    // HIP graphs: 0 none, 1 a block of six MINRES iterations replayed,
+    // 2 the whole Newton step (setup, diagonal, every MINRES iteration, the
+    // first LS_ROUNDS line-search rounds and the stop test) replayed once
+    // per step
+    int graph_mode = 1;
     bool graph_ok = false;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    bool sgraph_ok = false;
+    int sg_maxj = -1;
+    hipGraphExec_t sgexec = nullptr;
+    hipGraph_t sgraph = nullptr;
+    // per-slot Newton state on the device (graph mode 2) and its host mirror;
+    // gates of the device line search
+    NState *d_ns = nullptr, *h_ns = nullptr;
+    int *d_search = nullptr, *d_ftest = nullptr, *d_acc = nullptr;
 };
+
+// line-search rounds inside the whole-step graph; a slot still searching
+// after them continues in rounds launched one by one
+constexpr int LS_ROUNDS = 2;
 
 static void pool_free_region(tmop_pool *P, size_t off, size_t bytes)
 {
@@ -814,6 +936,12 @@ static void invalidate_graph(tmop_pool *P)
     P->gexec = nullptr;
     P->graph = nullptr;
     P->graph_ok = false;
+    if (P->sgexec) hipGraphExecDestroy(P->sgexec);
+    if (P->sgraph) hipGraphDestroy(P->sgraph);
+    P->sgexec = nullptr;
+    P->sgraph = nullptr;
+    P->sgraph_ok = false;
+    P->sg_maxj = -1;
 }
 
 // Rebuild tile lists, vector tiles, ranges and partial layout for the used slots.
@@ -1052,7 +1180,7 @@ static int run_minres(tmop_pool *P, int maxj)
     hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_gate[1], P->d_rg, vpart1(P), P->d_maxit, P->d_rtol, P->d_st, P->d_run, P->d_slots);
     int j = 0;
     while (j < maxj) {
-        if (P->use_graph && maxj - j >= 6) {
+        if (P->graph_mode == 1 && maxj - j >= 6) {
             if (!P->graph_ok) {
                 PHIP(hipStreamBeginCapture(P->s, hipStreamCaptureModeThreadLocal));
                 for (int k = 0; k < 6; ++k) minres_iter(P, k);
@@ -1092,6 +1220,111 @@ static void finish_slot(SlotH &s, int status)
     s.phase = PH_DONE;
     s.status = status;
     s.t_done = now_ms();
+}
+
+static int nblk(int n) { return (n + VB - 1) / VB; }
+
+// one line-search round h of every searching slot, decided on the device
+static void ls_round_device(tmop_pool *P, int h)
+{
+    const int M = P->max_slots, nv = nvt_all(P);
+    hipLaunchKernelGGL(kv_step, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_search, P->d_sc);
+    energy_to_sc(P, P->d_search, BXT);
+    hipLaunchKernelGGL(kn_ls_trial, dim3(nblk(M)), dim3(VB), 0, P->s, M, P->d_search, P->d_sc, P->d_ns, P->d_ftest);
+    gradient_to(P, P->d_ftest, BXT, BGT);
+    dot_to_sc(P, P->d_ftest, BGT, BGT, SC_DOT);
+    hipLaunchKernelGGL(kn_ls_decide, dim3(nblk(M)), dim3(VB), 0, P->s, M, h, P->d_search, P->d_ftest, P->d_sc, P->d_ns, P->d_acc);
+    hipLaunchKernelGGL(kv_copy, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_acc, BXT, BX);
+    hipLaunchKernelGGL(kv_copy, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_acc, BGT, BG);
+}
+
+// The Newton step of every iterating slot (gate 1) as one stream of launches
+// with no host decision: setup, Jacobi diagonal, maxj lockstep MINRES
+// iterations (slots stop on the device), LS_ROUNDS line-search rounds and the
+// stop test.  Captured once per layout and replayed.
+static void record_step(tmop_pool *P, int maxj)
+{
+    const int M = P->max_slots, nv = nvt_all(P);
+    const int *g1 = P->d_gate[1];
+    launch_elem(P, 2, g1, BX);  // setup
+    launch_elem(P, 4, g1, BX);  // diagonal
+    launch_gather(P, g1, BDIAG, 1, BDIAG, false);
+    hipLaunchKernelGGL(kv_absmax, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, BDIAG, vpart1(P));
+    hipLaunchKernelGGL(kr_vec, dim3(M), dim3(VB), 0, P->s, P->d_rg, g1, vpart1(P), 1, SC_DMAX, P->d_sc);
+    hipLaunchKernelGGL(kv_jacobi, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, P->d_sc);
+    hipLaunchKernelGGL(kv_mr_init, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, P->d_jac, vpart1(P));
+    hipLaunchKernelGGL(kv_mr_start, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, P->d_rg, vpart1(P), P->d_maxit, P->d_rtol, P->d_st, P->d_run, P->d_slots);
+    for (int j = 0; j < maxj; ++j) minres_iter(P, j % 6);
+    if (maxj > 0) {
+        const int k = (maxj - 1) % 6, par = k & 1;
+        const int *W = MR_W[(maxj - 1) % 3];
+        hipLaunchKernelGGL(kv_mr_finish, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g1, P->d_rg, P->d_st, par, vpart1_at(P, par), vpart2(P), mr_zc(k), W[2], W[0], W[1], P->d_run);
+    }
+    hipLaunchKernelGGL(kn_after_minres, dim3(nblk(M)), dim3(VB), 0, P->s, M, g1, P->d_st, P->d_ns, P->d_search, P->d_sc);
+    for (int h = 0; h < LS_ROUNDS; ++h) ls_round_device(P, h);
+    hipLaunchKernelGGL(kn_end, dim3(nblk(M)), dim3(VB), 0, P->s, M, g1, P->d_ns);
+}
+
+// Newton step with the decisions on the device (graph mode 2): upload the
+// Newton state, replay the step graph, read the state back once; rounds
+// beyond LS_ROUNDS (rare) follow one by one, each with a read-back.
+static int step_device(tmop_pool *P, int maxj, int maxh)
+{
+    const int M = P->max_slots;
+    for (int si = 0; si < M; ++si) {
+        const SlotH &s = P->slots[si];
+        NState &n = P->h_ns[si];
+        n.F = s.F;
+        n.gn = s.gn;
+        n.g0 = s.g0;
+        n.tol = s.sp.rel_grad_tol;
+        n.alpha = 1.0;
+        n.Ft = 0.0;
+        n.newton_its = s.newton_its;
+        n.max_newton = s.sp.max_newton;
+        n.minres_its = s.minres_its;
+        n.halvings = s.halvings;
+        n.max_halvings = s.sp.max_halvings;
+        n.status = s.status;
+        n.phase = s.used ? s.phase : PH_DONE;
+        n.searching = 0;
+    }
+    PHIP(hipMemcpyAsync(P->d_ns, P->h_ns, sizeof(NState) * M, hipMemcpyHostToDevice, P->s));
+    if (!P->sgraph_ok || P->sg_maxj != maxj) {
+        if (P->sgexec) hipGraphExecDestroy(P->sgexec);
+        if (P->sgraph) hipGraphDestroy(P->sgraph);
+        P->sgexec = nullptr;
+        P->sgraph = nullptr;
+        PHIP(hipStreamBeginCapture(P->s, hipStreamCaptureModeThreadLocal));
+        record_step(P, maxj);
+        PHIP(hipStreamEndCapture(P->s, &P->sgraph));
+        PHIP(hipGraphInstantiate(&P->sgexec, P->sgraph, nullptr, nullptr, 0));
+        P->sgraph_ok = true;
+        P->sg_maxj = maxj;
+    }
+    PHIP(hipGraphLaunch(P->sgexec, P->s));
+    for (int h = LS_ROUNDS;; ++h) {
+        PHIP(hipMemcpyAsync(P->h_ns, P->d_ns, sizeof(NState) * M, hipMemcpyDeviceToHost, P->s));
+        PHIP(hipStreamSynchronize(P->s));
+        bool searching = false;
+        for (int si = 0; si < M; ++si) searching = searching || (P->h_gate[1][si] && P->h_ns[si].searching);
+        if (!searching || h > maxh) break;
+        ls_round_device(P, h);
+        hipLaunchKernelGGL(kn_end, dim3(nblk(M)), dim3(VB), 0, P->s, M, P->d_gate[1], P->d_ns);
+    }
+    PHIP(hipGetLastError());
+    for (int si = 0; si < M; ++si) {
+        if (!P->h_gate[1][si]) continue;
+        SlotH &s = P->slots[si];
+        const NState &n = P->h_ns[si];
+        s.F = n.F;
+        s.gn = n.gn;
+        s.newton_its = n.newton_its;
+        s.minres_its = n.minres_its;
+        s.halvings = n.halvings;
+        if (n.phase == NS_DONE) finish_slot(s, n.status);
+    }
+    return TMOP_OK;
 }
 
 // One Newton iteration for every active slot (initial evaluation first for new slots).
@@ -1161,6 +1394,15 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
         }
         PHIP(hipMemcpyAsync(P->d_maxit, P->h_gate[4], sizeof(int) * M, hipMemcpyHostToDevice, P->s));
         PHIP(hipMemcpyAsync(P->d_rtol, P->h_rtol, sizeof(double) * M, hipMemcpyHostToDevice, P->s));
+        if (P->graph_mode == 2) {
+            for (int si = 0; si < M; ++si)
+                if (P->h_gate[1][si]) P->slots[si].h_ready = true;
+            PCHK(step_device(P, maxj, maxh));
+            int na = 0;
+            for (auto &s : P->slots) na += (s.used && s.phase != PH_DONE) ? 1 : 0;
+            if (n_active) *n_active = na;
+            return TMOP_OK;
+        }
         const int *g1 = P->d_gate[1];
         launch_elem(P, 2, g1, BX);   // setup
         for (int si = 0; si < M; ++si)
@@ -1300,6 +1542,11 @@ extern "C" int tmop_pool_create(tmop_pool **out, size_t budget, int max_slots, v
     if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_sc, sizeof(double) * NSC * max_slots, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_st, sizeof(BState) * 2 * max_slots, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_int, sizeof(int) * max_slots, 0);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_ns, sizeof(NState) * max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&P->h_ns, sizeof(NState) * max_slots, 0);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_search, sizeof(int) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_ftest, sizeof(int) * max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_acc, sizeof(int) * max_slots);
     if (e != hipSuccess) {
         tmop_pool_destroy(P);
         return pfail(e == hipErrorOutOfMemory ? TMOP_ERR_OOM : TMOP_ERR_HIP,
@@ -1340,6 +1587,11 @@ extern "C" int tmop_pool_destroy(tmop_pool *P)
     if (P->h_sc) hipHostFree(P->h_sc);
     if (P->h_st) hipHostFree(P->h_st);
     if (P->h_int) hipHostFree(P->h_int);
+    hipFree(P->d_ns);
+    if (P->h_ns) hipHostFree(P->h_ns);
+    hipFree(P->d_search);
+    hipFree(P->d_ftest);
+    hipFree(P->d_acc);
     if (P->s && P->own_stream) hipStreamDestroy(P->s);
     delete P;
     return TMOP_OK;
@@ -1671,7 +1923,8 @@ extern "C" int tmop_pool_set_lanczos_bank(tmop_pool *P, int enable)
 extern "C" int tmop_pool_set_graph(tmop_pool *P, int enable)
 {
     if (!P) return pfail(TMOP_ERR_INVALID_ARG, "null pool");
-    P->use_graph = enable != 0;
+    if (enable < 0 || enable > 2) return pfail(TMOP_ERR_INVALID_ARG, "graph mode must be 0, 1 or 2");
+    P->graph_mode = enable;
     invalidate_graph(P);
     return TMOP_OK;
 }
@@ -1696,6 +1949,8 @@ extern "C" int tmop_batch_solve(int count, const tmop_mesh_desc *meshes, const t
     tmop_pool *P = nullptr;
     PCHK(tmop_pool_create(&P, total, count, stream));
     P->use_bank = true;
+    // one graph launch per Newton step: the batch's layout never changes
+    P->graph_mode = 2;
     std::vector<int> slot(count, -1);
     int r = TMOP_OK;
     for (int k = 0; k < count && r == TMOP_OK; ++k)

@@ -436,14 +436,17 @@ class Pool:
     """Many solves advanced together (see tmop_pool_* in include/tmop.h)."""
 
     def __init__(self, hbm_budget, max_slots, graph=True, lanczos_bank=False):
+        """``graph``: 0 (or False) no HIP graphs, 1 (or True) a replayed block of
+        six MINRES iterations, 2 the whole Newton step replayed once per step."""
         import torch
         self._torch = torch
         h = ctypes.c_void_p()
         _pcheck(lib().tmop_pool_create(ctypes.byref(h), int(hbm_budget), int(max_slots), None))
         self._h = h
         self._keep = {}
-        if not graph:
-            _pcheck(lib().tmop_pool_set_graph(h, 0))
+        mode = (1 if graph else 0) if isinstance(graph, bool) else int(graph)
+        if mode != 1:
+            _pcheck(lib().tmop_pool_set_graph(h, mode))
         if lanczos_bank:
             _pcheck(lib().tmop_pool_set_lanczos_bank(h, 1))
 

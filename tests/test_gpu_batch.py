@@ -186,3 +186,79 @@ def test_admission_budget_and_busy():
     while pool.step() > 0:
         pass
     pool.close()
+
+
+def _kershaw_case():
+    """Kershaw 6x2x2 Q2 (eps 0.3) with sliding boundary nodes: its line searches
+    halve the step up to several times (12 halvings in 11 Newton steps), more
+    than the rounds the whole-step graph holds."""
+    import torch
+    from paper_2205_12721_amd.tmop import request
+    ns, p = (6, 2, 2), 2
+    mask = inputs.sliding_mask(ns, p)
+    x = inputs.kershaw_nodes(ns, p, basis.gll_nodes(p), 0.3, 0.3)
+    mdev = torch.as_tensor(mask).cuda()
+    md, prm = request(3, ns, p, 4, precision="fp64", storage="tensor", ess=mdev)
+    return md, prm, x, mask, mdev
+
+
+@pytest.mark.parametrize("bank", [False, True])
+def test_whole_step_graph_bitwise(bank):
+    """Newton steps replayed as one graph (line search and stop test decided on the
+    device) give bitwise the nodes, energies and counts of the eager step and of the
+    six-iteration MINRES graph, for a heterogeneous mix plus a mesh whose line
+    searches run past the graph's rounds."""
+    from paper_2205_12721_amd.tmop import Pool, request_bytes, solve_params
+    kmd, kprm, kx, _, kmask = _kershaw_case()
+    reqs = [_req(c) for c in MIX] + [(kmd, kprm)]
+    x0s = [_mesh(c)[1] for c in MIX] + [kx]
+    total = sum(request_bytes(*r) for r in reqs)
+    res = {}
+    for mode in (0, 1, 2):
+        pool = Pool((8 if bank else 1) * total, len(reqs), graph=mode, lanczos_bank=bank)
+        xs = [to_dev(x) for x in x0s]
+        slots = [pool.admit(md, prm, solve_params(rel_grad_tol=1e-10), x)
+                 for (md, prm), x in zip(reqs, xs)]
+        steps = 0
+        while pool.step() > 0:
+            steps += 1
+        out = []
+        for s, x in zip(slots, xs):
+            done, rep = pool.poll(s)
+            assert done
+            pool.result(s, x)
+            out.append((to_host(x), rep))
+        pool.close()
+        res[mode] = out
+        log("graph mode", mode, "steps", steps, [(r["status"], r["newton_its"], r["halvings_total"])
+                                                for _, r in out])
+    assert res[0][-1][1]["halvings_total"] > 2
+    for mode in (1, 2):
+        for (xa, ra), (xb, rb) in zip(res[0], res[mode]):
+            assert np.array_equal(xa, xb)
+            for k in ("status", "newton_its", "minres_its_total", "halvings_total", "F", "g_norm"):
+                assert ra[k] == rb[k], (mode, k, ra[k], rb[k])
+
+
+def test_whole_step_graph_kershaw_matches_oracle():
+    """The Kershaw mesh's pooled solve with whole-step graphs against the oracle's
+    Newton solve (sliding boundary nodes): nodes within 1e-9 relative."""
+    import oracle
+    from paper_2205_12721_amd.tmop import Pool, request_bytes, solve_params
+    md, prm, x0, mask, _ = _kershaw_case()
+    pool = Pool(request_bytes(md, prm), 1, graph=2)
+    xd = to_dev(x0)
+    sl = pool.admit(md, prm, solve_params(rel_grad_tol=1e-10), xd)
+    while pool.step() > 0:
+        pass
+    done, rep = pool.poll(sl)
+    pool.result(sl, xd)
+    pool.close()
+    pb0 = oracle.Problem.box(3, (6, 2, 2), 2, 4)
+    pb = oracle.Problem(3, 2, 4, pb0.e2n, pb0.nx, ess=mask.astype(bool))
+    xo, ro = oracle.newton_solve(pb, x0, rel_grad_tol=1e-10, max_newton=200)
+    e = rel(to_host(xd), xo)
+    log("kershaw pooled", rep["newton_its"], rep["halvings_total"], "oracle", ro["newton_its"],
+        ro["halvings_total"], "x rel %.2e" % e)
+    assert done and rep["status"] == 0 and ro["status"] == 0
+    assert e <= TOLX
