@@ -274,6 +274,20 @@ int tmop_pool_admit(tmop_pool *pool, const tmop_mesh_desc *mesh, const tmop_para
                     const tmop_solve_params *sp, const double *x_dev, void *src_stream,
                     int *slot);
 
+/* Admit one solve whose objective carries the limiting term (Sec. 2.2, eq.
+ * eq_F_full, second integral; Sec. 3.5, eq. eq_pa_limiting), as
+ * tmop_set_limiting does for a context: F gains coef * sum_E int_{E_t}
+ * |x - x0|^2 / delta^2, with its gradient and its mass-like Hessian.
+ * x0_dev: device [dim*N_x] reference nodes, copied into the slot's region
+ * (read after the work queued on src_stream); coef >= 0 and delta > 0, else
+ * TMOP_ERR_INVALID_ARG; coef = 0 admits a plain solve.  The region is
+ * tmop_pool_request_bytes plus the reference nodes (d*N_x doubles rounded
+ * up to 256 bytes).  Slots with the term run their own kernel launches (the
+ * Hessian action in its base tile shape).  Otherwise as tmop_pool_admit. */
+int tmop_pool_admit_limited(tmop_pool *pool, const tmop_mesh_desc *mesh, const tmop_params *prm,
+                            const tmop_solve_params *sp, const double *x_dev, const double *x0_dev,
+                            double coef, double delta, void *src_stream, int *slot);
+
 /* Advance every unfinished solve by one Newton iteration (new solves first
  * get their initial energy, det check and gradient).  *n_active receives the
  * number of unfinished solves.  Synchronises the pool's stream. */

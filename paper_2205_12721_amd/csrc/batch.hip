@@ -719,11 +719,14 @@ double now_ms()
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
+// a kernel class: slots with the limiting term (lim = 1) launch their own
+// kernel variants
 struct ClassKey {
-    int dim, p, nq, storage, prec;
+    int dim, p, nq, storage, prec, lim;
     bool operator<(const ClassKey &o) const
     {
-        return std::tie(dim, p, nq, storage, prec) < std::tie(o.dim, o.p, o.nq, o.storage, o.prec);
+        return std::tie(dim, p, nq, storage, prec, lim) <
+               std::tie(o.dim, o.p, o.nq, o.storage, o.prec, o.lim);
     }
 };
 
@@ -748,6 +751,7 @@ enum { PH_NEW = 0, PH_ITER = 1, PH_DONE = 2 };
 struct SlotH {
     bool used = false;
     int dim = 0, p = 0, nq = 0, storage = 0, prec = 0;
+    int lim = 0;  // the slot carries the limiting term
     int ne = 0, nx = 0, ndof = 0, nqe = 0, np = 0, S = 0;
     size_t off = 0, bytes = 0;
     SlotDev dev{};
@@ -956,7 +960,7 @@ static int pool_rebuild(tmop_pool *P)
     for (int si = 0; si < P->max_slots; ++si) {
         SlotH &s = P->slots[si];
         if (!s.used) continue;
-        ClassKey k{s.dim, s.p, s.nq, s.storage, s.prec};
+        ClassKey k{s.dim, s.p, s.nq, s.storage, s.prec, s.lim};
         auto it = P->classes.find(k);
         if (it == P->classes.end()) {
             ClassH c;
@@ -966,9 +970,10 @@ static int pool_rebuild(tmop_pool *P)
             if (internal_tables(s.p, s.nq, &c.tb) != TMOP_OK)
                 return pfail(TMOP_ERR_INVALID_ARG, "bad order / quadrature");
             // start from the tile shape recorded for the class by the autotuner
+            // (classes with the limiting term keep the base shape)
             const int tt = tuned_tile(s.dim, s.p, s.nq, s.storage ? TMOP_HESS_COMPACT : TMOP_HESS_TENSOR,
                                       s.prec ? TMOP_MIXED : TMOP_FP64);
-            if (tt >= 0 && c.bops.epb_t[tt] > 0) c.tile = tt;
+            if (!s.lim && tt >= 0 && c.bops.epb_t[tt] > 0) c.tile = tt;
             it = P->classes.emplace(k, c).first;
         }
         ClassH &c = it->second;
@@ -1064,6 +1069,15 @@ static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
         const int nt = (int)c.tiles.size();
         if (!nt) continue;
         const int st = c.key.storage, pr = c.key.prec;
+        if (c.key.lim) {
+            BLaunch f = which == 0   ? c.bops.energyL
+                        : which == 1 ? c.bops.gradientL
+                        : which == 2 ? c.bops.setup[st][pr]
+                        : which == 3 ? c.bops.applyL[st][pr]
+                                     : c.bops.diagL[st][pr];
+            f(nt, P->s, c.tb, c.d_tiles, P->d_slots, gate, vin, P->d_part + c.pbase);
+            continue;
+        }
         if (which == 3 && c.tile != 1) {
             c.bops.apply_t[st][pr][c.tile]((int)c.atiles.size(), P->s, c.tb, c.d_atiles, P->d_slots,
                                           gate, vin, nullptr);
@@ -1607,15 +1621,21 @@ extern "C" int tmop_pool_request_bytes(const tmop_mesh_desc *m, const tmop_param
     return TMOP_OK;
 }
 
-extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop_params *prm,
-                               const tmop_solve_params *sp, const double *x_dev, void *src_stream,
-                               int *slot)
+// Admission of one solve; x0_dev != NULL adds the limiting term
+// coef |x - x0|^2 / delta^2 with the reference nodes copied into the region.
+static int pool_admit_impl(tmop_pool *P, const tmop_mesh_desc *m, const tmop_params *prm,
+                           const tmop_solve_params *sp, const double *x_dev, const double *x0_dev,
+                           double coef, double delta, void *src_stream, int *slot)
 {
     if (!P || !sp || !x_dev || !slot) return pfail(TMOP_ERR_INVALID_ARG, "null argument");
+    if (x0_dev && (!(delta > 0.0) || !(coef >= 0.0) || !std::isfinite(coef) || !std::isfinite(delta)))
+        return pfail(TMOP_ERR_INVALID_ARG, "limiting term needs coef >= 0 and delta > 0");
     SlotH s;
     std::string why;
     int r = request_sizes(m, prm, s, why);
     if (r != TMOP_OK) return pfail(r, why);
+    const bool with_x0 = x0_dev != nullptr && coef > 0.0;
+    if (with_x0) s.bytes += up256((size_t)s.ndof * 8);
     BOps probe;
     if (!find_bops(s.dim, s.p, s.nq, &probe))
         return pfail(TMOP_ERR_UNSUPPORTED, "no kernel for this (dim, p, nq1d)");
@@ -1666,7 +1686,7 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     g.e2n = nullptr;
     g.ess_mode = m->ess_mode;
     g.ess = nullptr;  // a mask is copied into the slot's region below
-    g.x0 = nullptr;  // pooled solves have no limiting term
+    g.x0 = nullptr;  // the limiting term, when asked for, is set below
     g.lim = 0.0;
     s.dev.tg = tg;
     char *base = P->arena + off;
@@ -1686,6 +1706,15 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
         g.ess = mask;
         o += up256((size_t)s.ndof);
     }
+    double *x0 = nullptr;
+    if (with_x0) {
+        // limiting term: reference nodes in the region, lim = coef det W / delta^2
+        x0 = (double *)(base + o);
+        o += up256((size_t)s.ndof * 8);
+        g.x0 = x0;
+        g.lim = coef * tg.detW / (delta * delta);
+        s.lim = 1;
+    }
     s.dev.bank = nullptr;
     s.dev.hist = nullptr;
     s.dev.bstride = 0;
@@ -1704,6 +1733,8 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
         e = hipMemcpyAsync(s.dev.vec[BX], x_dev, sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s);
     if (e == hipSuccess && mask)
         e = hipMemcpyAsync(mask, m->ess_mask, (size_t)s.ndof, hipMemcpyDeviceToDevice, P->s);
+    if (e == hipSuccess && x0)
+        e = hipMemcpyAsync(x0, x0_dev, sizeof(double) * s.ndof, hipMemcpyDeviceToDevice, P->s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->d_slots + si, &s.dev, sizeof(SlotDev), hipMemcpyHostToDevice, P->s);
     if (e == hipSuccess) e = hipStreamSynchronize(P->s);
@@ -1717,6 +1748,22 @@ extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop
     P->dirty = true;
     *slot = si;
     return TMOP_OK;
+}
+
+extern "C" int tmop_pool_admit(tmop_pool *P, const tmop_mesh_desc *m, const tmop_params *prm,
+                               const tmop_solve_params *sp, const double *x_dev, void *src_stream,
+                               int *slot)
+{
+    return pool_admit_impl(P, m, prm, sp, x_dev, nullptr, 0.0, 1.0, src_stream, slot);
+}
+
+extern "C" int tmop_pool_admit_limited(tmop_pool *P, const tmop_mesh_desc *m, const tmop_params *prm,
+                                       const tmop_solve_params *sp, const double *x_dev,
+                                       const double *x0_dev, double coef, double delta,
+                                       void *src_stream, int *slot)
+{
+    if (!x0_dev) return pfail(TMOP_ERR_INVALID_ARG, "null reference nodes");
+    return pool_admit_impl(P, m, prm, sp, x_dev, x0_dev, coef, delta, src_stream, slot);
 }
 
 extern "C" int tmop_pool_step(tmop_pool *P, int *n_active)
@@ -1865,7 +1912,7 @@ extern "C" int tmop_pool_autotune(tmop_pool *P, int reps)
     PHIP(hipEventCreate(&e1));
     for (auto &kv : P->classes) {
         ClassH &c = kv.second;
-        if (c.tiles.empty()) continue;
+        if (c.tiles.empty() || c.key.lim) continue;
         const int st = c.key.storage, pr = c.key.prec;
         int best = -1;
         float tbest = 0.f;

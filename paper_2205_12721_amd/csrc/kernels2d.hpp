@@ -741,24 +741,24 @@ __global__ __launch_bounds__(BLOCK) void k2_diagc(Geom g, Tables tb, Target tg, 
     b2_diagc<P, NQ, TT, LIM>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_energy(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ part)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_energy<P, NQ>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_energy<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_gradient<P, NQ>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_gradient<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -771,14 +771,14 @@ __global__ __launch_bounds__(BLOCK) void kb2_setup(Tables tb, const Tile *__rest
     b2_setup<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_apply(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_apply<P, NQ, TT, CT>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_apply<P, NQ, TT, CT, LIM>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -791,34 +791,34 @@ __global__ __launch_bounds__(BLOCK) void kb2_setupc(Tables tb, const Tile *__res
     b2_setupc<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_applyc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_applyc<P, NQ, TT, CT>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_applyc<P, NQ, TT, CT, LIM>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_diag(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_diag<P, NQ, TT>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_diag<P, NQ, TT, LIM>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb2_diagc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_diagc<P, NQ, TT>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_diagc<P, NQ, TT, LIM>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 }  // namespace tmop

@@ -1145,24 +1145,24 @@ __global__ __launch_bounds__(BLOCK) void k3_diagc(Geom g, Tables tb, Target tg, 
     b3_diagc<P, NQ, TT, LIM>(g, tb, tg, Q, dE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb3_energy(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ part)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_energy<P, NQ>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_energy<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb3_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_gradient<P, NQ>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_gradient<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -1175,14 +1175,14 @@ __global__ __launch_bounds__(BLOCK) void kb3_setup(Tables tb, const Tile *__rest
     b3_setup<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT, int T2 = 2>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void kb3_apply(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
     constexpr int EPB = S3<P, NQ, T2>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_apply<P, NQ, TT, CT, false, T2>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_apply<P, NQ, TT, CT, LIM, T2>(s.g, tb, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>
@@ -1195,14 +1195,14 @@ __global__ __launch_bounds__(BLOCK) void kb3_setupc(Tables tb, const Tile *__res
     b3_setupc<P, NQ, TT>(s.g, tb, s.tg, s.vec[vin], (TT *)s.H, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT, typename CT, int T2 = 2>
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __global__ __launch_bounds__(BLOCK) void kb3_applyc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin)
 {
     constexpr int EPB = S3<P, NQ, T2>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_applyc<P, NQ, TT, CT, false, T2>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_applyc<P, NQ, TT, CT, LIM, T2>(s.g, tb, s.tg, (const TT *)s.H, s.vec[vin], (CT *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 // Does the Hessian action of this class have a tile shape T2 distinct from
@@ -1214,24 +1214,24 @@ constexpr bool tile_ok3()
                        sizeof(Lds3<P, NQ, double, 9, T2>) <= 96 * 1024);
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb3_diag(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_diag<P, NQ, TT>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_diag<P, NQ, TT, LIM>(s.g, tb, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool LIM = false>
 __global__ __launch_bounds__(BLOCK) void kb3_diagc(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_diagc<P, NQ, TT>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_diagc<P, NQ, TT, LIM>(s.g, tb, s.tg, (const TT *)s.H, (double *)s.eV, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 }  // namespace tmop

@@ -62,6 +62,11 @@ struct BOps {
     BLaunch setup[2][2];  // [storage tensor/compact][fp64/fp32]
     BLaunch apply[2][2];
     BLaunch diag[2][2];
+    // with the limiting term (slots that carry reference nodes x0; the
+    // quadrature data and its setup are the same)
+    BLaunch energyL, gradientL;
+    BLaunch applyL[2][2];
+    BLaunch diagL[2][2];
     // Hessian action per tile shape (as in Ops); apply_t[..][..][1] == apply
     int epb_t[3];
     BLaunch apply_t[2][2][3];
@@ -124,6 +129,16 @@ bool bops3_p4(int nq, BOps *out);
             hipLaunchKernelGGL((K##_gradient<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
                                gt, vin, part);                                                 \
         };                                                                                     \
+        o.energyL = [](int grid, hipStream_t s, const Tables &t, const Tile *tl, const SlotDev *sl, \
+                       const int *gt, int vin, double *part) {                                 \
+            hipLaunchKernelGGL((K##_energy<P, NQ, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
+                               gt, vin, part);                                                 \
+        };                                                                                     \
+        o.gradientL = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,              \
+                         const SlotDev *sl, const int *gt, int vin, double *part) {            \
+            hipLaunchKernelGGL((K##_gradient<P, NQ, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, \
+                               sl, gt, vin, part);                                             \
+        };                                                                                     \
         TMOP_BOPS_PREC(K, P, NQ, 0, double, double)                                            \
         TMOP_BOPS_PREC(K, P, NQ, 1, float, float)                                              \
         fill_tiles_##K<P, NQ>(o);                                                              \
@@ -159,6 +174,26 @@ bool bops3_p4(int nq, BOps *out);
     o.diag[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,              \
                         const SlotDev *sl, const int *gt, int, double *) {                     \
         hipLaunchKernelGGL((K##_diagc<P, NQ, TT>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, gt); \
+    };                                                                                         \
+    o.applyL[0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,            \
+                          const SlotDev *sl, const int *gt, int vin, double *) {               \
+        hipLaunchKernelGGL((K##_apply<P, NQ, TT, CT, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, \
+                           sl, gt, vin);                                                       \
+    };                                                                                         \
+    o.applyL[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,            \
+                          const SlotDev *sl, const int *gt, int vin, double *) {               \
+        hipLaunchKernelGGL((K##_applyc<P, NQ, TT, CT, true>), dim3(grid), dim3(BLOCK), 0, s, t, \
+                           tl, sl, gt, vin);                                                   \
+    };                                                                                         \
+    o.diagL[0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int, double *) {                    \
+        hipLaunchKernelGGL((K##_diag<P, NQ, TT, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
+                           gt);                                                                \
+    };                                                                                         \
+    o.diagL[1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                         const SlotDev *sl, const int *gt, int, double *) {                    \
+        hipLaunchKernelGGL((K##_diagc<P, NQ, TT, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl,  \
+                           sl, gt);                                                            \
     };
 bool ops2(int p, int nq, Ops *out);
 bool ops3_p1(int nq, Ops *out);

@@ -57,22 +57,22 @@ inline void fill_btile3(BOps &o)
         o.epb_t[IDX] = S3<P, NQ, T2>::EPB;
         o.apply_t[0][0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
                                   const SlotDev *sl, const int *gt, int vin, double *) {
-            hipLaunchKernelGGL((kb3_apply<P, NQ, double, double, T2>), dim3(grid), dim3(BLOCK),
+            hipLaunchKernelGGL((kb3_apply<P, NQ, double, double, false, T2>), dim3(grid), dim3(BLOCK),
                                0, s, t, tl, sl, gt, vin);
         };
         o.apply_t[0][1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
                                   const SlotDev *sl, const int *gt, int vin, double *) {
-            hipLaunchKernelGGL((kb3_apply<P, NQ, float, float, T2>), dim3(grid), dim3(BLOCK), 0,
+            hipLaunchKernelGGL((kb3_apply<P, NQ, float, float, false, T2>), dim3(grid), dim3(BLOCK), 0,
                                s, t, tl, sl, gt, vin);
         };
         o.apply_t[1][0][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
                                   const SlotDev *sl, const int *gt, int vin, double *) {
-            hipLaunchKernelGGL((kb3_applyc<P, NQ, double, double, T2>), dim3(grid), dim3(BLOCK),
+            hipLaunchKernelGGL((kb3_applyc<P, NQ, double, double, false, T2>), dim3(grid), dim3(BLOCK),
                                0, s, t, tl, sl, gt, vin);
         };
         o.apply_t[1][1][IDX] = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,
                                   const SlotDev *sl, const int *gt, int vin, double *) {
-            hipLaunchKernelGGL((kb3_applyc<P, NQ, float, float, T2>), dim3(grid), dim3(BLOCK), 0,
+            hipLaunchKernelGGL((kb3_applyc<P, NQ, float, float, false, T2>), dim3(grid), dim3(BLOCK), 0,
                                s, t, tl, sl, gt, vin);
         };
     } else {

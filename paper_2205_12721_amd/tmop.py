@@ -109,6 +109,9 @@ SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_size_t)],
     "tmop_pool_admit": [_P, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
                         ctypes.POINTER(SolveParams), _P, _P, ctypes.POINTER(ctypes.c_int)],
+    "tmop_pool_admit_limited": [_P, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params),
+                                ctypes.POINTER(SolveParams), _P, _P, ctypes.c_double,
+                                ctypes.c_double, _P, ctypes.POINTER(ctypes.c_int)],
     "tmop_pool_step": [_P, ctypes.POINTER(ctypes.c_int)],
     "tmop_pool_poll": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveReport)],
     "tmop_pool_result": [_P, ctypes.c_int, _P, _P],
@@ -426,9 +429,14 @@ def solve_params(rel_grad_tol=1e-8, max_newton=200, max_minres=50, minres_rtol=1
                        int(bool(jacobi)), g0_norm)
 
 
-def request_bytes(md, prm):
+def request_bytes(md, prm, limited=False):
+    """Arena bytes of one pooled solve (with ``limited`` also its reference nodes)."""
     b = ctypes.c_size_t()
     _pcheck(lib().tmop_pool_request_bytes(ctypes.byref(md), ctypes.byref(prm), ctypes.byref(b)))
+    if limited:
+        nx = (md.nx * md.order_p + 1) * (md.ny * md.order_p + 1) * \
+            ((md.nz * md.order_p + 1) if md.dim == 3 else 1)
+        return b.value + (8 * md.dim * nx + 255) // 256 * 256
     return b.value
 
 
@@ -461,13 +469,21 @@ class Pool:
         except Exception:
             pass
 
-    def admit(self, md, prm, sp, x):
-        """Returns the slot index; raises TmopError (code ERR_BUSY / ERR_BUDGET ...)."""
+    def admit(self, md, prm, sp, x, x0=None, coef=1.0, delta=1.0):
+        """Returns the slot index; raises TmopError (code ERR_BUSY / ERR_BUDGET ...).
+        With reference nodes x0 the solve carries the limiting term
+        coef |x - x0|^2 / delta^2 (tmop_pool_admit_limited)."""
         slot = ctypes.c_int(-1)
         s = self._torch.cuda.current_stream().cuda_stream
-        _pcheck(lib().tmop_pool_admit(self._h, ctypes.byref(md), ctypes.byref(prm), ctypes.byref(sp),
-                                      _ptr(x, dtype=self._torch.float64), ctypes.c_void_p(s),
-                                      ctypes.byref(slot)))
+        if x0 is None:
+            _pcheck(lib().tmop_pool_admit(self._h, ctypes.byref(md), ctypes.byref(prm),
+                                          ctypes.byref(sp), _ptr(x, dtype=self._torch.float64),
+                                          ctypes.c_void_p(s), ctypes.byref(slot)))
+        else:
+            _pcheck(lib().tmop_pool_admit_limited(
+                self._h, ctypes.byref(md), ctypes.byref(prm), ctypes.byref(sp),
+                _ptr(x, dtype=self._torch.float64), _ptr(x0, dtype=self._torch.float64),
+                float(coef), float(delta), ctypes.c_void_p(s), ctypes.byref(slot)))
         self._keep[slot.value] = (md, prm, sp)
         return slot.value
 
