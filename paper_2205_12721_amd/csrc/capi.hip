@@ -129,7 +129,7 @@ void gll_nodes01(int p, double *x)
 void lagrange_tables(int p, int nq, const double *xi, const double *chi, double *B, double *G)
 {
     const int ni = p + 1;
-    std::vector<double> lam(ni);
+    double lam[MAXNI];  // no heap allocation: the no-allocation entry point builds tables too
     for (int i = 0; i < ni; ++i) {
         double d = 1.0;
         for (int m = 0; m < ni; ++m)
@@ -1063,23 +1063,25 @@ extern "C" int tmop_autotune(tmop_ctx *c, const double *v, double *y, int reps, 
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     const int keep = c->tile;
-    int best = -1;
-    float tbest = 0.f;
-    for (int t = 0; t < 3; ++t) {
-        if (c->ops.epb_t[t] == 0) continue;
-        c->tile = t;
-        for (int k = 0; k < 2; ++k) apply_elem(c, v);
-        HIPCHK(hipEventRecord(e0, c->s));
-        for (int k = 0; k < reps; ++k) apply_elem(c, v);
-        HIPCHK(hipEventRecord(e1, c->s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (best < 0 || ms < tbest) {
-            best = t;
-            tbest = ms;
+    // three rounds over the shapes, each shape's best round counts: a shape
+    // timed first is not penalised by clocks or caches still settling
+    float tmin[3] = {0.f, 0.f, 0.f};
+    for (int round = 0; round < 3; ++round)
+        for (int t = 0; t < 3; ++t) {
+            if (c->ops.epb_t[t] == 0) continue;
+            c->tile = t;
+            for (int k = 0; k < 2; ++k) apply_elem(c, v);
+            HIPCHK(hipEventRecord(e0, c->s));
+            for (int k = 0; k < reps; ++k) apply_elem(c, v);
+            HIPCHK(hipEventRecord(e1, c->s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (round == 0 || ms < tmin[t]) tmin[t] = ms;
         }
-    }
+    int best = -1;
+    for (int t = 0; t < 3; ++t)
+        if (c->ops.epb_t[t] != 0 && (best < 0 || tmin[t] < tmin[best])) best = t;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->tile = best < 0 ? keep : best;
