@@ -49,15 +49,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "89a4952fede496624256444c7e6bc6140a33fef5551834276f196b44277106d5"
+_SHA_C2 = "627a7eaebd07f4ccd8a3c76db336bd5aecc007b8c3e598c59fbf1a1be17c5b35"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 719741919, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 719758038, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366610605, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 367206682, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245084945, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 245111657, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135357549, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135281207, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
