@@ -49,7 +49,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "627a7eaebd07f4ccd8a3c76db336bd5aecc007b8c3e598c59fbf1a1be17c5b35"
+_SHA_C2 = "c23f5f3a72e331be9d4163ebb59570900989550fecce3cad288c246b6dcd7ce5"
 TRAFFIC = {
     ("c2", "tensor_fp64"): {"bytes": 719758038, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
@@ -62,14 +62,21 @@ TRAFFIC = {
 }
 
 
+# Sources of the device code a single-context Hessian action runs (its element
+# kernels, the node gather and what they include); host-only files (capi.hip,
+# batch.hip) and other element classes' units do not change the measured kernels.
+ACTION_SOURCES = ("gather.hpp", "kernels3d.hpp", "kernels2d.hpp", "k2.hip", "k3_p1.hip",
+                  "k3_p2.hip", "k3_p3.hip", "k3_p4.hip", "ops.hpp", "tiles3.hpp",
+                  "tmop_dev.hpp", "vec.hip", "vec.hpp")
+
+
 def csrc_sha256():
     import hashlib
     d = os.path.join(ROOT, "paper_2205_12721_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in sorted(ACTION_SOURCES):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 

@@ -27,6 +27,8 @@
 #include "../../include/tmop.h"
 #include "ops.hpp"
 #include "tmop_dev.hpp"
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "gather.hpp"
 #include "vec.hpp"
 
@@ -1344,6 +1346,11 @@ static int step_device(tmop_pool *P, int maxj, int maxh)
 // One Newton iteration for every active slot (initial evaluation first for new slots).
 static int pool_step_impl(tmop_pool *P, int *n_active)
 {
+    // roctx range (rocprofv3 --marker-trace); a no-op without a profiler
+    struct Range {
+        Range() { roctxRangePush("tmop pool step"); }
+        ~Range() { roctxRangePop(); }
+    } range;
     if (P->dirty) PCHK(pool_rebuild(P));
     const int M = P->max_slots;
     // ---- initial evaluation of new slots -------------------------------

@@ -13,6 +13,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/tmop.h"
 #include "ops.hpp"
 #include "tmop_dev.hpp"
@@ -29,6 +31,13 @@ int fail(int code, const std::string &msg)
     g_err = msg;
     return code;
 }
+
+// roctx range over a host scope (phases of the Newton-MINRES solve, visible
+// in rocprofv3 --marker-trace; a no-op when no profiler is attached)
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+};
 
 #define HIPCHK(call)                                                                         \
     do {                                                                                     \
@@ -901,14 +910,22 @@ static int newton_update(tmop_ctx *c, double *x, double &F, double &gn, int max_
                          double rtol, int max_halvings, bool jacobi, int check_every,
                          tmop_solve_report *rep)
 {
+    TraceRange step_range("tmop newton step");
     double t0 = now_ms();
-    setup_impl(c, x);
-    if (jacobi) make_jacobi(c);
-    HIPCHK(hipStreamSynchronize(c->s));
+    {
+        TraceRange r("tmop setup+diagonal");
+        setup_impl(c, x);
+        if (jacobi) make_jacobi(c);
+        HIPCHK(hipStreamSynchronize(c->s));
+    }
     double t1 = now_ms();
     int its = 0;
-    CHK(minres_impl(c, c->sv[SV_G], c->sv[SV_DX], max_minres, rtol, jacobi, check_every, &its));
+    {
+        TraceRange r("tmop minres");
+        CHK(minres_impl(c, c->sv[SV_G], c->sv[SV_DX], max_minres, rtol, jacobi, check_every, &its));
+    }
     double t2 = now_ms();
+    TraceRange ls_range("tmop line search");
     rep->minres_its_total += its;
     rep->t_apply_ms += c->acc_apply_ms;
     rep->t_apply_elem_ms += c->acc_elem_ms;

@@ -262,3 +262,30 @@ def test_whole_step_graph_kershaw_matches_oracle():
         ro["halvings_total"], "x rel %.2e" % e)
     assert done and rep["status"] == 0 and ro["status"] == 0
     assert e <= TOLX
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_line_search_failure_matches_oracle(mode):
+    """With no halving allowed (max_halvings = 0) the Kershaw mesh's solve stops with
+    TMOP_ERR_LINESEARCH at the first Newton step whose full step fails a test, in
+    every graph mode (the whole-step graph decides it on the device) and in the
+    oracle, after the same number of accepted steps and at the same nodes."""
+    import oracle
+    from paper_2205_12721_amd.tmop import ERR_LINESEARCH, Pool, request_bytes, solve_params
+    md, prm, x0, mask, _ = _kershaw_case()
+    pb0 = oracle.Problem.box(3, (6, 2, 2), 2, 4)
+    pb = oracle.Problem(3, 2, 4, pb0.e2n, pb0.nx, ess=mask.astype(bool))
+    xo, ro = oracle.newton_solve(pb, x0, rel_grad_tol=1e-10, max_newton=200, max_halvings=0)
+    pool = Pool(request_bytes(md, prm), 1, graph=mode)
+    xd = to_dev(x0)
+    sl = pool.admit(md, prm, solve_params(rel_grad_tol=1e-10, max_halvings=0), xd)
+    while pool.step() > 0:
+        pass
+    done, rep = pool.poll(sl)
+    pool.result(sl, xd)
+    pool.close()
+    log("mode", mode, "status", rep["status"], "newton", rep["newton_its"], "halvings",
+        rep["halvings_total"], "oracle", ro["status"], ro["newton_its"], ro["halvings_total"])
+    assert done and rep["status"] == ERR_LINESEARCH and ro["status"] == ERR_LINESEARCH
+    assert rep["newton_its"] == ro["newton_its"]
+    assert rel(to_host(xd), xo) <= TOLX
