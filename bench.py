@@ -20,7 +20,7 @@ FP64 oracle is timed on the host cores as a reference baseline.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --apply-only [--workload c2] [--reps 10]
            [--storage tensor|compact|both] [--precision fp64|mixed|both] [--copy-ref]
-           [--all-kernels]
+           [--all-kernels [--mfma]]
        python bench.py --batch-only [--batch-meshes 256]
 
 ``--apply-only`` runs only the Hessian action, for profilers: one setup per
@@ -28,7 +28,9 @@ variant on the workload's mesh, then 2 x reps actions back to back on the
 library's stream (``tmop_time_apply``), printing the mean device time per
 action; ``--copy-ref`` adds a plain 1 GiB device-to-device copy, a kernel of
 known traffic to scale hardware byte counters by; ``--all-kernels`` also runs
-the energy, gradient, setup and diagonal kernels reps times per variant.
+the energy, gradient, setup and diagonal kernels reps times per variant, and
+``--mfma`` the FP64 energy, gradient and setup again with their forward sweeps
+on the matrix cores (``tmop_set_sweeps``).
 """
 import argparse
 import json
@@ -49,15 +51,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "c23f5f3a72e331be9d4163ebb59570900989550fecce3cad288c246b6dcd7ce5"
+_SHA_C2 = "ff9a886d8770745e27d084588c6182f5c29edd3a3af30b46a6bfd2a30289851f"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 719758038, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 719678386, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 367206682, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 366573315, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245111657, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 245114635, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135281207, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135324338, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
@@ -65,7 +67,7 @@ TRAFFIC = {
 # Sources of the device code a single-context Hessian action runs (its element
 # kernels, the node gather and what they include); host-only files (capi.hip,
 # batch.hip) and other element classes' units do not change the measured kernels.
-ACTION_SOURCES = ("gather.hpp", "kernels3d.hpp", "kernels2d.hpp", "k2.hip", "k3_p1.hip",
+ACTION_SOURCES = ("gather.hpp", "kernels3d.hpp", "kernels2d.hpp", "k2.hip", "k3_p1.hip", "mfma3.hpp",
                   "k3_p2.hip", "k3_p3.hip", "k3_p4.hip", "ops.hpp", "tiles3.hpp",
                   "tmop_dev.hpp", "vec.hip", "vec.hpp")
 
@@ -615,6 +617,15 @@ def apply_only(args):
                     ctx.gradient(x, y)
                     ctx.hessian_setup(x)
                     ctx.hessian_diag(y)
+                if args.mfma and q == "fp64" and dim == 3 and nq <= 5:
+                    # and with the forward sweeps on the matrix cores
+                    ctx.set_sweeps("mfma")
+                    for _ in range(args.reps):
+                        ctx.energy(x)
+                        ctx.gradient(x, y)
+                        ctx.hessian_setup(x)
+                    ctx.set_sweeps("pencil")
+                    ctx.hessian_setup(x)
             elem, tot = ctx.time_apply(v, y, args.reps)
             out["%s_%s" % (s, q)] = dict(elem_us=round(elem * 1e3, 2), total_us=round(tot * 1e3, 2),
                                          elements_per_workgroup=ctx.tile_epb())
@@ -666,6 +677,9 @@ def main():
                     help="run only the batched solve (no sequential loop), for profilers")
     ap.add_argument("--all-kernels", action="store_true",
                     help="--apply-only: also run energy, gradient, setup and diagonal reps times")
+    ap.add_argument("--mfma", action="store_true",
+                    help="--apply-only --all-kernels: also run energy, gradient and FP64 setup "
+                         "with the forward sweeps on the matrix cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -723,6 +737,12 @@ def main():
     rf = roofline(ne, nqe, S, ctx.ndof, 8, elem_ms, tot_ms, traffic_for("tensor_fp64", cname, epb))
     rf["median_action_us"] = round(med_ms * 1e3, 2)
     kl = kernel_leg(ctx, x0, ne, nqe, S, dim, p, nq)
+    # the same forward sweeps on the FP64 matrix cores (tmop_set_sweeps)
+    if nq <= 5 and dim == 3:
+        ctx.set_sweeps("mfma")
+        km = kernel_leg(ctx, x0, ne, nqe, S, dim, p, nq)
+        ctx.set_sweeps("pencil")
+        kl["mfma_forward_sweeps"] = {k: km[k] for k in ("setup", "gradient", "energy")}
     # action FLOP: forward and backward sweeps plus the d^2 x d^2 point product
     act_flop = 2.0 * ne * (2 * sweep_fma(dim, p, nq) + nqe * (dim * dim) ** 2)
     kl["action_GFLOP_s"] = round(act_flop / (tot_ms / 1e3) / 1e9, 2)

@@ -74,6 +74,7 @@ enum { TMOP_FP64 = 0, TMOP_MIXED = 1 };       /* tmop_params.precision */
 enum { TMOP_ESS_BOUNDARY = 0, TMOP_ESS_NONE = 1, TMOP_ESS_MASK = 2 };
 enum { TMOP_HESS_TENSOR = 0, TMOP_HESS_COMPACT = 1 };  /* tmop_params.hess_storage */
 enum { TMOP_QUAD_GL = 0, TMOP_QUAD_GLL = 1 };          /* tmop_params.quad_rule */
+enum { TMOP_SWEEPS_PENCIL = 0, TMOP_SWEEPS_MFMA = 1 };  /* tmop_set_sweeps */
 
 typedef struct tmop_ctx tmop_ctx;
 
@@ -418,6 +419,17 @@ int tmop_set_tile(tmop_ctx *ctx, int epb);
  * NULL removes the term.  coef >= 0 and delta > 0, else TMOP_ERR_INVALID_ARG.
  * The Jacobi diagonal is recomputed on its next use. */
 int tmop_set_limiting(tmop_ctx *ctx, const double *x0_dev, double coef, double delta);
+
+/* How the forward sum-factorized contractions (Sec. 3.2: the Jacobian at
+ * the points from three 1D contractions with B and G) of the energy, gradient
+ * and FP64 Hessian setup kernels run: TMOP_SWEEPS_PENCIL (default), one lane
+ * per 1D line with the tables in scalar registers; or TMOP_SWEEPS_MFMA, each
+ * contraction as 16 x 16 x 4 FP64 matrix-core products.  Same values up to
+ * rounding order.  MFMA exists for hex classes with nq1d <= 5 (else
+ * TMOP_ERR_UNSUPPORTED) and is not used while a limiting term is set; the
+ * Hessian action and diagonal always use the pencil form.  Errors:
+ * INVALID_ARG, UNSUPPORTED. */
+int tmop_set_sweeps(tmop_ctx *ctx, int mode);
 
 /* Enable (1) or disable (0) HIP-event timing of the Hessian actions inside
  * MINRES; results land in tmop_solve_report.t_apply_ms / n_apply. */

@@ -243,6 +243,7 @@ enum { SV_DX, SV_XT, SV_G, SV_GT, SV_R1, SV_R2, SV_Y, SV_V, SV_W, SV_W1, SV_W2, 
 struct tmop_ctx {
     double *x0buf = nullptr;  // reference nodes of the limiting term (library copy)
     int tile = 1;             // Hessian-action tile shape (index into Ops::epb_t)
+    int sweeps = TMOP_SWEEPS_PENCIL;  // forward sweeps of energy, gradient, setup
     Geom g{};
     Tables tb{};
     Target tg{};
@@ -503,9 +504,16 @@ extern "C" int tmop_destroy(tmop_ctx *c)
 // Evaluations
 // ---------------------------------------------------------------------------
 
+// The matrix-core forward sweeps apply when chosen and the objective has no
+// limiting term.
+static bool use_mfma(const tmop_ctx *c)
+{
+    return c->sweeps == TMOP_SWEEPS_MFMA && c->g.lim == 0.0;
+}
+
 static int energy_mindet_impl(tmop_ctx *c, const double *x, double *F, double *mindet)
 {
-    c->ops.energy(c->grid, c->s, c->g, c->tb, c->tg, x, c->part);
+    (use_mfma(c) ? c->ops.energyM : c->ops.energy)(c->grid, c->s, c->g, c->tb, c->tg, x, c->part);
     launch_reduce3(c->part, c->grid, c->scal, c->s);
     HIPCHK(hipMemcpyAsync(c->hscal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c->s));
     HIPCHK(hipStreamSynchronize(c->s));
@@ -537,7 +545,8 @@ extern "C" int tmop_energy_mindet(tmop_ctx *c, const double *x, double *F, doubl
 
 static void gradient_impl(tmop_ctx *c, const double *x, double *g)
 {
-    c->ops.gradient(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->eV, c->part);
+    (use_mfma(c) ? c->ops.gradientM : c->ops.gradient)(c->grid, c->s, c->g, c->tb, c->tg, x,
+                                                       (double *)c->eV, c->part);
     launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, g, 0, nullptr, c->s);
 }
 
@@ -556,11 +565,13 @@ static void setup_impl(tmop_ctx *c, const double *x)
         if (mixed)
             c->ops.setupc32(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, c->part);
         else
-            c->ops.setupc64(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, c->part);
+            (use_mfma(c) ? c->ops.setupcM64 : c->ops.setupc64)(c->grid, c->s, c->g, c->tb, c->tg,
+                                                               x, (double *)c->H, c->part);
     } else if (mixed)
         c->ops.setup32(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, c->part);
     else
-        c->ops.setup64(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, c->part);
+        (use_mfma(c) ? c->ops.setupM64 : c->ops.setup64)(c->grid, c->s, c->g, c->tb, c->tg, x,
+                                                         (double *)c->H, c->part);
     c->have_setup = true;
     c->have_diag = false;
 }
@@ -1150,6 +1161,16 @@ extern "C" int tmop_set_limiting(tmop_ctx *c, const double *x0, double coef, dou
     HIPCHK(hipMemcpyAsync(c->x0buf, x0, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->s));
     c->g.x0 = c->x0buf;
     c->g.lim = coef * c->tg.detW / (delta * delta);
+    return TMOP_OK;
+}
+
+extern "C" int tmop_set_sweeps(tmop_ctx *c, int mode)
+{
+    if (!c || (mode != TMOP_SWEEPS_PENCIL && mode != TMOP_SWEEPS_MFMA))
+        return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    if (mode == TMOP_SWEEPS_MFMA && !c->ops.energyM)
+        return fail(TMOP_ERR_UNSUPPORTED, "no matrix-core sweeps for this class");
+    c->sweeps = mode;
     return TMOP_OK;
 }
 

@@ -23,6 +23,7 @@
 // Forward:  X -> R1 -> R2 -> RY(J);  point stage RY(J) -> RY(Y) in place;
 // backward: RY(Y) -> R2 -> R1 -> E-vector.
 #pragma once
+#include "mfma3.hpp"
 #include "tmop_dev.hpp"
 
 namespace tmop {
@@ -540,20 +541,28 @@ __device__ __forceinline__ void lim_values3(const Geom &g, const Tables &tb, con
 // count of points with det T <= 0 (Sec. 3.3, eq. D0_expression; Sec. 2.3).
 // LIM adds w_q lim |x - x0|^2 (the limiting integral of eq. eq_F_full with
 // xi = |y|^2 / delta^2 over the target element, lim = coef det W / delta^2).
-template <int P, int NQ, bool LIM = false>
+// MF: forward sweeps on the matrix cores (forward3_mfma) instead of the
+// pencil sweeps (classes with n_q <= 5, without the limiting term).
+template <int P, int NQ, bool LIM = false, bool MF = false>
 __device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, double *__restrict__ part, int e0,
                                  int nel)
 {
     using S = S3<P, NQ>;
     constexpr int NR = Planes3<LIM>::NR;
+    static_assert(!(MF && LIM), "no matrix-core sweeps with the limiting term");
     __shared__ Lds3<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
     __shared__ double red[BLOCK / 64];
+    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
     if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
+    if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    if constexpr (MF)
+        forward3_mfma<P, NQ, NR>(mft, L.X, L.R1, L.R2, L.RY, nel);
+    else
+        forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double esum = 0.0, dmin = 1.0e300, bad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
@@ -589,20 +598,26 @@ __device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const
 // Gradient E-vector (Sec. 3.3, eq. eq_vm_pa_grad): per point z P, then the
 // transposed contractions.  bad[blockIdx] counts points with det T <= 0.
 // LIM adds 2 w_q lim (x - x0)_c(q) wbar_i(q) through the value planes.
-template <int P, int NQ, bool LIM = false>
+template <int P, int NQ, bool LIM = false, bool MF = false>
 __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
                                    const double *__restrict__ x, double *__restrict__ gE,
                                    double *__restrict__ bad, int e0, int nel)
 {
     using S = S3<P, NQ>;
     constexpr int NR = Planes3<LIM>::NR;
+    static_assert(!(MF && LIM), "no matrix-core sweeps with the limiting term");
     __shared__ Lds3<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
     __shared__ double red[BLOCK / 64];
+    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
     if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
+    if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    if constexpr (MF)
+        forward3_mfma<P, NQ, NR>(mft, L.X, L.R1, L.R2, L.RY, nel);
+    else
+        forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
@@ -631,7 +646,7 @@ __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, con
 
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
 // element-major in the 16-byte-run layout of qdata_store.
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool MF = false>
 __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const Target &tg,
                                 const double *__restrict__ x, TT *__restrict__ H,
                                 double *__restrict__ bad, int e0, int nel)
@@ -639,9 +654,14 @@ __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const 
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
+    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
+    if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    if constexpr (MF)
+        forward3_mfma<P, NQ>(mft, L.X, L.R1, L.R2, L.RY, nel);
+    else
+        forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
@@ -782,7 +802,7 @@ __device__ __forceinline__ void mul_winv(const Target &t, const CT *in, CT *out,
         }
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool MF = false>
 __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, TT *__restrict__ Q,
                                  double *__restrict__ bad, int e0, int nel)
@@ -790,9 +810,14 @@ __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const
     using S = S3<P, NQ>;
     __shared__ Lds3<P, NQ, double> L;
     __shared__ double red[BLOCK / 64];
+    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
+    if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
-    forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
+    if constexpr (MF)
+        forward3_mfma<P, NQ>(mft, L.X, L.R1, L.R2, L.RY, nel);
+    else
+        forward3<P, NQ>(tb, L.X, L.R1, L.R2, L.RY, nel);
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
@@ -1081,28 +1106,28 @@ __device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const 
 // packed pools; no limiting term).
 // ------------------------------------------------------------------------
 
-template <int P, int NQ, bool LIM>
+template <int P, int NQ, bool LIM, bool MF = false>
 __global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ part)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_energy<P, NQ, LIM>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
+    b3_energy<P, NQ, LIM, MF>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, bool LIM>
+template <int P, int NQ, bool LIM, bool MF = false>
 __global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_gradient<P, NQ, LIM>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+    b3_gradient<P, NQ, LIM, MF>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool MF = false>
 __global__ __launch_bounds__(BLOCK) void k3_setup(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_setup<P, NQ, TT>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
+    b3_setup<P, NQ, TT, MF>(g, tb, tg, x, H, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT, typename CT, bool LIM, int T2 = 2>
@@ -1113,12 +1138,12 @@ __global__ __launch_bounds__(BLOCK) void k3_apply(Geom g, Tables tb, const TT *_
     b3_apply<P, NQ, TT, CT, LIM, T2>(g, tb, H, v, yE, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, typename TT>
+template <int P, int NQ, typename TT, bool MF = false>
 __global__ __launch_bounds__(BLOCK) void k3_setupc(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_setupc<P, NQ, TT>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
+    b3_setupc<P, NQ, TT, MF>(g, tb, tg, x, Q, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT, typename CT, bool LIM, int T2 = 2>

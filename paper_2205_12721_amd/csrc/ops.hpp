@@ -48,6 +48,13 @@ struct Ops {
     decltype(apply32) apply32_t[3];
     decltype(applyc64) applyc64_t[3];
     decltype(applyc32) applyc32_t[3];
+    // forward sweeps on the matrix cores (tmop_set_sweeps): energy, gradient
+    // and the FP64 setups without the limiting term; null where the class
+    // has no such form (quads, n_q > 5)
+    decltype(energy) energyM;
+    decltype(gradient) gradientM;
+    decltype(setup64) setupM64;
+    decltype(setupc64) setupcM64;
 };
 
 // Batched launchers (grid = number of tiles); every batched element kernel
@@ -83,6 +90,10 @@ inline void fill_tiles_k2(Ops &o)
         o.applyc64_t[t] = t == 1 ? o.applyc64 : nullptr;
         o.applyc32_t[t] = t == 1 ? o.applyc32 : nullptr;
     }
+    o.energyM = nullptr;
+    o.gradientM = nullptr;
+    o.setupM64 = nullptr;
+    o.setupcM64 = nullptr;
 }
 
 template <int P, int NQ>

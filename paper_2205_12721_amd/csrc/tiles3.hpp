@@ -42,12 +42,46 @@ inline void fill_tile3(Ops &o)
     }
 }
 
+// Matrix-core forward sweeps (forward3_mfma) where the class has them.
+template <int P, int NQ>
+inline void fill_mfma3(Ops &o)
+{
+    if constexpr (3 * NQ <= 16) {
+        o.energyM = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,
+                       const double *x, double *part) {
+            hipLaunchKernelGGL((k3_energy<P, NQ, false, true>), dim3(grid), dim3(BLOCK), 0, s, g,
+                               t, w, x, part);
+        };
+        o.gradientM = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                         const Target &w, const double *x, double *gE, double *bad) {
+            hipLaunchKernelGGL((k3_gradient<P, NQ, false, true>), dim3(grid), dim3(BLOCK), 0, s,
+                               g, t, w, x, gE, bad);
+        };
+        o.setupM64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                        const Target &w, const double *x, double *H, double *bad) {
+            hipLaunchKernelGGL((k3_setup<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s, g,
+                               t, w, x, H, bad);
+        };
+        o.setupcM64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                         const Target &w, const double *x, double *Q, double *bad) {
+            hipLaunchKernelGGL((k3_setupc<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s,
+                               g, t, w, x, Q, bad);
+        };
+    } else {
+        o.energyM = nullptr;
+        o.gradientM = nullptr;
+        o.setupM64 = nullptr;
+        o.setupcM64 = nullptr;
+    }
+}
+
 template <int P, int NQ>
 inline void fill_tiles_k3(Ops &o)
 {
     fill_tile3<P, NQ, 1, 0>(o);
     fill_tile3<P, NQ, 2, 1>(o);
     fill_tile3<P, NQ, 4, 2>(o);
+    fill_mfma3<P, NQ>(o);
 }
 
 template <int P, int NQ, int T2, int IDX>

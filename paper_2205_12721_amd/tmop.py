@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
 
 
 QUAD_RULES = {"gl": 0, "gll": 1}   # TMOP_QUAD_GL, TMOP_QUAD_GLL
+SWEEPS = {"pencil": 0, "mfma": 1}  # TMOP_SWEEPS_PENCIL, TMOP_SWEEPS_MFMA
 
 
 class SolveParams(ctypes.Structure):
@@ -97,6 +98,7 @@ SIGNATURES = {
                     ctypes.POINTER(ctypes.c_int)],
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
+    "tmop_set_sweeps": [_P, ctypes.c_int],
     "tmop_set_lanczos_bank_limit": [_P, ctypes.c_size_t],
     "tmop_pool_set_lanczos_bank": [_P, ctypes.c_int],
     "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
@@ -339,6 +341,11 @@ class Context:
 
     def set_timing(self, enable=True):
         _check(lib().tmop_set_timing(self._h, int(bool(enable))))
+
+    def set_sweeps(self, mode):
+        """Forward contractions of energy, gradient and FP64 setup: "pencil"
+        (default) or "mfma" (FP64 matrix cores; hex classes with nq1d <= 5)."""
+        _check(lib().tmop_set_sweeps(self._h, SWEEPS[mode]))
 
     def set_lanczos_bank_limit(self, max_bytes):
         """Bytes the resident MINRES Lanczos vectors may take (0: three-term
