@@ -13,9 +13,10 @@ DoFs d*N_x over the median time of one standalone ``tmop_hessian_apply`` call
 warm-up actions, each call bracketed by HIP events recorded on the library's
 stream; the setup is not timed).  ``roofline`` is the same action's
 algorithmic HBM bytes over its mean time back to back; the mixed-precision and
-compact-storage variants, the 64^3 Q2 and 32^3 Q4 workloads, the batched and
-served forms and the Kershaw benchmark are reported beside it, and the plain
-FP64 oracle is timed on the host cores as a reference baseline.
+compact-storage variants, the 64^3 Q2 and 32^3 Q4 workloads, the 2D 8x8 Q2
+ten-iteration solve, the batched and served forms and the Kershaw benchmark
+are reported beside it, and the plain FP64 oracle is timed on the host cores
+as a reference baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --apply-only [--workload c2] [--reps 10]
@@ -265,6 +266,13 @@ def cpu_baseline(cfg, x, v, seconds):
         if el >= seconds:
             break
     cores = oracle.num_threads()
+    # the oracle's energy (with the det check) and gradient on the same mesh
+    t2 = time.perf_counter()
+    pb.energy(x)
+    t_en = time.perf_counter() - t2
+    t2 = time.perf_counter()
+    pb.gradient(x)
+    t_gr = time.perf_counter() - t2
     # the same oracle on one thread, two actions
     oracle.set_num_threads(1)
     t1 = time.perf_counter()
@@ -280,8 +288,53 @@ def cpu_baseline(cfg, x, v, seconds):
         "sample": "%d Hessian actions of the FP64 oracle (direct, not sum-factorized) on the "
                   "same mesh and vector, %.1f s" % (reps, el),
         "one_thread_value": round(pb.ndof * 2 / t1 / 1e9, 6),
+        "energy_ms": round(t_en * 1e3, 2),
+        "gradient_GDoF_s": round(pb.ndof / t_gr / 1e9, 6),
         "cpu_model": cpu_model(),
     }, y
+
+
+def config1_leg(with_oracle):
+    """The 2D 8x8 Q2 mu_2 configuration: 10 Newton-MINRES iterations (no early
+    stop) on the GPU, wall time of the solve; with the oracle the same solve on
+    the host, its time and the relative difference of the final nodes."""
+    import numpy as np
+    import torch
+
+    from paper_2205_12721_amd import inputs
+    from paper_2205_12721_amd.tmop import Context, basis_nodes
+    c = inputs.CONFIGS["c1"]
+    ctx = Context(c["dim"], c["n"], c["p"], c["nq"])
+    buf = torch.empty(ctx.ndof, dtype=torch.float64, device="cuda")
+
+    def valid(xh):
+        buf.copy_(torch.as_tensor(xh))
+        return ctx.min_det(buf) > 0
+
+    xh, _ = inputs.config_mesh("c1", basis_nodes(c["p"]), is_valid=valid)
+    x = torch.as_tensor(xh).cuda()
+    for _ in range(2):  # warm-up solves
+        buf.copy_(x)
+        ctx.solve(buf, rel_grad_tol=0.0, max_newton=10)
+    torch.cuda.synchronize()
+    buf.copy_(x)
+    t0 = time.perf_counter()
+    rep = ctx.solve(buf, rel_grad_tol=0.0, max_newton=10)
+    torch.cuda.synchronize()
+    out = {"mesh": "2D 8x8 Q2, 4x4 Gauss-Legendre points, mu_2", "dofs": ctx.ndof,
+           "gpu_ms": round((time.perf_counter() - t0) * 1e3, 3),
+           "newton_its": rep["newton_its"], "minres_its": rep["minres_its_total"]}
+    if with_oracle:
+        import oracle
+        pb = oracle.Problem.box(c["dim"], c["n"], c["p"], c["nq"])
+        t0 = time.perf_counter()
+        xo, ro = oracle.newton_solve(pb, xh, rel_grad_tol=0.0, max_newton=10)
+        out["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        out["oracle_newton_its"] = ro["newton_its"]
+        xg = buf.cpu().numpy()
+        out["x_rel_diff_vs_oracle"] = float("%.3g" % (np.linalg.norm(xg - xo) / np.linalg.norm(xo)))
+    ctx.close()
+    return out
 
 
 def cpu_model():
@@ -828,6 +881,9 @@ def main():
         out["kershaw"] = kershaw_leg([int(v) for v in args.kershaw_orders.split(",") if v],
                                      cuts=[int(v) for v in args.kershaw_minres_cuts.split(",") if v])
         log("[bench] kershaw leg done")
+
+    out["config1"] = config1_leg(not args.no_cpu_baseline)
+    log("[bench] config1 done")
 
     if not args.no_copy_bw:
         bw = copy_bandwidth(torch)
