@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "ff9a886d8770745e27d084588c6182f5c29edd3a3af30b46a6bfd2a30289851f"
+_SHA_C2 = "0479d6cf8d6798f972409bd7d314db7caa7f06627e2e2daffd4b3ba6180b523d"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 719678386, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 719775956, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366573315, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 370522772, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245114635, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 245108803, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135324338, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135362945, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
@@ -96,6 +96,8 @@ WORKLOADS = {
     "c3b": ("c3b", 3, 32, 4, 6),
     "c1": ("c1", 2, 8, 2, 4),
 }
+# --apply-only also takes the Kershaw meshes (24^3, 9^3 points, sliding boundary)
+KERSHAW_WORKLOADS = {"kershaw%d" % p: p for p in (1, 2, 3, 4)}
 
 
 _T0 = time.monotonic()
@@ -641,26 +643,34 @@ def apply_only(args):
 
     from paper_2205_12721_amd import inputs
     from paper_2205_12721_amd.tmop import Context, basis_nodes
-    c = inputs.CONFIGS[args.workload]
-    dim, n, p, nq = c["dim"], c["n"], c["p"], c["nq"]
     st = ["tensor", "compact"] if args.storage == "both" else [args.storage]
     pr = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    probe = Context(dim, n, p, nq)
-    buf = torch.empty(probe.ndof, dtype=torch.float64, device="cuda")
+    ckw = {}
+    if args.workload in KERSHAW_WORKLOADS:
+        dim, n, p, nq = 3, (24, 24, 24), KERSHAW_WORKLOADS[args.workload], 9
+        ckw["ess"] = torch.as_tensor(inputs.sliding_mask(n, p)).cuda()
+        xh = inputs.kershaw_nodes(n, p, basis_nodes(p), 0.3, 0.3)
+        vec_seed = 200 + p
+    else:
+        c = inputs.CONFIGS[args.workload]
+        dim, n, p, nq = c["dim"], c["n"], c["p"], c["nq"]
+        probe = Context(dim, n, p, nq)
+        buf = torch.empty(probe.ndof, dtype=torch.float64, device="cuda")
 
-    def valid(xh):
-        buf.copy_(torch.as_tensor(xh))
-        return probe.min_det(buf) > 0
+        def valid(xh):
+            buf.copy_(torch.as_tensor(xh))
+            return probe.min_det(buf) > 0
 
-    xh, _ = inputs.config_mesh(args.workload, basis_nodes(p), is_valid=valid)
-    probe.close()
+        xh, _ = inputs.config_mesh(args.workload, basis_nodes(p), is_valid=valid)
+        probe.close()
+        vec_seed = c["vec_seed"]
     x = torch.as_tensor(xh).cuda()
-    v = torch.as_tensor(inputs.gaussian_vector(x.numel(), c["vec_seed"])).cuda()
+    v = torch.as_tensor(inputs.gaussian_vector(x.numel(), vec_seed)).cuda()
     y = torch.empty_like(v)
     out = {}
     for s in st:
         for q in pr:
-            ctx = Context(dim, n, p, nq, precision=q, storage=s)
+            ctx = Context(dim, n, p, nq, precision=q, storage=s, **ckw)
             ctx.hessian_setup(x)
             ctx.hessian_apply(v, y)
             if args.all_kernels:
@@ -701,7 +711,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--minres", type=int, default=20)
     ap.add_argument("--apply-reps", type=int, default=30)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2",
+                    choices=sorted(WORKLOADS) + sorted(KERSHAW_WORKLOADS),
+                    help="kershaw1..4 only with --apply-only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -756,6 +768,8 @@ def main():
         # the batched solve alone, for profilers
         print(json.dumps(batch_leg(args.batch_meshes, sequential=False)), flush=True)
         return
+    if args.workload not in WORKLOADS:
+        sys.exit("--workload %s runs with --apply-only only" % args.workload)
     cfg = WORKLOADS[args.workload]
     cname, dim, n, p, nq = cfg
     S = dim * dim * (dim * dim + 1) // 2

@@ -689,52 +689,105 @@ __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const 
 //   transposed contractions -> E-vector.
 // CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
 // accumulation).
+// Point stage of the action at point q of element el: Y = H : (grad v) from
+// the point's stored tensor hr, in place of the gradient planes of RY.
+template <int P, int NQ, typename TT, typename CT, int NR, bool LIM>
+__device__ __forceinline__ void apply_point3(const Tables &tb, const Geom &g, const TT *hr, int el,
+                                             int q, CT *RY)
+{
+    constexpr int NQ3 = S3<P, NQ>::NQ3;
+    CT hv[45];
+#pragma unroll
+    for (int k = 0; k < 45; ++k) hv[k] = (CT)hr[k];
+    CT J[9];
+    point_J3<P, NQ, CT, NR>(RY, el, q, J);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        CT s = 0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s += hv[sym_index<9>(r, c)] * J[c];
+        RY[(el * NR + r) * NQ3 + q] = s;
+    }
+    if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, RY);
+}
+
 template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
                                 const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ, T2>;
+    using QL = QLay<TT, 45, S::NQ3>;
     constexpr int NR = Planes3<LIM>::NR;
-    // at most one quadrature point per lane: its tensor is loaded before the
-    // sweeps and stays in flight behind them (barriers wait on LDS only)
-    constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;
+    // The lanes take the workgroup's points in PASSES passes of BLOCK.  With
+    // one pass (ONE) each lane's tensor is loaded before the sweeps and stays
+    // in flight behind them (barriers wait on LDS only).  With PF (more than
+    // one pass at the base tile shape, n_q^3 > 256) the first pass is loaded
+    // so too and each later pass while the previous one computes, at the cost
+    // of a second register set for the tensor: taken for FP32 data, and for
+    // FP64 data only where the LDS already limits a CU to two workgroups (the
+    // registers would otherwise cut the workgroups per CU).
+    constexpr int PASSES = (S::EPB * S::NQ3 + BLOCK - 1) / BLOCK;
+    constexpr bool ONE = PASSES == 1;
+    constexpr bool PF = !ONE && T2 == 2 &&
+                        (sizeof(TT) == 4 || 3 * sizeof(Lds3<P, NQ, CT, NR, T2>) > LDS_PER_CU);
     __shared__ Lds3<P, NQ, CT, NR, T2> L;
     // v loads first, then the tensor loads, then v to LDS: waiting for v
     // leaves the tensor loads in flight
     Gath3<P, NQ, T2> gv;
     gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
-    TT hraw[45];
-    if (ONE) {
-        // every lane loads (lanes past the last point re-read the first
-        // point): with no branch around these loads, the wait for the v loads
-        // can leave all of them in flight
-        const int t = threadIdx.x < npts ? threadIdx.x : 0;
-        const int el = t / S::NQ3, q = t % S::NQ3;
-        qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE, q,
-                                         hraw);
-    }
-    gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
-    __syncthreads();
-    forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
-    for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
-        const int el = idx / S::NQ3, q = idx % S::NQ3;
-        if (!ONE)
-            qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QLay<TT, 45, S::NQ3>::STRIDE,
-                                             q, hraw);
-        CT hv[45];
+    if constexpr (PF) {
+        // point data of pass k; lanes past the last point re-read the first
+        // point, so that no branch sits around the loads
+        TT hraw[2][45];
+        auto load_pass = [&](int k, TT *dst) {
+            const int i = threadIdx.x + k * BLOCK;
+            const int t = i < npts ? i : 0;
+            qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + t / S::NQ3) * QL::STRIDE,
+                                             t % S::NQ3, dst);
+        };
+        load_pass(0, hraw[0]);
+        gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
+        __syncthreads();
+        forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
 #pragma unroll
-        for (int k = 0; k < 45; ++k) hv[k] = (CT)hraw[k];
-        CT J[9];
-        point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            CT s = 0;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) s += hv[sym_index<9>(r, c)] * J[c];
-            L.RY[(el * NR + r) * S::NQ3 + q] = s;
+        for (int k = 0; k < PASSES; ++k) {
+            const int idx = threadIdx.x + k * BLOCK;
+            if (k + 1 < PASSES) load_pass(k + 1, hraw[(k + 1) & 1]);
+            if (idx < npts)
+                apply_point3<P, NQ, TT, CT, NR, LIM>(tb, g, hraw[k & 1], idx / S::NQ3,
+                                                     idx % S::NQ3, L.RY);
         }
-        if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
+    } else {
+        TT hraw[45];
+        if (ONE) {
+            // every lane loads (lanes past the last point re-read the first
+            // point): with no branch around these loads, the wait for the v
+            // loads can leave all of them in flight
+            const int t = threadIdx.x < npts ? threadIdx.x : 0;
+            const int el = t / S::NQ3, q = t % S::NQ3;
+            qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QL::STRIDE, q, hraw);
+        }
+        gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
+        __syncthreads();
+        forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
+        for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
+            const int el = idx / S::NQ3, q = idx % S::NQ3;
+            if (!ONE) qdata_load<TT, 45, S::NQ3, true>(H + (size_t)(e0 + el) * QL::STRIDE, q, hraw);
+            CT hv[45];
+#pragma unroll
+            for (int k = 0; k < 45; ++k) hv[k] = (CT)hraw[k];
+            CT J[9];
+            point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                CT s = 0;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) s += hv[sym_index<9>(r, c)] * J[c];
+                L.RY[(el * NR + r) * S::NQ3 + q] = s;
+            }
+            if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
+        }
     }
     __syncthreads();
     backward3<P, NQ, CT, CT, NR, LIM, true>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
@@ -857,43 +910,55 @@ __device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const
                                  CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ, T2>;
+    using QL = QLay<TT, NC3, S::NQ3>;
     constexpr int NR = Planes3<LIM>::NR;
-    constexpr bool ONE = S::EPB * S::NQ3 <= BLOCK;  // as in b3_apply
+    // passes of the points as in b3_apply; the 13 values of a point are few
+    // enough that PF (the next pass loaded while the previous one computes)
+    // costs no workgroups per CU, and one pass runs unrolled (fewer registers
+    // than the loop form: 90 instead of 107 VGPRs at Q3, five workgroups per
+    // CU instead of four)
+    constexpr int PASSES = (S::EPB * S::NQ3 + BLOCK - 1) / BLOCK;
+    constexpr bool ONE = PASSES == 1;
+    constexpr bool PF = !ONE && T2 == 2;
     __shared__ Lds3<P, NQ, CT, NR, T2> L;
     Gath3<P, NQ, T2> gv;
     gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);
     const int npts = nel * S::NQ3;
-    TT draw[NC3];
-    if (ONE) {
-        // branch-free, as in b3_apply
-        const int t = threadIdx.x < npts ? threadIdx.x : 0;
-        const int el = t / S::NQ3, q = t % S::NQ3;
-        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, draw);
-    }
+    auto load_pass = [&](int k, TT *dst) {
+        const int i = threadIdx.x + k * BLOCK;
+        const int t = i < npts ? i : 0;
+        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + t / S::NQ3) * QL::STRIDE, t % S::NQ3, dst);
+    };
+    TT draw[PF ? 2 : 1][NC3];
+    if (ONE || PF) load_pass(0, draw[0]);
     gather3_store<P, NQ, CT, T2>(gv, nel, L.X);
     __syncthreads();
     forward3<P, NQ, CT, NR, LIM>(tb, L.X, L.R1, L.R2, L.RY, nel);
-    for (int idx = threadIdx.x; idx < npts; idx += BLOCK) {
-        const int el = idx / S::NQ3, q = idx % S::NQ3;
-        if (!ONE)
-            qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q,
-                                        draw);
-        CT d[NC3];
 #pragma unroll
-        for (int k = 0; k < NC3; ++k) d[k] = (CT)draw[k];
-        CT J[9], Y[9];
-        point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
-        if (tg.ideal) {
-            compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
-        } else {
-            CT M[9], Yt[9];
-            mul_winv<3, CT>(tg, J, M, false);
-            compact_action3<CT>(d, d[9], d[10], d[11], d[12], M, Yt);
-            mul_winv<3, CT>(tg, Yt, Y, true);
+    for (int k = 0; k < PASSES; ++k) {
+        const int idx = threadIdx.x + k * BLOCK;
+        if (PF && k + 1 < PASSES) load_pass(k + 1, draw[(k + 1) & 1]);
+        if (!ONE && !PF && idx < npts) load_pass(k, draw[0]);
+        if (idx < npts) {
+            const TT *dr = draw[PF ? (k & 1) : 0];
+            const int el = idx / S::NQ3, q = idx % S::NQ3;
+            CT d[NC3];
+#pragma unroll
+            for (int m = 0; m < NC3; ++m) d[m] = (CT)dr[m];
+            CT J[9], Y[9];
+            point_J3<P, NQ, CT, NR>(L.RY, el, q, J);
+            if (tg.ideal) {
+                compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
+            } else {
+                CT M[9], Yt[9];
+                mul_winv<3, CT>(tg, J, M, false);
+                compact_action3<CT>(d, d[9], d[10], d[11], d[12], M, Yt);
+                mul_winv<3, CT>(tg, Yt, Y, true);
+            }
+#pragma unroll
+            for (int r = 0; r < 9; ++r) L.RY[(el * NR + r) * S::NQ3 + q] = Y[r];
+            if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
         }
-#pragma unroll
-        for (int r = 0; r < 9; ++r) L.RY[(el * NR + r) * S::NQ3 + q] = Y[r];
-        if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, L.RY);
     }
     __syncthreads();
     backward3<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);

@@ -15,6 +15,7 @@ namespace tmop {
 constexpr int BLOCK = 256;
 constexpr int MAXNI = 9;   // p <= 8
 constexpr int MAXNQ = 10;  // up to 10 points per direction
+constexpr int LDS_PER_CU = 160 * 1024;  // bytes of LDS per compute unit (gfx950)
 
 // Division by a divisor d >= 1 fixed at set-up, exact for 0 <= n < 2^31:
 // floor(n / d) = (n m) >> s with l = ceil(log2 d), m = ceil(2^(31+l) / d),
