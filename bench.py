@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "0479d6cf8d6798f972409bd7d314db7caa7f06627e2e2daffd4b3ba6180b523d"
+_SHA_C2 = "368d7ab20b6d40130b2e0a8537e05cccfb59af22193a95a57156623edf0288da"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 719775956, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 719923291, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 370522772, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 370743633, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245108803, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 245108003, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135362945, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 135352941, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 

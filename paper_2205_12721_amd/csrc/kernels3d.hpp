@@ -188,11 +188,12 @@ __device__ __forceinline__ void gather3(const Geom &g, const double *__restrict_
 
 // Forward sweeps X -> R1 -> R2 -> RY (J at every point, plane el*NR + c*3 + b;
 // with VAL also the value of component c, plane el*NR + 9 + c).
-template <int P, int NQ, typename CT, int NR = 9, bool VAL = false>
-__device__ __forceinline__ void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, CT *RY, int nel)
+// Forward sweeps of axes 1 and 2: X -> R1 -> R2, ending with a barrier.
+template <int P, int NQ, typename CT>
+__device__ __forceinline__ void forward3_head(const Tables &tb, const CT *X, CT *R1, CT *R2, int nel)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, NP = S::NP, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    constexpr int NI = S::NI, NP = S::NP, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2;
     // axis 1: pencils (r, i3, i2), r = el*3 + c
     for (int pen = threadIdx.x; pen < nel * 3 * NI * NI; pen += BLOCK) {
         const int i23 = pen % (NI * NI), r = pen / (NI * NI);
@@ -241,6 +242,14 @@ __device__ __forceinline__ void forward3(const Tables &tb, const CT *X, CT *R1, 
         }
     }
     __syncthreads();
+}
+
+template <int P, int NQ, typename CT, int NR = 9, bool VAL = false>
+__device__ __forceinline__ void forward3(const Tables &tb, const CT *X, CT *R1, CT *R2, CT *RY, int nel)
+{
+    using S = S3<P, NQ>;
+    constexpr int NI = S::NI, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    forward3_head<P, NQ, CT>(tb, X, R1, R2, nel);
     // axis 3: pencils (r, q2, q1) -> J at the NQ points of the pencil
     for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
         const int q12 = pen % NQ2, r = pen / NQ2;
@@ -290,47 +299,14 @@ __device__ __forceinline__ long ev_index3(const Geom &g, int e, int c, int i1, i
     return (long)c * g.ne * NP + ((long)(ez * NI + i3) * EY + (ey * NI + i2)) * EX + ex * NI + i1;
 }
 
-// Backward (transposed) sweeps RY -> R2 -> R1 -> E-vector:
-//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q)  (+ RY[9+c](q) w_i(q) with VAL).
-template <int P, int NQ, typename CT, typename OT, int NR = 9, bool VAL = false, bool CW = false>
-__device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
-                                 CT *R1, int nel, OT *__restrict__ out)
+// Backward sweeps of axes 2 and 1: R2 (the axis-3 contractions) -> R1 ->
+// E-vector.  Called after a barrier that ends the writes of R2.
+template <int P, int NQ, typename CT, typename OT, bool CW = false>
+__device__ __forceinline__ void backward3_tail(const Tables &tb, const Geom &g, int e0, CT *R2,
+                                               CT *R1, int nel, OT *__restrict__ out)
 {
     using S = S3<P, NQ>;
-    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
-    // axis 3: pencils (r, q2, q1)
-    for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
-        const int q12 = pen % NQ2, r = pen / NQ2;
-        const int el = r / 3, c = r % 3;
-        const CT *y = RY + (el * NR + c * 3) * NQ3 + q12;  // [b] stride NQ^3, [q3] stride NQ^2
-        const CT *yv = RY + (el * NR + 9 + c) * NQ3 + q12;
-        CT y0[NQ], y1[NQ], y2[NQ], ym[VAL ? NQ : 1];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            y0[q] = y[q * NQ2];
-            y1[q] = y[NQ3 + q * NQ2];
-            y2[q] = y[2 * NQ3 + q * NQ2];
-            if (VAL) ym[q] = yv[q * NQ2];
-        }
-        CT *o = R2 + r * 3 * L2 + q12;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-            CT t0 = 0, t1 = 0, t2 = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
-                t0 += b3 * y0[q];
-                t1 += b3 * y1[q];
-                t2 += g3 * y2[q];
-                // the value term follows the B B path of plane 2 on axes 1, 2
-                if (VAL) t2 += b3 * ym[q];
-            }
-            o[k * NQ2] = t0;
-            o[L2 + k * NQ2] = t1;
-            o[2 * L2 + k * NQ2] = t2;
-        }
-    }
-    __syncthreads();
+    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2;
     // axis 2: pencils (r, i3, q1)
     for (int pen = threadIdx.x; pen < nel * 3 * NI * NQ; pen += BLOCK) {
         const int q1 = pen % NQ, i3 = (pen / NQ) % NI, r = pen / (NQ * NI);
@@ -412,6 +388,51 @@ __device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e
         const int i2 = rest % NI, i3 = (rest / NI) % NI, c = rest / (NI * NI);
         out[ev_index3<P>(g, e0 + el, c, k, i2, i3)] = (OT)Y[(((el * 3 + c) * NI + i3) * NI + i2) * NI + k];
     }
+}
+
+
+// Backward (transposed) sweeps RY -> R2 -> R1 -> E-vector:
+//   y_c(i) = sum_q sum_b RY[c][b](q) d w_i/d xbar_b (q)  (+ RY[9+c](q) w_i(q) with VAL).
+template <int P, int NQ, typename CT, typename OT, int NR = 9, bool VAL = false, bool CW = false>
+__device__ __forceinline__ void backward3(const Tables &tb, const Geom &g, int e0, const CT *RY, CT *R2,
+                                 CT *R1, int nel, OT *__restrict__ out)
+{
+    using S = S3<P, NQ>;
+    constexpr int NI = S::NI, L1 = S::L1, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    // axis 3: pencils (r, q2, q1)
+    for (int pen = threadIdx.x; pen < nel * 3 * NQ2; pen += BLOCK) {
+        const int q12 = pen % NQ2, r = pen / NQ2;
+        const int el = r / 3, c = r % 3;
+        const CT *y = RY + (el * NR + c * 3) * NQ3 + q12;  // [b] stride NQ^3, [q3] stride NQ^2
+        const CT *yv = RY + (el * NR + 9 + c) * NQ3 + q12;
+        CT y0[NQ], y1[NQ], y2[NQ], ym[VAL ? NQ : 1];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            y0[q] = y[q * NQ2];
+            y1[q] = y[NQ3 + q * NQ2];
+            y2[q] = y[2 * NQ3 + q * NQ2];
+            if (VAL) ym[q] = yv[q * NQ2];
+        }
+        CT *o = R2 + r * 3 * L2 + q12;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            CT t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
+                t0 += b3 * y0[q];
+                t1 += b3 * y1[q];
+                t2 += g3 * y2[q];
+                // the value term follows the B B path of plane 2 on axes 1, 2
+                if (VAL) t2 += b3 * ym[q];
+            }
+            o[k * NQ2] = t0;
+            o[L2 + k * NQ2] = t1;
+            o[2 * L2 + k * NQ2] = t2;
+        }
+    }
+    __syncthreads();
+    backward3_tail<P, NQ, CT, OT, CW>(tb, g, e0, R2, R1, nel, out);
 }
 
 // J[c*3+b] = d x_c / d xbar_b at point q of element el, left in RY by forward3.
@@ -712,8 +733,10 @@ __device__ __forceinline__ void apply_point3(const Tables &tb, const Geom &g, co
 }
 
 template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
-__device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
-                                const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+__device__ __forceinline__ void b3_apply_points(const Geom &g, const Tables &tb,
+                                                const TT *__restrict__ H,
+                                                const double *__restrict__ v,
+                                                CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ, T2>;
     using QL = QLay<TT, 45, S::NQ3>;
@@ -855,6 +878,166 @@ __device__ __forceinline__ void mul_winv(const Target &t, const CT *in, CT *out,
         }
 }
 
+// Hessian action of the classes with more points than lanes (n_q^3 > 256:
+// n_q = 7 and the 9-point classes; one element per workgroup), point layers
+// along the third axis taken CH at a time, CH n_q^2 <= 256.  Per chunk: the
+// axis-3 forward contraction for its layers only (J at its points), the
+// point stage, and the axis-3 transposed contraction added into per-lane
+// accumulators (one lane per (component, q1, q2) pencil, 3 n_q^2 <= 256).
+// Only one chunk of point values is held in LDS (9 CH n_q^2 instead of
+// 9 n_q^3 entries: 47 instead of 82 KB per workgroup at p = 4, n_q = 9 in
+// FP64, three workgroups per CU instead of two).  The point data of the next
+// chunk is loaded as soon as the point stage has used the current one, so it
+// is in flight during the accumulation and the next forward contraction.
+// Every sum runs in the order of the unchunked sweeps (q3 ascending), so the
+// result is bitwise that of forward3 / point stage / backward3.
+template <int P, int NQ, typename TT, typename CT, bool COMPACT>
+__device__ __forceinline__ void b3_apply_layers(const Geom &g, const Tables &tb, const Target &tg,
+                                                const TT *__restrict__ Hq,
+                                                const double *__restrict__ v,
+                                                CT *__restrict__ yE, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    constexpr int NI = S::NI, L2 = S::L2, NQ2 = S::NQ2, NQ3 = S::NQ3;
+    constexpr int NS = COMPACT ? NC3 : 45;
+    using QL = QLay<TT, NS, NQ3>;
+    constexpr int CH = BLOCK / NQ2;          // point layers per chunk
+    constexpr int NCH = (NQ + CH - 1) / CH;  // chunks
+    constexpr int CN = CH * NQ2;             // points per chunk (at most)
+    static_assert(S::EPB == 1 && CH >= 1 && 3 * NQ2 <= BLOCK, "one element, one pencil per lane");
+    // X / R2 and R1 / point values share storage as in Lds3
+    __shared__ union {
+        CT X[3 * S::NP];
+        CT R2[9 * L2];
+    } A;
+    __shared__ union {
+        CT R1[6 * S::L1];
+        CT RY[9 * CN];
+    } B;
+    Gath3<P, NQ> gv;
+    gather3_load<P, NQ>(g, v, e0, nel, true, gv);
+    const TT *he = Hq + (size_t)e0 * QL::STRIDE;
+    // the point data of chunk ch for this lane (lanes past the chunk's points
+    // re-read point 0, so that no branch sits around the loads)
+    TT hraw[NS];
+    auto load_chunk = [&](int ch) {
+        const int q3 = ch * CH + (int)threadIdx.x / NQ2;
+        const bool in = (int)threadIdx.x < CN && q3 < NQ;
+        const int q = in ? q3 * NQ2 + (int)threadIdx.x % NQ2 : 0;
+        qdata_load<TT, NS, NQ3, !COMPACT>(he, q, hraw);
+    };
+    load_chunk(0);
+    gather3_store<P, NQ, CT>(gv, nel, A.X);
+    __syncthreads();
+    forward3_head<P, NQ, CT>(tb, A.X, B.R1, A.R2, nel);
+    // pencil of this lane for the axis-3 contractions
+    const bool pen = (int)threadIdx.x < 3 * NQ2;
+    const int c = (int)threadIdx.x / NQ2, q12 = (int)threadIdx.x % NQ2;
+    CT acc0[NI], acc1[NI], acc2[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) acc0[k] = acc1[k] = acc2[k] = 0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int nl = (ch + 1) * CH <= NQ ? CH : NQ - ch * CH;  // layers of this chunk
+        // axis 3, forward: J[c][b] at this chunk's layers (plane c*3+b of RY)
+        if (pen) {
+            const CT *t = A.R2 + c * 3 * L2 + q12;
+            CT t0[NI], t1[NI], t2[NI];
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                t0[k] = t[k * NQ2];
+                t1[k] = t[L2 + k * NQ2];
+                t2[k] = t[2 * L2 + k * NQ2];
+            }
+#pragma unroll
+            for (int l = 0; l < CH; ++l) {
+                if (l < nl) {
+                    const int q = ch * CH + l;
+                    CT a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+                    for (int k = 0; k < NI; ++k) {
+                        const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
+                        a0 += b3 * t0[k];
+                        a1 += b3 * t1[k];
+                        a2 += g3 * t2[k];
+                    }
+                    CT *o = B.RY + (c * 3) * CN + l * NQ2 + q12;
+                    o[0] = a0;
+                    o[CN] = a1;
+                    o[2 * CN] = a2;
+                }
+            }
+        }
+        __syncthreads();
+        // point stage at this chunk's points
+        const int tp = threadIdx.x;
+        if (tp < nl * NQ2) {
+            CT J[9], Y[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) J[k] = B.RY[k * CN + tp];
+            if constexpr (COMPACT) {
+                CT d[NC3];
+#pragma unroll
+                for (int m = 0; m < NC3; ++m) d[m] = (CT)hraw[m];
+                if (tg.ideal) {
+                    compact_action3<CT>(d, d[9], d[10], d[11], d[12], J, Y);
+                } else {
+                    CT M[9], Yt[9];
+                    mul_winv<3, CT>(tg, J, M, false);
+                    compact_action3<CT>(d, d[9], d[10], d[11], d[12], M, Yt);
+                    mul_winv<3, CT>(tg, Yt, Y, true);
+                }
+            } else {
+                CT hv[45];
+#pragma unroll
+                for (int m = 0; m < 45; ++m) hv[m] = (CT)hraw[m];
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    CT sr = 0;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) sr += hv[sym_index<9>(r, k)] * J[k];
+                    Y[r] = sr;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) B.RY[k * CN + tp] = Y[k];
+        }
+        if (ch + 1 < NCH) load_chunk(ch + 1);
+        __syncthreads();
+        // axis 3, transposed: this chunk's layers added into the accumulators
+        if (pen) {
+            const CT *y = B.RY + (c * 3) * CN + q12;
+#pragma unroll
+            for (int l = 0; l < CH; ++l) {
+                if (l < nl) {
+                    const int q = ch * CH + l;
+                    const CT y0 = y[l * NQ2], y1 = y[CN + l * NQ2], y2 = y[2 * CN + l * NQ2];
+#pragma unroll
+                    for (int k = 0; k < NI; ++k) {
+                        const CT b3 = tabB<CT>(tb, q * NI + k), g3 = tabG<CT>(tb, q * NI + k);
+                        acc0[k] += b3 * y0;
+                        acc1[k] += b3 * y1;
+                        acc2[k] += g3 * y2;
+                    }
+                }
+            }
+        }
+        if (ch + 1 < NCH) __syncthreads();
+    }
+    // R2 was last read before the point stage of the last chunk
+    if (pen) {
+        CT *o = A.R2 + c * 3 * L2 + q12;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            o[k * NQ2] = acc0[k];
+            o[L2 + k * NQ2] = acc1[k];
+            o[2 * L2 + k * NQ2] = acc2[k];
+        }
+    }
+    __syncthreads();
+    backward3_tail<P, NQ, CT, CT, !COMPACT>(tb, g, e0, A.R2, B.R1, nel, yE);
+}
+
 template <int P, int NQ, typename TT, bool MF = false>
 __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, TT *__restrict__ Q,
@@ -905,14 +1088,15 @@ __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const
 }
 
 template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
-__device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
-                                 const TT *__restrict__ Q, const double *__restrict__ v,
-                                 CT *__restrict__ yE, int e0, int nel)
+__device__ __forceinline__ void b3_applyc_points(const Geom &g, const Tables &tb,
+                                                 const Target &tg, const TT *__restrict__ Q,
+                                                 const double *__restrict__ v,
+                                                 CT *__restrict__ yE, int e0, int nel)
 {
     using S = S3<P, NQ, T2>;
     using QL = QLay<TT, NC3, S::NQ3>;
     constexpr int NR = Planes3<LIM>::NR;
-    // passes of the points as in b3_apply; the 13 values of a point are few
+    // passes of the points as in b3_apply_points; the 13 values of a point are few
     // enough that PF (the next pass loaded while the previous one computes)
     // costs no workgroups per CU, and one pass runs unrolled (fewer registers
     // than the loop form: 90 instead of 107 VGPRs at Q3, five workgroups per
@@ -962,6 +1146,41 @@ __device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const
     }
     __syncthreads();
     backward3<P, NQ, CT, CT, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, yE);
+}
+
+// Hessian action, element part: the layer-chunked body or the point-pass
+// body.  Layer chunks apply to the classes with more points than lanes at the
+// base tile shape, without the limiting term, where they measured faster
+// (24^3 Kershaw meshes p = 1..4 with 9^3 points, and p = 4 with 7^3 points):
+// FP64 compact data (-11% to -26%, from 3 to 5 workgroups per CU) and the
+// FP64 tensor at p = 4 (-5%).  The FP64 tensor at p <= 3 (+3%: its 360 bytes
+// per point gain more from the point-pass body's two passes of loads in
+// flight) and the FP32 forms (+2% to +7%) keep the point-pass body.
+template <int P, int NQ, int T2, bool LIM, typename CT, bool COMPACT>
+constexpr bool apply_layers3()
+{
+    return S3<P, NQ>::NQ3 > BLOCK && T2 == 2 && !LIM && sizeof(CT) == 8 && (COMPACT || P >= 4);
+}
+
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
+__device__ __forceinline__ void b3_apply(const Geom &g, const Tables &tb, const TT *__restrict__ H,
+                                const double *__restrict__ v, CT *__restrict__ yE, int e0, int nel)
+{
+    if constexpr (apply_layers3<P, NQ, T2, LIM, CT, false>())
+        b3_apply_layers<P, NQ, TT, CT, false>(g, tb, Target{}, H, v, yE, e0, nel);
+    else
+        b3_apply_points<P, NQ, TT, CT, LIM, T2>(g, tb, H, v, yE, e0, nel);
+}
+
+template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
+__device__ __forceinline__ void b3_applyc(const Geom &g, const Tables &tb, const Target &tg,
+                                 const TT *__restrict__ Q, const double *__restrict__ v,
+                                 CT *__restrict__ yE, int e0, int nel)
+{
+    if constexpr (apply_layers3<P, NQ, T2, LIM, CT, true>())
+        b3_apply_layers<P, NQ, TT, CT, true>(g, tb, tg, Q, v, yE, e0, nel);
+    else
+        b3_applyc_points<P, NQ, TT, CT, LIM, T2>(g, tb, tg, Q, v, yE, e0, nel);
 }
 
 // Hessian diagonal, element part (Sec. 3.4, last paragraph):
