@@ -704,12 +704,6 @@ __device__ __forceinline__ void b3_setup(const Geom &g, const Tables &tb, const 
     if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
-// Hessian action, element part (Sec. 3.4, eq. eq_vm_pa_hess):
-//   grad v at the points (forward contractions of P v),
-//   Y_an = sum_bp H[an,bp] (grad v)_bp  with the stored tensor,
-//   transposed contractions -> E-vector.
-// CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
-// accumulation).
 // Point stage of the action at point q of element el: Y = H : (grad v) from
 // the point's stored tensor hr, in place of the gradient planes of RY.
 template <int P, int NQ, typename TT, typename CT, int NR, bool LIM>
@@ -732,6 +726,13 @@ __device__ __forceinline__ void apply_point3(const Tables &tb, const Geom &g, co
     if (LIM) lim_point3<NQ, CT, NR>(tb, g, el, q, RY);
 }
 
+// Hessian action, element part (Sec. 3.4, eq. eq_vm_pa_hess):
+//   grad v at the points (forward contractions of P v),
+//   Y_an = sum_bp H[an,bp] (grad v)_bp  with the stored tensor,
+//   transposed contractions -> E-vector.
+// CT = double (FP64) or float (mixed: FP32 tensor, FP32 arithmetic and
+// accumulation).  This is the point-pass body; b3_apply chooses between it
+// and the layer-chunked body (b3_apply_layers).
 template <int P, int NQ, typename TT, typename CT, bool LIM = false, int T2 = 2>
 __device__ __forceinline__ void b3_apply_points(const Geom &g, const Tables &tb,
                                                 const TT *__restrict__ H,

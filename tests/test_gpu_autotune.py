@@ -2,7 +2,9 @@
 base and double the base max(1, 256 / n_q^3) where they fit the LDS).
 
 * every tile shape gives bitwise the same action (each element is computed
-  alike), and that action matches the oracle within 1e-11
+  alike), and that action matches the oracle within 1e-11; at p = 4,
+  n_q = 7 the base shape runs the layer-chunked body (FP64) and the double
+  shape the point-pass body, so the two bodies are compared bitwise
 * tmop_autotune picks one of the shapes, leaves y = H v, and the choice is
   recorded for the class (a later context of the class starts with it)
 * the pool's autotuner runs between steps and the batched solve still ends
@@ -24,7 +26,7 @@ def _shapes(base):
 @pytest.mark.parametrize("storage", ["tensor", "compact"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("ns,p,nq", [((5, 4, 3), 1, 3), ((4, 3, 3), 2, 4), ((3, 3, 2), 3, 5),
-                                     ((3, 2, 2), 4, 6)])
+                                     ((3, 2, 2), 4, 6), ((2, 2, 3), 4, 7)])
 def test_tile_shapes_agree(ns, p, nq, storage, precision):
     from paper_2205_12721_amd.tmop import Context, TmopError
     log("case", ns, p, nq, storage, precision)
