@@ -1097,14 +1097,15 @@ __device__ __forceinline__ void b3_applyc_points(const Geom &g, const Tables &tb
     using S = S3<P, NQ, T2>;
     using QL = QLay<TT, NC3, S::NQ3>;
     constexpr int NR = Planes3<LIM>::NR;
-    // passes of the points as in b3_apply_points; the 13 values of a point are few
-    // enough that PF (the next pass loaded while the previous one computes)
-    // costs no workgroups per CU, and one pass runs unrolled (fewer registers
-    // than the loop form: 90 instead of 107 VGPRs at Q3, five workgroups per
-    // CU instead of four)
+    // passes of the points as in b3_apply_points; the 13 values of a point are
+    // few enough that PF (the next pass loaded while the previous one
+    // computes) costs no workgroups per CU at any tile shape (with two points
+    // per lane: -6% at 24^3 Q3, -9% at 32^3 Q4, -3% for the 256-mesh batch),
+    // and one pass runs unrolled (fewer registers than the loop form: 90
+    // instead of 107 VGPRs at Q3, five workgroups per CU instead of four)
     constexpr int PASSES = (S::EPB * S::NQ3 + BLOCK - 1) / BLOCK;
     constexpr bool ONE = PASSES == 1;
-    constexpr bool PF = !ONE && T2 == 2;
+    constexpr bool PF = !ONE;
     __shared__ Lds3<P, NQ, CT, NR, T2> L;
     Gath3<P, NQ, T2> gv;
     gather3_load<P, NQ, T2>(g, v, e0, nel, true, gv);

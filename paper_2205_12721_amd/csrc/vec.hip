@@ -676,7 +676,7 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
                    const double *w1, const double *w2, double *wout, double *x, double *r1hv,
                    double *part, MrHist *hist, hipStream_t s)
 {
-    // one node per lane up to 2048 workgroups; its partials (alpha) number
+    // one node per lane up to 1024 workgroups; its partials (alpha) number
     // nb1, those of the vector kernels (beta^2) nb2
     const int nb1 = mr_gather_grid(g), nb2 = reduce_blocks((long)g.dim * g.nx);
 #define TMOP_G(D, T)                                                                          \
@@ -699,7 +699,10 @@ void mr_gather_upd(const Geom &g, const int32_t *csr_ptr, const int32_t *csr_ent
 #undef TMOP_G
 }
 
-int mr_gather_grid(const Geom &g) { return vgrid((long)g.nx, 2048); }
+// At most 1024 workgroups (a lane takes several nodes on large meshes): every
+// workgroup of the next kernel sums all of these partials, and with 2048 the
+// Newton step measured 0.4-1.9% slower (24^3 Q3, 64^3 Q2, Kershaw p = 4).
+int mr_gather_grid(const Geom &g) { return vgrid((long)g.nx, 1024); }
 
 void mr_lanczos2(long n, int nb1, int j, const MinresState *st, const double *part1, double *hv,
                  const double *r2, const double *minv, double *z, double *part2, hipStream_t s)
