@@ -411,27 +411,36 @@ __global__ __launch_bounds__(VB) void kv_mr_gather_upd(
     const double *__restrict__ w1 = S.vec[vw1], *__restrict__ w2 = S.vec[vw2];
     double *__restrict__ r1 = S.vec[vr1], *__restrict__ x = S.vec[BDX];
     double *__restrict__ wo = S.vec[vwout];
-    double acc = 0.0;
-    for (int i = i0; i < i1; i += VB) {
-        if (vupd) {
+    if (vupd)
+        for (int i = i0; i < i1; i += VB) {
             const double wn = (sprev * zp[i] - u.oldeps * w1[i] - u.delta * w2[i]) * u.ig;
             wo[i] = wn;
             x[i] += u.phi * wn;
         }
-        if (gat) {
-            const int c = i >= g.nx ? (DIM == 3 && i >= 2 * g.nx ? 2 : 1) : 0;
-            const int node = i - c * g.nx;
-            int gc[3];
-            box_coords<DIM>(g, node, gc);
-            const bool fixed = is_fixed(g, c, node, gc[0], gc[1], gc[2]);
+    if (!gat) return;
+    // G^T with one lane per node for all components (the copy positions are
+    // worked out once per node and the loads of every component are in
+    // flight together): the slot's nodes are split evenly over its vector
+    // tiles (the tiles of a slot are consecutive VCH-DoF chunks from 0)
+    double acc = 0.0;
+    const int ntile = (DIM * g.nx + VCH - 1) / VCH, jt = t.start / VCH;
+    const int npt = (g.nx + ntile - 1) / ntile;
+    const int nb = jt * npt, ne = nb + npt < g.nx ? nb + npt : g.nx;
+    for (int node = nb + (int)threadIdx.x; node < ne; node += VB) {
+        int gc[3];
+        box_coords<DIM>(g, node, gc);
+        ET sv[DIM];
+        gather_box_all<DIM, ET>(g, eV, gc, sv);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const size_t i = (size_t)c * g.nx + node;
             const double vi = sc * zc[i];
-            double h = fixed ? vi : sc * (double)gather_box_node<DIM, ET>(g, eV, c, node, gc);
+            double h = is_fixed(g, c, node, gc[0], gc[1], gc[2]) ? vi : sc * (double)sv[c];
             if (u.o.j >= 1) h -= cr * r1[i];
             r1[i] = h;
             acc += vi * h;
         }
     }
-    if (!gat) return;
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) part[pbase + blockIdx.x] = acc;
 }
