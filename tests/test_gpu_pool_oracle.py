@@ -8,6 +8,9 @@ slot by slot with the pool's own batched kernels (``tmop_pool_evaluate``):
   DoFs and on one that is not) and diagonal at the initial mesh: 1e-11
   relative for FP64 slots and for the FP64 parts of mixed slots (energy,
   gradient), the FP32 bound for the mixed action and diagonal;
+* the Hessian action and diagonal of pooled classes with more quadrature
+  points than lanes (p = 4 with 7^3 points, p = 2 with 9^3), whose element
+  kernels take the layer-chunked body: 1e-11 (FP64), the FP32 bound (mixed);
 * the first Newton step (the pool's lockstep MINRES, line search and update)
   against the oracle's first Newton step, with MINRES allowed 200 iterations
   so that it stops at its tolerance: the same line-search decisions; for
@@ -108,6 +111,31 @@ def test_pool_operators_match_oracle():
             % (eF, emd, eg, ey, ey2, ed))
         assert eF <= TOL64 and emd <= 1e-12 and eg <= TOL64
         assert ey <= t and ey2 <= t and ed <= t
+    pool.close()
+
+
+# classes with more points than lanes: the pool's element kernels run the
+# layer-chunked body for FP64 compact data and the FP64 tensor at p = 4, the
+# point-pass body otherwise
+LAYERED = [
+    dict(dim=3, ns=(2, 2, 2), p=4, nq=7, precision="fp64", storage="compact", seed=91),
+    dict(dim=3, ns=(2, 2, 2), p=4, nq=7, precision="fp64", storage="tensor", seed=92),
+    dict(dim=3, ns=(2, 3, 2), p=2, nq=9, precision="fp64", storage="compact", seed=93),
+    dict(dim=3, ns=(2, 2, 2), p=4, nq=7, precision="mixed", storage="compact", seed=94),
+]
+
+
+def test_pool_layered_classes_match_oracle():
+    pool, probs, slots, _ = _admit_all(LAYERED)
+    for c, (pb, x), sl in zip(LAYERED, probs, slots):
+        t = TOL32 if c["precision"] == "mixed" else TOL64
+        xd = to_dev(x)
+        pool.hessian_setup(sl, xd)
+        v = inputs.gaussian_vector(pb.ndof, c["seed"] + 1, pb.ess)
+        ey = rel(to_host(pool.hessian_apply(sl, to_dev(v))), pb.hvp(x, v))
+        ed = rel(to_host(pool.hessian_diag(sl, xd)), pb.diag(x))
+        log("pool slot", sl, c, "Hv %.1e diag %.1e" % (ey, ed))
+        assert ey <= t and ed <= t
     pool.close()
 
 
