@@ -19,7 +19,7 @@ are reported beside it, and the plain FP64 oracle is timed on the host cores
 as a reference baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       python bench.py --apply-only [--workload c2] [--reps 10]
+       python bench.py --apply-only [--workload c2|c3a|c3b|kershaw1..4] [--reps 10]
            [--storage tensor|compact|both] [--precision fp64|mixed|both] [--copy-ref]
            [--all-kernels [--mfma]]
        python bench.py --batch-only [--batch-meshes 256]
