@@ -145,6 +145,17 @@ typedef struct {
     int reserved;
 } tmop_solve_report;
 
+/* One entry of a solve's per-iteration record (Sec. 2.3): the objective and
+ * |g_c| at the mesh after k accepted Newton updates (k = 0: the initial mesh),
+ * and the MINRES iterations and line-search halvings of the update that led
+ * to it (0 for k = 0). */
+typedef struct {
+    double F;
+    double g_norm;
+    int minres_its;
+    int halvings;
+} tmop_iter_record;
+
 /* ---------------------------------------------------------------------- */
 /* Context                                                                 */
 /* ---------------------------------------------------------------------- */
@@ -419,6 +430,12 @@ int tmop_set_tile(tmop_ctx *ctx, int epb);
  * NULL removes the term.  coef >= 0 and delta > 0, else TMOP_ERR_INVALID_ARG.
  * The Jacobi diagonal is recomputed on its next use. */
 int tmop_set_limiting(tmop_ctx *ctx, const double *x0_dev, double coef, double delta);
+
+/* The per-iteration record of the context's last tmop_solve: copies
+ * min(cap, entries) records into the host array out (newton_its + 1 entries
+ * for a solve that ran) and sets *n to the number of entries (also when cap
+ * is smaller).  out may be NULL when cap is 0.  Errors: INVALID_ARG. */
+int tmop_solve_history(tmop_ctx *ctx, tmop_iter_record *out, int cap, int *n);
 
 /* How the forward sum-factorized contractions (Sec. 3.2: the Jacobian at
  * the points from three 1D contractions with B and G) of the energy, gradient

@@ -278,6 +278,7 @@ struct tmop_ctx {
     // HIP-event timing of the Hessian actions inside MINRES
     bool timing = false;
     std::vector<hipEvent_t> tev;
+    std::vector<tmop_iter_record> hist;  // per-iteration record of the last tmop_solve
     int tev_used = 0;
     double acc_apply_ms = 0.0, acc_elem_ms = 0.0;
     int acc_napply = 0;
@@ -1000,6 +1001,7 @@ extern "C" int tmop_solve(tmop_ctx *c, double *x, const tmop_solve_params *sp,
 {
     if (!c || !x || !sp || !rep) return fail(TMOP_ERR_INVALID_ARG, "null argument");
     std::memset(rep, 0, sizeof(*rep));
+    c->hist.clear();
     const double t0 = now_ms();
     double F = 0.0, gn = 0.0;
     int r = solve_start(c, x, F, gn, rep);
@@ -1009,6 +1011,7 @@ extern "C" int tmop_solve(tmop_ctx *c, double *x, const tmop_solve_params *sp,
     }
     const double n0 = sp->g0_norm > 0.0 ? sp->g0_norm : gn;
     rep->g0_norm = n0;
+    c->hist.push_back(tmop_iter_record{F, gn, 0, 0});
     int status = TMOP_ERR_NOT_CONVERGED;
     for (int it = 0; it <= sp->max_newton; ++it) {
         if (n0 == 0.0 || F == 0.0 || gn <= sp->rel_grad_tol * n0) {
@@ -1016,12 +1019,15 @@ extern "C" int tmop_solve(tmop_ctx *c, double *x, const tmop_solve_params *sp,
             break;
         }
         if (it == sp->max_newton) break;
+        const int its0 = rep->minres_its_total, h0 = rep->halvings_total;
         r = newton_update(c, x, F, gn, sp->max_minres, sp->minres_rtol, sp->max_halvings,
                           sp->jacobi != 0, 8, rep);
         if (r != TMOP_OK) {
             status = r;
             break;
         }
+        c->hist.push_back(
+            tmop_iter_record{F, gn, rep->minres_its_total - its0, rep->halvings_total - h0});
     }
     rep->F = F;
     rep->g_norm = gn;
@@ -1161,6 +1167,15 @@ extern "C" int tmop_set_limiting(tmop_ctx *c, const double *x0, double coef, dou
     HIPCHK(hipMemcpyAsync(c->x0buf, x0, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->s));
     c->g.x0 = c->x0buf;
     c->g.lim = coef * c->tg.detW / (delta * delta);
+    return TMOP_OK;
+}
+
+extern "C" int tmop_solve_history(tmop_ctx *c, tmop_iter_record *out, int cap, int *n)
+{
+    if (!c || !n || cap < 0 || (cap > 0 && !out)) return fail(TMOP_ERR_INVALID_ARG, "bad argument");
+    const int m = (int)c->hist.size();
+    for (int k = 0; k < m && k < cap; ++k) out[k] = c->hist[k];
+    *n = m;
     return TMOP_OK;
 }
 

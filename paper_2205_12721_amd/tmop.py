@@ -73,6 +73,11 @@ class SolveReport(ctypes.Structure):
         return d
 
 
+class IterRecord(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double), ("g_norm", ctypes.c_double),
+                ("minres_its", ctypes.c_int), ("halvings", ctypes.c_int)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _lib_handle = None
@@ -99,6 +104,8 @@ SIGNATURES = {
     "tmop_time_apply": [_P, _P, _P, ctypes.c_int, _D, _D],
     "tmop_set_timing": [_P, ctypes.c_int],
     "tmop_set_sweeps": [_P, ctypes.c_int],
+    "tmop_solve_history": [_P, ctypes.POINTER(IterRecord), ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_int)],
     "tmop_set_lanczos_bank_limit": [_P, ctypes.c_size_t],
     "tmop_pool_set_lanczos_bank": [_P, ctypes.c_int],
     "tmop_set_limiting": [_P, _P, ctypes.c_double, ctypes.c_double],
@@ -370,7 +377,17 @@ class Context:
             _check(code)
         d = rep.as_dict()
         d["message"] = lib().tmop_last_error().decode() if code else ""
+        d["history"] = self.solve_history()
         return d
+
+    def solve_history(self):
+        """Per-iteration record of the last solve: (F, |g|, MINRES iterations,
+        halvings) for the initial mesh and after each accepted Newton update."""
+        n = ctypes.c_int()
+        _check(lib().tmop_solve_history(self._h, None, 0, ctypes.byref(n)))
+        buf = (IterRecord * max(n.value, 1))()
+        _check(lib().tmop_solve_history(self._h, buf, n.value, ctypes.byref(n)))
+        return [(r.F, r.g_norm, r.minres_its, r.halvings) for r in buf[:n.value]]
 
     def newton_step(self, x, n_minres=20, jacobi=True):
         rep = SolveReport()

@@ -91,6 +91,33 @@ def test_resume_reproduces_uninterrupted_run():
     ctx.close()
 
 
+def test_solve_history():
+    """The per-iteration record of a solve (``tmop_solve_history``): entry 0 is
+    the initial mesh (the oracle's F and |g| at 1e-11), entry 1 the mesh after
+    the first Newton update (the oracle's at 1e-9 of F0 and |g0|; MINRES may
+    take 200 iterations so that it stops at its tolerance, as in the pooled
+    first-step test), the MINRES and halving columns sum to the report's
+    totals, there is one entry per accepted update plus one, and the last
+    entry holds the report's final F and |g|."""
+    from paper_2205_12721_amd.tmop import Context
+    pb, x0 = make_case(3, (3, 3, 3), 2, 4, seed=51)
+    xo, ro = oracle.newton_solve(pb, x0, rel_grad_tol=1e-10, max_newton=100, max_minres=200)
+    ctx = Context(3, (3, 3, 3), 2, 4)
+    rg = ctx.solve(to_dev(x0), rel_grad_tol=1e-10, max_newton=100, max_minres=200)
+    ctx.close()
+    h, ho = rg["history"], ro["history"]
+    log("history gpu", h[:3], "oracle", ho[:3])
+    assert rg["status"] == 0 and len(h) == rg["newton_its"] + 1
+    assert abs(h[0][0] - ho[0][0]) <= 1e-11 * ho[0][0]
+    assert abs(h[0][1] - ho[0][1]) <= 1e-11 * ho[0][1]
+    assert abs(h[1][0] - ho[1][0]) <= 1e-9 * ho[0][0]
+    assert abs(h[1][1] - ho[1][1]) <= 1e-9 * ho[0][1]
+    assert h[0][2] == 0 and h[0][3] == 0
+    assert sum(e[2] for e in h) == rg["minres_its_total"]
+    assert sum(e[3] for e in h) == rg["halvings_total"]
+    assert h[-1][0] == rg["F"] and h[-1][1] == rg["g_norm"]
+
+
 def test_solve_error_codes():
     import torch
     from paper_2205_12721_amd.tmop import Context
