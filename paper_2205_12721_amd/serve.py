@@ -81,12 +81,33 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
     import torch
     pool = Pool(hbm_budget, max_slots, graph=graph, lanczos_bank=lanczos_bank)
     sp = solve_params(rel_grad_tol=rel_grad_tol, max_newton=max_newton, max_minres=max_minres)
-    n = len(reqs)
     # every request's nodes are on the device when it arrives
     xds = [torch.as_tensor(x).cuda() for x in xs_host]
     torch.cuda.synchronize()
+
+    def describe(r):
+        return request(r["dim"], r["n"], r["p"], r["nq"], precision=precision, storage=storage)
+
+    try:
+        return serve_loop(reqs, xds, pool, sp, describe)
+    finally:
+        pool.close()
+
+
+def serve_loop(reqs, xs, pool, sp, describe):
+    """The scheduling loop of ``serve`` over any pool object.
+
+    ``pool`` provides ``admit(md, prm, sp, x) -> slot`` (raising ``TmopError``:
+    ``ERR_BUSY`` is back-pressure, any other code rejects the request),
+    ``step()``, ``poll(slot) -> (done, report)``, ``result(slot, x)``,
+    ``release(slot)`` and ``info() -> {"used": bytes}``; ``xs[k]`` is request
+    k's node vector (written with the result); ``describe(r)`` gives the
+    ``(mesh, params)`` pair the pool admits.  Arrivals follow
+    ``r["t_arrive"]`` (seconds from the start) on the host monotonic clock.
+    Returns (summary, per-request records)."""
+    n = len(reqs)
     pending = []            # arrived, not admitted (FIFO)
-    resident = {}           # slot -> (request index, device tensor)
+    resident = {}           # slot -> (request index, node vector)
     rec = [None] * n
     nxt = 0
     t0 = time.monotonic()
@@ -100,8 +121,8 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
         while pending:
             k = pending[0]
             r = reqs[k]
-            md, prm = request(r["dim"], r["n"], r["p"], r["nq"], precision=precision, storage=storage)
-            xd = xds[k]
+            md, prm = describe(r)
+            xd = xs[k]
             try:
                 slot = pool.admit(md, prm, sp, xd)
             except TmopError as e:
@@ -133,7 +154,6 @@ def serve(reqs, xs_host, hbm_budget, max_slots=256, precision="mixed", storage="
             if wait > 0:
                 time.sleep(min(wait, 0.01))
     wall = time.monotonic() - t0
-    pool.close()
     out = _summary(rec, wall)
     out.update(ticks=ticks, peak_bytes=peak_used)
     return out, rec
