@@ -551,6 +551,43 @@ static void gradient_impl(tmop_ctx *c, const double *x, double *g)
     launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, g, 0, nullptr, c->s);
 }
 
+// Energy, min det A, gradient and |g|^2 of one point in one element pass
+// (the gradient kernel also sums the energy) and one host synchronisation.
+// g2 is a dot of g with itself; F, md and g agree with energy_mindet_impl
+// and gradient_impl up to rounding (the same terms in the same order, but
+// the compiler fuses the products of mu and of P differently when both are
+// live).  F = inf and TMOP_ERR_INVERTED when det T <= 0 somewhere (g is then
+// of no use).
+static int energy_gradient_impl(tmop_ctx *c, const double *x, double *F, double *md, double *g,
+                                double *g2)
+{
+    (use_mfma(c) ? c->ops.gradientEM : c->ops.gradientE)(c->grid, c->s, c->g, c->tb, c->tg, x,
+                                                         (double *)c->eV, c->part);
+    launch_reduce3(c->part, c->grid, c->scal, c->s);
+    launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, g, 0, nullptr, c->s);
+    launch_dot(c->ndof, g, g, c->part, c->scal + 8, c->s);
+    HIPCHK(hipMemcpyAsync(c->hscal, c->scal, 9 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    const double bad = c->hscal[2];
+    *md = c->hscal[1];
+    *F = bad > 0.0 ? INFINITY : c->hscal[0];
+    *g2 = c->hscal[8];
+    if (bad > 0.0) return fail(TMOP_ERR_INVERTED, "det T <= 0 at a quadrature point");
+    return TMOP_OK;
+}
+
+extern "C" int tmop_energy_gradient(tmop_ctx *c, const double *x, double *F, double *md,
+                                    double *g, double *g2)
+{
+    if (!c || !x || !g) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    double f, m, gg;
+    const int r = energy_gradient_impl(c, x, &f, &m, g, &gg);
+    if (F) *F = f;
+    if (md) *md = m;
+    if (g2) *g2 = gg;
+    return r;
+}
+
 extern "C" int tmop_gradient(tmop_ctx *c, const double *x, double *g)
 {
     if (!c || !x || !g) return fail(TMOP_ERR_INVALID_ARG, "null argument");
@@ -949,13 +986,10 @@ static int newton_update(tmop_ctx *c, double *x, double &F, double &gn, int max_
     double Ft = 0.0, gtn = 0.0;
     for (int h = 0; h <= max_halvings; ++h) {
         launch_step(c->ndof, x, c->sv[SV_DX], alpha, c->sv[SV_XT], c->s);
-        double md = 0.0;
-        const int r = energy_mindet_impl(c, c->sv[SV_XT], &Ft, &md);
+        double md = 0.0, g2 = 0.0;
+        const int r = energy_gradient_impl(c, c->sv[SV_XT], &Ft, &md, c->sv[SV_GT], &g2);
         if (r != TMOP_OK && r != TMOP_ERR_INVERTED) return r;
         if (r == TMOP_OK && md > 0.0 && Ft < 1.2 * F) {
-            gradient_impl(c, c->sv[SV_XT], c->sv[SV_GT]);
-            double g2;
-            CHK(dot_host(c, c->sv[SV_GT], c->sv[SV_GT], &g2));
             gtn = std::sqrt(g2);
             if (gtn < 1.2 * gn) {
                 ok = true;
@@ -984,13 +1018,10 @@ static int solve_start(tmop_ctx *c, double *x, double &F, double &gn, tmop_solve
     double xx;
     CHK(dot_host(c, x, x, &xx));
     if (!std::isfinite(xx)) return fail(TMOP_ERR_NONFINITE, "non-finite node coordinates");
-    double md;
-    const int r = energy_mindet_impl(c, x, &F, &md);
+    double md, g2;
+    const int r = energy_gradient_impl(c, x, &F, &md, c->sv[SV_G], &g2);
     if (r != TMOP_OK) return r;
     if (!(md > 0.0)) return fail(TMOP_ERR_INVERTED, "det A <= 0 at a quadrature point");
-    gradient_impl(c, x, c->sv[SV_G]);
-    double g2;
-    CHK(dot_host(c, c->sv[SV_G], c->sv[SV_G], &g2));
     gn = std::sqrt(g2);
     rep->F0 = F;
     return TMOP_OK;

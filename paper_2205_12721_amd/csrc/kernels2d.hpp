@@ -277,7 +277,7 @@ __device__ __forceinline__ void b2_energy(const Geom &g, const Tables &tb, const
     constexpr int NR = Planes2<LIM>::NR;
     __shared__ Lds2<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 2 * S::NQ2 : 1];
-    __shared__ double red[BLOCK / 64];
+    __shared__ double red[3 * (BLOCK / 64)];
     if (LIM) lim_values2<P, NQ>(g, tb, x, e0, nel, L, U);
     gather2<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
@@ -298,17 +298,16 @@ __device__ __forceinline__ void b2_energy(const Geom &g, const Tables &tb, const
             esum += qweight2<NQ>(tb, q) * g.lim * (u0 * u0 + u1 * u1);
         }
     }
-    const double s = block_sum(esum, red);
-    const double m = block_min(dmin, red);
-    const double b = block_sum(bad, red);
+    block_energy3(esum, dmin, bad, red);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = s;
-        part[gridDim.x + blockIdx.x] = m;
-        part[2 * gridDim.x + blockIdx.x] = b;
+        part[blockIdx.x] = esum;
+        part[gridDim.x + blockIdx.x] = dmin;
+        part[2 * gridDim.x + blockIdx.x] = bad;
     }
 }
 
-template <int P, int NQ, bool LIM = false>
+// EN: also the energy partials of b2_energy, as in b3_gradient.
+template <int P, int NQ, bool LIM = false, bool EN = false>
 __device__ __forceinline__ void b2_gradient(const Geom &g, const Tables &tb, const Target &tg,
                                    const double *__restrict__ x, double *__restrict__ gE,
                                    double *__restrict__ bad, int e0, int nel)
@@ -317,21 +316,28 @@ __device__ __forceinline__ void b2_gradient(const Geom &g, const Tables &tb, con
     constexpr int NR = Planes2<LIM>::NR;
     __shared__ Lds2<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 2 * S::NQ2 : 1];
-    __shared__ double red[BLOCK / 64];
+    __shared__ double red[3 * (BLOCK / 64)];
     if (LIM) lim_values2<P, NQ>(g, tb, x, e0, nel, L, U);
     gather2<P, NQ>(g, x, e0, nel, L.X, false);
     __syncthreads();
     forward2<P, NQ, double, NR>(tb, L.X, L.R1, L.RY, nel);
-    double nbad = 0.0;
+    double nbad = 0.0, esum = 0.0, dmin = 1.0e300;
     for (int idx = threadIdx.x; idx < nel * S::NQ2; idx += BLOCK) {
         const int el = idx / S::NQ2, q = idx % S::NQ2;
         double J[4], Pm[4], mu;
         point_J2<P, NQ, double, NR>(L.RY, el, q, J);
+        if (EN) dmin = fmin(dmin, det_only<2>(J));
         const double z = qweight2<NQ>(tb, q) * tg.detW;
         if (!metric_first<2>(tg, J, z, &mu, Pm)) {
             nbad += 1.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) Pm[k] = 0.0;
+        } else if (EN) {
+            esum += z * mu;
+        }
+        if (EN && LIM) {
+            const double u0 = U[(el * 2) * S::NQ2 + q], u1 = U[(el * 2 + 1) * S::NQ2 + q];
+            esum += qweight2<NQ>(tb, q) * g.lim * (u0 * u0 + u1 * u1);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) L.RY[(el * NR + k) * S::NQ2 + q] = Pm[k];
@@ -344,8 +350,17 @@ __device__ __forceinline__ void b2_gradient(const Geom &g, const Tables &tb, con
     }
     __syncthreads();
     backward2<P, NQ, double, double, NR, LIM>(tb, g, e0, L.RY, L.R1, nel, gE);
-    const double b = block_sum(nbad, red);
-    if (threadIdx.x == 0) bad[blockIdx.x] = b;
+    if (EN) {
+        block_energy3(esum, dmin, nbad, red);
+        if (threadIdx.x == 0) {
+            bad[blockIdx.x] = esum;
+            bad[gridDim.x + blockIdx.x] = dmin;
+            bad[2 * gridDim.x + blockIdx.x] = nbad;
+        }
+    } else {
+        const double b = block_sum(nbad, red);
+        if (threadIdx.x == 0) bad[blockIdx.x] = b;
+    }
 }
 
 template <int P, int NQ, typename TT>
@@ -685,12 +700,12 @@ __global__ __launch_bounds__(BLOCK) void k2_energy(Geom g, Tables tb, Target tg,
     b2_energy<P, NQ, LIM>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, bool LIM>
+template <int P, int NQ, bool LIM, bool EN = false>
 __global__ __launch_bounds__(BLOCK) void k2_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const int e0 = blockIdx.x * EPB;
-    b2_gradient<P, NQ, LIM>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+    b2_gradient<P, NQ, LIM, EN>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT>

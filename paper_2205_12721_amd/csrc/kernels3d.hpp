@@ -574,8 +574,10 @@ __device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const
     static_assert(!(MF && LIM), "no matrix-core sweeps with the limiting term");
     __shared__ Lds3<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
-    __shared__ double red[BLOCK / 64];
-    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
+    // the matrix-core tables during the sweeps, the reduction at the end
+    constexpr int NRED = 3 * (BLOCK / 64), NMF = MF ? 2 * NQ * S::NI : 0;
+    __shared__ double red[NRED > NMF ? NRED : NMF];
+    double *mft = red;
     if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
     if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
@@ -606,20 +608,24 @@ __device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const
             esum += qweight3<NQ>(tb, q) * g.lim * y2;
         }
     }
-    const double s = block_sum(esum, red);
-    const double m = block_min(dmin, red);
-    const double b = block_sum(bad, red);
+    block_energy3(esum, dmin, bad, red);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = s;
-        part[gridDim.x + blockIdx.x] = m;
-        part[2 * gridDim.x + blockIdx.x] = b;
+        part[blockIdx.x] = esum;
+        part[gridDim.x + blockIdx.x] = dmin;
+        part[2 * gridDim.x + blockIdx.x] = bad;
     }
 }
 
 // Gradient E-vector (Sec. 3.3, eq. eq_vm_pa_grad): per point z P, then the
 // transposed contractions.  bad[blockIdx] counts points with det T <= 0.
 // LIM adds 2 w_q lim (x - x0)_c(q) wbar_i(q) through the value planes.
-template <int P, int NQ, bool LIM = false, bool MF = false>
+// EN: also the energy partials of b3_energy (the point stage evaluates mu
+// anyway): the sums, the min det and the count of points with det T <= 0 go
+// to the planes bad[blockIdx], bad[grid + blockIdx], bad[2 grid + blockIdx]
+// (the same terms in the same order as b3_energy; with mu and P both live
+// the compiler may fuse their products differently, so the energy and the
+// gradient can differ from the separate kernels' in the last bits).
+template <int P, int NQ, bool LIM = false, bool EN = false, bool MF = false>
 __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
                                    const double *__restrict__ x, double *__restrict__ gE,
                                    double *__restrict__ bad, int e0, int nel)
@@ -629,8 +635,10 @@ __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, con
     static_assert(!(MF && LIM), "no matrix-core sweeps with the limiting term");
     __shared__ Lds3<P, NQ, double, NR> L;
     __shared__ double U[LIM ? S::EPB * 3 * S::NQ3 : 1];
-    __shared__ double red[BLOCK / 64];
-    __shared__ double mft[MF ? 2 * NQ * S::NI : 1];
+    // the matrix-core tables during the sweeps, the reduction at the end
+    constexpr int NRED = 3 * (BLOCK / 64), NMF = MF ? 2 * NQ * S::NI : 0;
+    __shared__ double red[NRED > NMF ? NRED : NMF];
+    double *mft = red;
     if (LIM) lim_values3<P, NQ>(g, tb, x, e0, nel, L, U);
     if (MF) mfma_tables<S::NI, NQ>(tb, mft);
     gather3<P, NQ>(g, x, e0, nel, L.X, false);
@@ -639,16 +647,28 @@ __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, con
         forward3_mfma<P, NQ, NR>(mft, L.X, L.R1, L.R2, L.RY, nel);
     else
         forward3<P, NQ, double, NR>(tb, L.X, L.R1, L.R2, L.RY, nel);
-    double nbad = 0.0;
+    double nbad = 0.0, esum = 0.0, dmin = 1.0e300;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
         double J[9], Pm[9], mu;
         point_J3<P, NQ, double, NR>(L.RY, el, q, J);
+        if (EN) dmin = fmin(dmin, det_only<3>(J));
         const double z = point_weight3<NQ>(tb, tg, q);
         if (!metric_first<3>(tg, J, z, &mu, Pm)) {
             nbad += 1.0;
 #pragma unroll
             for (int k = 0; k < 9; ++k) Pm[k] = 0.0;
+        } else if (EN) {
+            esum += z * mu;
+        }
+        if (EN && LIM) {
+            double y2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u = U[(el * 3 + c) * S::NQ3 + q];
+                y2 += u * u;
+            }
+            esum += qweight3<NQ>(tb, q) * g.lim * y2;
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) L.RY[(el * NR + k) * S::NQ3 + q] = Pm[k];
@@ -661,8 +681,17 @@ __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, con
     }
     __syncthreads();
     backward3<P, NQ, double, double, NR, LIM>(tb, g, e0, L.RY, L.R2, L.R1, nel, gE);
-    const double b = block_sum(nbad, red);
-    if (threadIdx.x == 0) bad[blockIdx.x] = b;
+    if (EN) {
+        block_energy3(esum, dmin, nbad, red);
+        if (threadIdx.x == 0) {
+            bad[blockIdx.x] = esum;
+            bad[gridDim.x + blockIdx.x] = dmin;
+            bad[2 * gridDim.x + blockIdx.x] = nbad;
+        }
+    } else {
+        const double b = block_sum(nbad, red);
+        if (threadIdx.x == 0) bad[blockIdx.x] = b;
+    }
 }
 
 // Hessian setup (Sec. 3.4): per point the packed z * H_A tensor, stored
@@ -1400,12 +1429,12 @@ __global__ __launch_bounds__(BLOCK) void k3_energy(Geom g, Tables tb, Target tg,
     b3_energy<P, NQ, LIM, MF>(g, tb, tg, x, part, e0, min(EPB, g.ne - e0));
 }
 
-template <int P, int NQ, bool LIM, bool MF = false>
+template <int P, int NQ, bool LIM, bool EN = false, bool MF = false>
 __global__ __launch_bounds__(BLOCK) void k3_gradient(Geom g, Tables tb, Target tg, const double *__restrict__ x, double *__restrict__ gE, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
-    b3_gradient<P, NQ, LIM, MF>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
+    b3_gradient<P, NQ, LIM, EN, MF>(g, tb, tg, x, gE, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT, bool MF = false>

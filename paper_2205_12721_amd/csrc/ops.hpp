@@ -15,6 +15,9 @@ struct Ops {
                    const double *x, double *part);
     void (*gradient)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
                      const double *x, double *gE, double *bad);
+    // gradient E-vector plus the energy partials (three planes of grid
+    // entries in part, as energy writes them)
+    decltype(gradient) gradientE;
     void (*setup64)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
                     const double *x, double *H, double *bad);
     void (*setup32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
@@ -52,7 +55,7 @@ struct Ops {
     // and the FP64 setups without the limiting term; null where the class
     // has no such form (quads, n_q > 5)
     decltype(energy) energyM;
-    decltype(gradient) gradientM;
+    decltype(gradient) gradientM, gradientEM;
     decltype(setup64) setupM64;
     decltype(setupc64) setupcM64;
 };
@@ -92,6 +95,7 @@ inline void fill_tiles_k2(Ops &o)
     }
     o.energyM = nullptr;
     o.gradientM = nullptr;
+    o.gradientEM = nullptr;
     o.setupM64 = nullptr;
     o.setupcM64 = nullptr;
 }
@@ -230,6 +234,14 @@ bool ops3_p4(int nq, Ops *out);
                 hipLaunchKernelGGL((K##_gradient<P, NQ, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, bad); \
             } else {                                                                         \
                 hipLaunchKernelGGL((K##_gradient<P, NQ, false>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, bad); \
+            }                                                                      \
+        };                                                                                       \
+        o.gradientE = [](int grid, hipStream_t s, const Geom &g, const Tables &t,               \
+                         const Target &w, const double *x, double *gE, double *part) {          \
+            if (g.lim != 0.0) {                                                                   \
+                hipLaunchKernelGGL((K##_gradient<P, NQ, true, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, part); \
+            } else {                                                                         \
+                hipLaunchKernelGGL((K##_gradient<P, NQ, false, true>), dim3(grid), dim3(BLOCK), 0, s, g, t, w, x, gE, part); \
             }                                                                      \
         };                                                                                       \
         o.setup64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w, \

@@ -54,8 +54,13 @@ inline void fill_mfma3(Ops &o)
         };
         o.gradientM = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
                          const Target &w, const double *x, double *gE, double *bad) {
-            hipLaunchKernelGGL((k3_gradient<P, NQ, false, true>), dim3(grid), dim3(BLOCK), 0, s,
-                               g, t, w, x, gE, bad);
+            hipLaunchKernelGGL((k3_gradient<P, NQ, false, false, true>), dim3(grid), dim3(BLOCK),
+                               0, s, g, t, w, x, gE, bad);
+        };
+        o.gradientEM = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
+                          const Target &w, const double *x, double *gE, double *part) {
+            hipLaunchKernelGGL((k3_gradient<P, NQ, false, true, true>), dim3(grid), dim3(BLOCK),
+                               0, s, g, t, w, x, gE, part);
         };
         o.setupM64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t,
                         const Target &w, const double *x, double *H, double *bad) {
@@ -70,6 +75,7 @@ inline void fill_mfma3(Ops &o)
     } else {
         o.energyM = nullptr;
         o.gradientM = nullptr;
+        o.gradientEM = nullptr;
         o.setupM64 = nullptr;
         o.setupcM64 = nullptr;
     }

@@ -257,6 +257,34 @@ __device__ inline double block_min(double v, double *red)
     return s;
 }
 
+// The energy partials of a workgroup: sum of s, min of m, sum of b, with the
+// shuffles and the order of block_sum / block_min but one exchange through
+// LDS (red holds 3 BLOCK/64 doubles).  Results valid in thread 0.
+__device__ inline void block_energy3(double &s, double &m, double &b, double *red)
+{
+    constexpr int NW = BLOCK / 64;
+    s = wave_sum(s);
+    m = wave_min(m);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[w] = s;
+        red[NW + w] = m;
+        red[2 * NW + w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = red[NW], e = 0.0;
+        for (int k = 0; k < NW; ++k) a += red[k];
+        for (int k = 1; k < NW; ++k) c = fmin(c, red[NW + k]);
+        for (int k = 0; k < NW; ++k) e += red[2 * NW + k];
+        s = a;
+        m = c;
+        b = e;
+    }
+}
+
 // ------------------------------------------------------------------------
 // Quality metrics at one point (T = A W^{-1}); closed-form derivatives of
 // mu_2 = |T|^2/(2 tau) - 1 and mu_303 = |T|^2/(3 tau^{2/3}) - 1.

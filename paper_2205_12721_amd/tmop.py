@@ -94,6 +94,7 @@ SIGNATURES = {
     "tmop_min_det": [_P, _P, _D],
     "tmop_energy_mindet": [_P, _P, _D, _D],
     "tmop_gradient": [_P, _P, _P],
+    "tmop_energy_gradient": [_P, _P, _D, _D, _P, _D],
     "tmop_hessian_setup": [_P, _P],
     "tmop_hessian_apply": [_P, _P, _P],
     "tmop_hessian_diag": [_P, _P],
@@ -305,6 +306,16 @@ class Context:
         out = self.new_vector() if out is None else out
         _check(lib().tmop_gradient(self._h, self._vec(x), self._vec(out)))
         return out
+
+    def energy_gradient(self, x, out=None):
+        """(F, min det A, g, |g|^2) in one element pass; F = inf when inverted."""
+        out = self.new_vector() if out is None else out
+        F, m, g2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        code = lib().tmop_energy_gradient(self._h, self._vec(x), ctypes.byref(F),
+                                          ctypes.byref(m), self._vec(out), ctypes.byref(g2))
+        if code not in (0, ERR_INVERTED):
+            _check(code)
+        return F.value, m.value, out, g2.value
 
     def hessian_setup(self, x):
         _check(lib().tmop_hessian_setup(self._h, self._vec(x)))
