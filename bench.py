@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "d6c27bb096e07f1c81cea5e65d1b30154e40d24c4f074b9bf7b574a07e6ddfab"
+_SHA_C2 = "b7b511e7c8a788bd6854d430717a0633e8611f7b4cb7f73425034cf7ed616003"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 719663718, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714364595, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 366581976, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 371503330, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 245108666, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249302013, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 135357383, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137370825, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 

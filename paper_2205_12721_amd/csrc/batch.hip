@@ -1073,6 +1073,8 @@ static double *vpart1_at(tmop_pool *P, int par)
     return par ? P->d_part + P->epart + 2 * P->vts.size() : vpart1(P);
 }
 
+// One element kernel over every class's tiles: which = 0 energy, 1 gradient,
+// 2 setup, 3 Hessian action, 4 diagonal, 5 gradient with the energy partials.
 static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
 {
     for (auto &kv : P->classes) {
@@ -1085,7 +1087,8 @@ static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
                         : which == 1 ? c.bops.gradientL
                         : which == 2 ? c.bops.setup[st][pr]
                         : which == 3 ? c.bops.applyL[st][pr]
-                                     : c.bops.diagL[st][pr];
+                        : which == 4 ? c.bops.diagL[st][pr]
+                                     : c.bops.gradientEL;
             f(nt, P->s, c.tb, c.d_tiles, P->d_slots, gate, vin, P->d_part + c.pbase);
             continue;
         }
@@ -1098,7 +1101,8 @@ static void launch_elem(tmop_pool *P, int which, const int *gate, int vin)
                     : which == 1 ? c.bops.gradient
                     : which == 2 ? c.bops.setup[st][pr]
                     : which == 3 ? c.bops.apply[st][pr]
-                                 : c.bops.diag[st][pr];
+                    : which == 4 ? c.bops.diag[st][pr]
+                                 : c.bops.gradientE;
         f(nt, P->s, c.tb, c.d_tiles, P->d_slots, gate, vin, P->d_part + c.pbase);
     }
 }
@@ -1144,6 +1148,16 @@ static void gradient_to(tmop_pool *P, const int *gate, int vin, int vout)
 {
     launch_elem(P, 1, gate, vin);
     launch_gather(P, gate, vout, 0, vout, false);
+}
+
+// One element pass for both (the gradient kernel also sums the energy):
+// F, min det and the bad count of the slots of gate ge into sc, their
+// gradient E-vectors into the slots' eV; the gather of g into vout follows
+// separately, for the slots that need it.
+static void energy_grad_elem(tmop_pool *P, const int *ge, int vin)
+{
+    launch_elem(P, 5, ge, vin);
+    hipLaunchKernelGGL(kr_energy, dim3(P->max_slots), dim3(VB), 0, P->s, P->d_rg, ge, P->d_part, P->d_sc);
 }
 
 static int read_sc(tmop_pool *P)
@@ -1254,9 +1268,9 @@ static void ls_round_device(tmop_pool *P, int h)
 {
     const int M = P->max_slots, nv = nvt_all(P);
     hipLaunchKernelGGL(kv_step, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_search, P->d_sc);
-    energy_to_sc(P, P->d_search, BXT);
+    energy_grad_elem(P, P->d_search, BXT);
     hipLaunchKernelGGL(kn_ls_trial, dim3(nblk(M)), dim3(VB), 0, P->s, M, P->d_search, P->d_sc, P->d_ns, P->d_ftest);
-    gradient_to(P, P->d_ftest, BXT, BGT);
+    launch_gather(P, P->d_ftest, BGT, 0, BGT, false);
     dot_to_sc(P, P->d_ftest, BGT, BGT, SC_DOT);
     hipLaunchKernelGGL(kn_ls_decide, dim3(nblk(M)), dim3(VB), 0, P->s, M, h, P->d_search, P->d_ftest, P->d_sc, P->d_ns, P->d_acc);
     hipLaunchKernelGGL(kv_copy, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, P->d_acc, BXT, BX);
@@ -1373,8 +1387,8 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
         PCHK(upload_gate(P, 0));
         const int *g0 = P->d_gate[0];
         dot_to_sc(P, g0, BX, BX, SC_DOT);
-        energy_to_sc(P, g0, BX);
-        gradient_to(P, g0, BX, BG);
+        energy_grad_elem(P, g0, BX);
+        launch_gather(P, g0, BG, 0, BG, false);
         PCHK(read_sc(P));
         std::vector<double> xx(M);
         for (int si = 0; si < M; ++si) xx[si] = P->h_sc[si * NSC + SC_DOT];
@@ -1469,7 +1483,7 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
             PHIP(hipMemcpyAsync(P->d_sc, P->h_sc, sizeof(double) * NSC * M, hipMemcpyHostToDevice, P->s));
             const int *g2 = P->d_gate[2];
             hipLaunchKernelGGL(kv_step, dim3(nv), dim3(VB), 0, P->s, P->d_vt, P->d_slots, g2, P->d_sc);
-            energy_to_sc(P, g2, BXT);
+            energy_grad_elem(P, g2, BXT);
             PCHK(read_sc(P));
             bool any3 = false;
             std::vector<double> Ft(M);
@@ -1484,7 +1498,7 @@ static int pool_step_impl(tmop_pool *P, int *n_active)
             if (any3) {
                 PCHK(upload_gate(P, 3));
                 const int *g3 = P->d_gate[3];
-                gradient_to(P, g3, BXT, BGT);
+                launch_gather(P, g3, BGT, 0, BGT, false);
                 dot_to_sc(P, g3, BGT, BGT, SC_DOT);
                 PCHK(read_sc(P));
                 bool anyacc = false;

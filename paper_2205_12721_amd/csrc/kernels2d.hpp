@@ -766,14 +766,14 @@ __global__ __launch_bounds__(BLOCK) void kb2_energy(Tables tb, const Tile *__res
     b2_energy<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, bool LIM = false>
+template <int P, int NQ, bool LIM = false, bool EN = false>
 __global__ __launch_bounds__(BLOCK) void kb2_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
 {
     constexpr int EPB = S2<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b2_gradient<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+    b2_gradient<P, NQ, LIM, EN>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>

@@ -462,10 +462,11 @@ __device__ __forceinline__ double point_weight3(const Tables &tb, const Target &
 // ------------------------------------------------------------------------
 // Quadrature data layout per element (hex kernels): NS values per point in
 // runs of VEC = 16 / sizeof(TT) consecutive values per point, [run][q][VEC],
-// then the NS % VEC remaining values as plain planes [s][q]; element blocks
-// of qdata_stride(NS, NQT, sizeof(TT)) values.  A lane reads or writes VEC
-// values of its point with one 16-byte access, and the lanes of a wave cover
-// consecutive 16-byte words.
+// then the NS % VEC remaining values as plain planes [s][q]; runs and planes
+// hold NQP = qdata_pts(NQT) points (the last NQP - NQT unused), so each
+// starts on a 128-byte line; element blocks of qdata_stride(NS, NQT,
+// sizeof(TT)) values.  A lane reads or writes VEC values of its point with
+// one 16-byte access, and the lanes of a wave cover consecutive 16-byte words.
 // ------------------------------------------------------------------------
 template <typename TT>
 struct alignas(16) Vec16 {
@@ -477,7 +478,9 @@ struct QLay {
     static constexpr int VEC = 16 / sizeof(TT);
     static constexpr int NV = NS / VEC;    // full runs
     static constexpr int TAIL = NV * VEC;  // first value stored in a plain plane
+    static constexpr long NQP = qdata_pts(NQT, sizeof(TT));  // points per run / plane
     static constexpr long STRIDE = qdata_stride(NS, NQT, sizeof(TT));
+    static_assert(NQP * 16 % 128 == 0 && NQP * sizeof(TT) % 128 == 0, "line-aligned runs");
 };
 
 // NT: non-temporal loads, for a stream read once per call that should not
@@ -489,14 +492,14 @@ __device__ __forceinline__ void qdata_load(const TT *__restrict__ he, int q, TT 
     typedef TT V __attribute__((ext_vector_type(L::VEC)));
 #pragma unroll
     for (int r = 0; r < L::NV; ++r) {
-        const V *a = (const V *)(he + ((long)r * NQT + q) * L::VEC);
+        const V *a = (const V *)(he + (r * L::NQP + q) * L::VEC);
         const V w = NT ? __builtin_nontemporal_load(a) : *a;
 #pragma unroll
         for (int k = 0; k < L::VEC; ++k) out[r * L::VEC + k] = w[k];
     }
 #pragma unroll
     for (int s = L::TAIL; s < NS; ++s) {
-        const TT *a = he + (long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q;
+        const TT *a = he + L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q;
         out[s] = NT ? __builtin_nontemporal_load(a) : *a;
     }
 }
@@ -510,10 +513,10 @@ __device__ __forceinline__ void qdata_store(TT *__restrict__ he, int q, const TT
         Vec16<TT> w;
 #pragma unroll
         for (int k = 0; k < L::VEC; ++k) w.v[k] = in[r * L::VEC + k];
-        *(Vec16<TT> *)(he + ((long)r * NQT + q) * L::VEC) = w;
+        *(Vec16<TT> *)(he + (r * L::NQP + q) * L::VEC) = w;
     }
 #pragma unroll
-    for (int s = L::TAIL; s < NS; ++s) he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q] = in[s];
+    for (int s = L::TAIL; s < NS; ++s) he[L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q] = in[s];
 }
 
 // one value s (diagonal kernels read a subset)
@@ -521,8 +524,8 @@ template <typename TT, int NS, int NQT>
 __device__ __forceinline__ TT qdata_at(const TT *__restrict__ he, int q, int s)
 {
     using L = QLay<TT, NS, NQT>;
-    return s < L::TAIL ? he[((long)(s / L::VEC) * NQT + q) * L::VEC + s % L::VEC]
-                       : he[(long)L::TAIL * NQT + (long)(s - L::TAIL) * NQT + q];
+    return s < L::TAIL ? he[((s / L::VEC) * L::NQP + q) * L::VEC + s % L::VEC]
+                       : he[L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q];
 }
 
 // ------------------------------------------------------------------------
@@ -1495,14 +1498,14 @@ __global__ __launch_bounds__(BLOCK) void kb3_energy(Tables tb, const Tile *__res
     b3_energy<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], part, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
-template <int P, int NQ, bool LIM = false>
+template <int P, int NQ, bool LIM = false, bool EN = false>
 __global__ __launch_bounds__(BLOCK) void kb3_gradient(Tables tb, const Tile *__restrict__ tiles, const SlotDev *__restrict__ slots, const int *__restrict__ gate, int vin, double *__restrict__ bad)
 {
     constexpr int EPB = S3<P, NQ>::EPB;
     const Tile t = tiles[blockIdx.x];
     if (gate && !gate[t.slot]) return;
     const SlotDev &s = slots[t.slot];
-    b3_gradient<P, NQ, LIM>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
+    b3_gradient<P, NQ, LIM, EN>(s.g, tb, s.tg, s.vec[vin], (double *)s.eV, bad, t.e0, min(EPB, s.g.ne - t.e0));
 }
 
 template <int P, int NQ, typename TT>

@@ -69,6 +69,8 @@ typedef void (*BLaunch)(int grid, hipStream_t, const Tables &, const Tile *, con
 struct BOps {
     int epb;
     BLaunch energy, gradient;
+    // gradient plus the energy partials of energy (same three planes)
+    BLaunch gradientE, gradientEL;
     BLaunch setup[2][2];  // [storage tensor/compact][fp64/fp32]
     BLaunch apply[2][2];
     BLaunch diag[2][2];
@@ -143,6 +145,16 @@ bool bops3_p4(int nq, BOps *out);
                         const SlotDev *sl, const int *gt, int vin, double *part) {             \
             hipLaunchKernelGGL((K##_gradient<P, NQ>), dim3(grid), dim3(BLOCK), 0, s, t, tl, sl, \
                                gt, vin, part);                                                 \
+        };                                                                                     \
+        o.gradientE = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,              \
+                         const SlotDev *sl, const int *gt, int vin, double *part) {            \
+            hipLaunchKernelGGL((K##_gradient<P, NQ, false, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, \
+                               sl, gt, vin, part);                                             \
+        };                                                                                     \
+        o.gradientEL = [](int grid, hipStream_t s, const Tables &t, const Tile *tl,             \
+                          const SlotDev *sl, const int *gt, int vin, double *part) {           \
+            hipLaunchKernelGGL((K##_gradient<P, NQ, true, true>), dim3(grid), dim3(BLOCK), 0, s, t, tl, \
+                               sl, gt, vin, part);                                             \
         };                                                                                     \
         o.energyL = [](int grid, hipStream_t s, const Tables &t, const Tile *tl, const SlotDev *sl, \
                        const int *gt, int vin, double *part) {                                 \

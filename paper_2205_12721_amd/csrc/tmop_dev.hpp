@@ -294,12 +294,20 @@ __device__ inline void block_energy3(double &s, double &m, double &b, double *re
 //   d2mu  = c_id Id + c_tc (T (x) C + C (x) T) + c_cc C (x) C + c_dc dC/dT
 // ------------------------------------------------------------------------
 
-// Quadrature data of one element: ns values per point at nqt points, the
-// element's block padded to a multiple of 16 bytes so that every element
-// starts 16-byte aligned (the hex kernels read it with 16-byte loads).
+// Quadrature data of one element: ns values per point, stored for nqt
+// points rounded up to qdata_pts(nqt, tbytes) so that every plane of one
+// value per point (tbytes each) and every run of 16 bytes per point starts
+// on a 128-byte cache line (element blocks included).  Without the padding
+// a line that straddles two runs was fetched from HBM once for each run the
+// streaming loads read it for.  No lane reads or writes the padding.
+inline __host__ __device__ constexpr int qdata_pts(int nqt, int tbytes)
+{
+    return (nqt + 128 / tbytes - 1) / (128 / tbytes) * (128 / tbytes);
+}
+
 inline __host__ __device__ constexpr long qdata_stride(int ns, int nqt, int tbytes)
 {
-    return ((long)ns * nqt + 16 / tbytes - 1) / (16 / tbytes) * (16 / tbytes);
+    return (long)ns * qdata_pts(nqt, tbytes);
 }
 
 // Metrics with kernels: 2, 7, 9, 55 in 2D; 303, 55 in 3D.
