@@ -224,6 +224,15 @@ int tmop_hessian_apply(tmop_ctx *ctx, const double *v_dev, double *y_dev);
 /* Diagonal of H_c (fixed entries 1) from the last setup.  Asynchronous. */
 int tmop_hessian_diag(tmop_ctx *ctx, double *d_dev);
 
+/* tmop_hessian_setup at x followed by tmop_hessian_diag into d_dev (device,
+ * d*N_x), in one element pass where the class allows it (hex classes whose
+ * n_q^3 points times elements per workgroup fit one workgroup pass, pencil
+ * sweeps; tensor or compact storage): the per-point data feeds the
+ * diagonal's contraction on chip instead of being read back from HBM
+ * (Sec. 3.4; the Newton solver's Jacobi preconditioner uses this).  The stored data and d
+ * are bitwise those of the two separate calls.  Asynchronous. */
+int tmop_hessian_setup_diag(tmop_ctx *ctx, const double *x_dev, double *d_dev);
+
 /* ---------------------------------------------------------------------- */
 /* Newton-MINRES solve (Sec. 2.3)                                          */
 /* ---------------------------------------------------------------------- */

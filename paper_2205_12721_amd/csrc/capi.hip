@@ -660,6 +660,27 @@ extern "C" int tmop_hessian_apply(tmop_ctx *c, const double *v, double *y)
     return TMOP_OK;
 }
 
+// Setup and the element diagonal (into eV) in one kernel, where the class
+// has it (hexes with one pass of points per workgroup, pencil sweeps);
+// false, with nothing launched, elsewhere.
+static bool setup_diag_impl(tmop_ctx *c, const double *x)
+{
+    if (use_mfma(c)) return false;
+    const bool cp = c->storage == TMOP_HESS_COMPACT;
+    if (c->precision == TMOP_MIXED) {
+        const auto f = cp ? c->ops.setupcd32 : c->ops.setupd32;
+        if (!f) return false;
+        f(c->grid, c->s, c->g, c->tb, c->tg, x, (float *)c->H, (double *)c->eV, c->part);
+    } else {
+        const auto f = cp ? c->ops.setupcd64 : c->ops.setupd64;
+        if (!f) return false;
+        f(c->grid, c->s, c->g, c->tb, c->tg, x, (double *)c->H, (double *)c->eV, c->part);
+    }
+    c->have_setup = true;
+    c->have_diag = false;
+    return true;
+}
+
 static void diag_impl(tmop_ctx *c, double *d)
 {
     if (c->storage == TMOP_HESS_COMPACT) {
@@ -679,6 +700,25 @@ extern "C" int tmop_hessian_diag(tmop_ctx *c, double *d)
     if (!c || !d) return fail(TMOP_ERR_INVALID_ARG, "null argument");
     if (!c->have_setup) return fail(TMOP_ERR_STATE, "tmop_hessian_setup was not called");
     diag_impl(c, d);
+    HIPCHK(hipGetLastError());
+    return TMOP_OK;
+}
+
+// Setup and diagonal: one kernel where the class has it, else the two.
+static void setup_diag_to(tmop_ctx *c, const double *x, double *d)
+{
+    if (setup_diag_impl(c, x)) {
+        launch_gather(c->g, c->csr_ptr, c->csr_ent, c->eV, false, d, 1, nullptr, c->s);
+    } else {
+        setup_impl(c, x);
+        diag_impl(c, d);
+    }
+}
+
+extern "C" int tmop_hessian_setup_diag(tmop_ctx *c, const double *x, double *d)
+{
+    if (!c || !x || !d) return fail(TMOP_ERR_INVALID_ARG, "null argument");
+    setup_diag_to(c, x, d);
     HIPCHK(hipGetLastError());
     return TMOP_OK;
 }
@@ -745,12 +785,18 @@ static int dot_host(tmop_ctx *c, const double *a, const double *b, double *out)
     return TMOP_OK;
 }
 
-static void make_jacobi(tmop_ctx *c)
+// The Jacobi preconditioner from the diagonal in c->diag.
+static void jacobi_from_diag(tmop_ctx *c)
 {
-    diag_impl(c, c->diag);
     launch_absmax(c->ndof, c->diag, c->part, c->scal + 9, c->s);
     launch_jacobi(c->ndof, c->diag, c->scal + 9, c->minv, c->s);
     c->have_diag = true;
+}
+
+static void make_jacobi(tmop_ctx *c)
+{
+    diag_impl(c, c->diag);
+    jacobi_from_diag(c);
 }
 
 // Room for nvec resident Lanczos vectors, within bank_limit.  False (and
@@ -963,8 +1009,12 @@ static int newton_update(tmop_ctx *c, double *x, double &F, double &gn, int max_
     double t0 = now_ms();
     {
         TraceRange r("tmop setup+diagonal");
-        setup_impl(c, x);
-        if (jacobi) make_jacobi(c);
+        if (jacobi) {
+            setup_diag_to(c, x, c->diag);
+            jacobi_from_diag(c);
+        } else {
+            setup_impl(c, x);
+        }
         HIPCHK(hipStreamSynchronize(c->s));
     }
     double t1 = now_ms();

@@ -1071,6 +1071,35 @@ __device__ __forceinline__ void b3_apply_layers(const Geom &g, const Tables &tb,
     backward3_tail<P, NQ, CT, CT, !COMPACT>(tb, g, e0, A.R2, B.R1, nel, yE);
 }
 
+// The compact data of one point (T and z times the four metric
+// coefficients), rounded to TT as stored; all zero and false when det T <= 0.
+template <typename TT>
+__device__ __forceinline__ bool compact_point3(const Target &tg, const double *J, double z, TT *hs)
+{
+    double T[9], C[9], out[NC3];
+    apply_winv<3>(tg, J, T);
+    const double tau = det_cof<3>(T, C);
+    const bool ok = tau > 0.0;
+    if (ok) {
+        double I1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) I1 += T[k] * T[k];
+        const MetricCoef m = metric_coef(tg.metric, I1, tau);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k] = T[k];
+        out[9] = z * m.c_id;
+        out[10] = z * m.c_tc;
+        out[11] = z * m.c_cc;
+        out[12] = z * m.c_dc;
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC3; ++k) out[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NC3; ++k) hs[k] = (TT)out[k];
+    return ok;
+}
+
 template <int P, int NQ, typename TT, bool MF = false>
 __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const Target &tg,
                                  const double *__restrict__ x, TT *__restrict__ Q,
@@ -1090,30 +1119,10 @@ __device__ __forceinline__ void b3_setupc(const Geom &g, const Tables &tb, const
     double nbad = 0.0;
     for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
         const int el = idx / S::NQ3, q = idx % S::NQ3;
-        double J[9], T[9], C[9], out[NC3];
+        double J[9];
         point_J3<P, NQ>(L.RY, el, q, J);
-        apply_winv<3>(tg, J, T);
-        const double tau = det_cof<3>(T, C);
-        const double z = point_weight3<NQ>(tb, tg, q);
-        if (tau > 0.0) {
-            double I1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) I1 += T[k] * T[k];
-            const MetricCoef m = metric_coef(tg.metric, I1, tau);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) out[k] = T[k];
-            out[9] = z * m.c_id;
-            out[10] = z * m.c_tc;
-            out[11] = z * m.c_cc;
-            out[12] = z * m.c_dc;
-        } else {
-            nbad += 1.0;
-#pragma unroll
-            for (int k = 0; k < NC3; ++k) out[k] = 0.0;
-        }
         TT hs[NC3];
-#pragma unroll
-        for (int k = 0; k < NC3; ++k) hs[k] = (TT)out[k];
+        if (!compact_point3<TT>(tg, J, point_weight3<NQ>(tb, tg, q), hs)) nbad += 1.0;
         qdata_store<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hs);
     }
     const double b = block_sum(nbad, red);
@@ -1361,20 +1370,14 @@ __device__ __forceinline__ void b3_diag(const Geom &g, const Tables &tb, const T
     diag_contract3<P, NQ, LIM>(tb, g, e0, L, nel, dE);
 }
 
-// Diagonal from compact data: within one component a the cofactor-derivative
-// term vanishes, so H[an,ap] = c_id (W^-1 W^-T)_np + c_tc (Tw_an Cw_ap +
-// Cw_an Tw_ap) + c_cc Cw_an Cw_ap with Tw = T W^{-T}, Cw = C W^{-T}.
-template <int P, int NQ, typename TT, bool LIM = false>
-__device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const Target &tg,
-                                const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+// The diagonal's LDS planes of one point from its compact data (b3_diagc).
+template <int P, int NQ, typename TT, bool LIM>
+__device__ __forceinline__ void diagc_point3(const Tables &tb, const Geom &g, const Target &tg,
+                                    const TT *hr, DiagLds3<P, NQ, LIM> &L, int el, int q)
 {
     using S = S3<P, NQ>;
     constexpr int NPR = DiagLds3<P, NQ, LIM>::NPR;
-    __shared__ DiagLds3<P, NQ, LIM> L;
-    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
-        const int el = idx / S::NQ3, q = idx % S::NQ3;
-        TT hr[NC3];
-        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hr);
+    {
         double T[9], C[9], Tw[9], Cw[9], WW[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) T[k] = (double)hr[k];
@@ -1414,7 +1417,123 @@ __device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const 
         }
         diag_lim3<P, NQ, LIM>(tb, g, L, el, q);
     }
+}
+
+// Diagonal from compact data: within one component a the cofactor-derivative
+// term vanishes, so H[an,ap] = c_id (W^-1 W^-T)_np + c_tc (Tw_an Cw_ap +
+// Cw_an Tw_ap) + c_cc Cw_an Cw_ap with Tw = T W^{-T}, Cw = C W^{-T}.
+template <int P, int NQ, typename TT, bool LIM = false>
+__device__ __forceinline__ void b3_diagc(const Geom &g, const Tables &tb, const Target &tg,
+                                const TT *__restrict__ Q, double *__restrict__ dE, int e0, int nel)
+{
+    using S = S3<P, NQ>;
+    __shared__ DiagLds3<P, NQ, LIM> L;
+    for (int idx = threadIdx.x; idx < nel * S::NQ3; idx += BLOCK) {
+        const int el = idx / S::NQ3, q = idx % S::NQ3;
+        TT hr[NC3];
+        qdata_load<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hr);
+        diagc_point3<P, NQ, TT, LIM>(tb, g, tg, hr, L, el, q);
+    }
     diag_contract3<P, NQ, LIM>(tb, g, e0, L, nel, dE);
+}
+
+// Hessian setup and the element part of the Hessian diagonal in one pass
+// (Sec. 3.4, the diagonal in its last paragraph), for the Jacobi
+// preconditioner of each Newton step: the setup's per-point tensor, rounded to
+// TT as it is stored, fills the diagonal's LDS planes at once instead of being
+// read back from HBM by b3_diag.  The diagonal's buffers overlay the sweeps'
+// (every lane holds its J before the barrier that hands the memory over), so
+// the workgroup needs no more LDS than b3_diag.  Classes whose points fit one
+// pass of the workgroup.  H, bad and dE are bitwise those of b3_setup then
+// b3_diag.
+template <int P, int NQ, typename TT, bool LIM>
+__device__ __forceinline__ void b3_setupd(const Geom &g, const Tables &tb, const Target &tg,
+                                 const double *__restrict__ x, TT *__restrict__ H,
+                                 double *__restrict__ dE, double *__restrict__ bad, int e0,
+                                 int nel)
+{
+    using S = S3<P, NQ>;
+    static_assert(S::EPB * S::NQ3 <= BLOCK, "one pass over the workgroup's points");
+    constexpr int NPR = DiagLds3<P, NQ, LIM>::NPR;
+    union Buf {
+        Lds3<P, NQ, double> s;
+        DiagLds3<P, NQ, LIM> d;
+    };
+    __shared__ Buf L;
+    __shared__ double red[BLOCK / 64];
+    gather3<P, NQ>(g, x, e0, nel, L.s.X, false);
+    __syncthreads();
+    forward3<P, NQ>(tb, L.s.X, L.s.R1, L.s.R2, L.s.RY, nel);
+    const bool act = (int)threadIdx.x < nel * S::NQ3;
+    const int el = act ? threadIdx.x / S::NQ3 : 0, q = act ? threadIdx.x % S::NQ3 : 0;
+    double J[9];
+    if (act) point_J3<P, NQ>(L.s.RY, el, q, J);
+    __syncthreads();
+    double nbad = 0.0;
+    if (act) {
+        double Hp[45];
+        const double z = point_weight3<NQ>(tb, tg, q);
+        if (!metric_second<3>(tg, J, z, Hp)) {
+            nbad = 1.0;
+#pragma unroll
+            for (int k = 0; k < 45; ++k) Hp[k] = 0.0;
+        }
+        using QL = QLay<TT, 45, S::NQ3>;
+        TT hs[45];
+#pragma unroll
+        for (int k = 0; k < 45; ++k) hs[k] = (TT)Hp[k];
+        qdata_store<TT, 45, S::NQ3>(H + (size_t)(e0 + el) * QL::STRIDE, q, hs);
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr) {
+            const int n = diag_pn(pr), p = diag_pp(pr);
+            const double f = (n == p) ? 1.0 : 2.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                L.d.sQ[((el * NPR + pr) * 3 + a) * S::NQ3 + q] =
+                    f * (double)hs[sym_index<9>(a * 3 + n, a * 3 + p)];
+        }
+        diag_lim3<P, NQ, LIM>(tb, g, L.d, el, q);
+    }
+    diag_contract3<P, NQ, LIM>(tb, g, e0, L.d, nel, dE);
+    const double b = block_sum(nbad, red);
+    if (threadIdx.x == 0) bad[blockIdx.x] = b;
+}
+
+// The same for compact storage: the setup's compact values, rounded to TT as
+// stored, give the diagonal's planes as b3_diagc computes them from the
+// stored data.  Q, bad and dE are bitwise those of b3_setupc then b3_diagc.
+template <int P, int NQ, typename TT, bool LIM>
+__device__ __forceinline__ void b3_setupcd(const Geom &g, const Tables &tb, const Target &tg,
+                                  const double *__restrict__ x, TT *__restrict__ Q,
+                                  double *__restrict__ dE, double *__restrict__ bad, int e0,
+                                  int nel)
+{
+    using S = S3<P, NQ>;
+    static_assert(S::EPB * S::NQ3 <= BLOCK, "one pass over the workgroup's points");
+    union Buf {
+        Lds3<P, NQ, double> s;
+        DiagLds3<P, NQ, LIM> d;
+    };
+    __shared__ Buf L;
+    __shared__ double red[BLOCK / 64];
+    gather3<P, NQ>(g, x, e0, nel, L.s.X, false);
+    __syncthreads();
+    forward3<P, NQ>(tb, L.s.X, L.s.R1, L.s.R2, L.s.RY, nel);
+    const bool act = (int)threadIdx.x < nel * S::NQ3;
+    const int el = act ? threadIdx.x / S::NQ3 : 0, q = act ? threadIdx.x % S::NQ3 : 0;
+    double J[9];
+    if (act) point_J3<P, NQ>(L.s.RY, el, q, J);
+    __syncthreads();
+    double nbad = 0.0;
+    if (act) {
+        TT hs[NC3];
+        if (!compact_point3<TT>(tg, J, point_weight3<NQ>(tb, tg, q), hs)) nbad = 1.0;
+        qdata_store<TT, NC3, S::NQ3>(Q + (size_t)(e0 + el) * QLay<TT, NC3, S::NQ3>::STRIDE, q, hs);
+        diagc_point3<P, NQ, TT, LIM>(tb, g, tg, hs, L.d, el, q);
+    }
+    diag_contract3<P, NQ, LIM>(tb, g, e0, L.d, nel, dE);
+    const double b = block_sum(nbad, red);
+    if (threadIdx.x == 0) bad[blockIdx.x] = b;
 }
 
 // ------------------------------------------------------------------------
@@ -1478,6 +1597,22 @@ __global__ __launch_bounds__(BLOCK) void k3_diag(Geom g, Tables tb, const TT *__
     constexpr int EPB = S3<P, NQ>::EPB;
     const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
     b3_diag<P, NQ, TT, LIM>(g, tb, H, dE, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, bool LIM>
+__global__ __launch_bounds__(BLOCK) void k3_setupd(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ H, double *__restrict__ dE, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
+    b3_setupd<P, NQ, TT, LIM>(g, tb, tg, x, H, dE, bad, e0, min(EPB, g.ne - e0));
+}
+
+template <int P, int NQ, typename TT, bool LIM>
+__global__ __launch_bounds__(BLOCK) void k3_setupcd(Geom g, Tables tb, Target tg, const double *__restrict__ x, TT *__restrict__ Q, double *__restrict__ dE, double *__restrict__ bad)
+{
+    constexpr int EPB = S3<P, NQ>::EPB;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
+    b3_setupcd<P, NQ, TT, LIM>(g, tb, tg, x, Q, dE, bad, e0, min(EPB, g.ne - e0));
 }
 
 template <int P, int NQ, typename TT, bool LIM>

@@ -58,6 +58,15 @@ struct Ops {
     decltype(gradient) gradientM, gradientEM;
     decltype(setup64) setupM64;
     decltype(setupc64) setupcM64;
+    // tensor setup plus the element part of the Hessian diagonal (into dE) in
+    // one pass; null where the class has no such kernel (quads, more than one
+    // pass of points per workgroup)
+    void (*setupd64)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const double *x, double *H, double *dE, double *bad);
+    void (*setupd32)(int grid, hipStream_t, const Geom &, const Tables &, const Target &,
+                     const double *x, float *H, double *dE, double *bad);
+    decltype(setupd64) setupcd64;  // the same for compact storage
+    decltype(setupd32) setupcd32;
 };
 
 // Batched launchers (grid = number of tiles); every batched element kernel
@@ -100,6 +109,10 @@ inline void fill_tiles_k2(Ops &o)
     o.gradientEM = nullptr;
     o.setupM64 = nullptr;
     o.setupcM64 = nullptr;
+    o.setupd64 = nullptr;
+    o.setupd32 = nullptr;
+    o.setupcd64 = nullptr;
+    o.setupcd32 = nullptr;
 }
 
 template <int P, int NQ>

@@ -81,6 +81,56 @@ inline void fill_mfma3(Ops &o)
     }
 }
 
+// Setup with the element diagonal (b3_setupd, b3_setupcd) where the class's
+// points fit one pass of the workgroup.
+template <int P, int NQ>
+inline void fill_setupd3(Ops &o)
+{
+    if constexpr (S3<P, NQ>::EPB * S3<P, NQ>::NQ3 <= BLOCK) {
+        o.setupd64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,
+                        const double *x, double *H, double *dE, double *bad) {
+            if (g.lim != 0.0)
+                hipLaunchKernelGGL((k3_setupd<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, H, dE, bad);
+            else
+                hipLaunchKernelGGL((k3_setupd<P, NQ, double, false>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, H, dE, bad);
+        };
+        o.setupd32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,
+                        const double *x, float *H, double *dE, double *bad) {
+            if (g.lim != 0.0)
+                hipLaunchKernelGGL((k3_setupd<P, NQ, float, true>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, H, dE, bad);
+            else
+                hipLaunchKernelGGL((k3_setupd<P, NQ, float, false>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, H, dE, bad);
+        };
+        o.setupcd64 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,
+                         const double *x, double *Q, double *dE, double *bad) {
+            if (g.lim != 0.0)
+                hipLaunchKernelGGL((k3_setupcd<P, NQ, double, true>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, Q, dE, bad);
+            else
+                hipLaunchKernelGGL((k3_setupcd<P, NQ, double, false>), dim3(grid), dim3(BLOCK), 0,
+                                   s, g, t, w, x, Q, dE, bad);
+        };
+        o.setupcd32 = [](int grid, hipStream_t s, const Geom &g, const Tables &t, const Target &w,
+                         const double *x, float *Q, double *dE, double *bad) {
+            if (g.lim != 0.0)
+                hipLaunchKernelGGL((k3_setupcd<P, NQ, float, true>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, Q, dE, bad);
+            else
+                hipLaunchKernelGGL((k3_setupcd<P, NQ, float, false>), dim3(grid), dim3(BLOCK), 0, s,
+                                   g, t, w, x, Q, dE, bad);
+        };
+    } else {
+        o.setupd64 = nullptr;
+        o.setupd32 = nullptr;
+        o.setupcd64 = nullptr;
+        o.setupcd32 = nullptr;
+    }
+}
+
 template <int P, int NQ>
 inline void fill_tiles_k3(Ops &o)
 {
@@ -88,6 +138,7 @@ inline void fill_tiles_k3(Ops &o)
     fill_tile3<P, NQ, 2, 1>(o);
     fill_tile3<P, NQ, 4, 2>(o);
     fill_mfma3<P, NQ>(o);
+    fill_setupd3<P, NQ>(o);
 }
 
 template <int P, int NQ, int T2, int IDX>

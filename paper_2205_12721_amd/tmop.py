@@ -98,6 +98,7 @@ SIGNATURES = {
     "tmop_hessian_setup": [_P, _P],
     "tmop_hessian_apply": [_P, _P, _P],
     "tmop_hessian_diag": [_P, _P],
+    "tmop_hessian_setup_diag": [_P, _P, _P],
     "tmop_solve": [_P, _P, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveReport)],
     "tmop_newton_step": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SolveReport)],
     "tmop_minres": [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -328,6 +329,12 @@ class Context:
     def hessian_diag(self, out=None):
         out = self.new_vector() if out is None else out
         _check(lib().tmop_hessian_diag(self._h, self._vec(out)))
+        return out
+
+    def hessian_setup_diag(self, x, out=None):
+        """hessian_setup(x) then hessian_diag(), in one element pass where the class allows."""
+        out = self.new_vector() if out is None else out
+        _check(lib().tmop_hessian_setup_diag(self._h, self._vec(x), self._vec(out)))
         return out
 
     def minres(self, b, max_its=50, rtol=1e-12, jacobi=True, out=None):
