@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "b7b511e7c8a788bd6854d430717a0633e8611f7b4cb7f73425034cf7ed616003"
+_SHA_C2 = "14294b8c0035855e0a7164300cd683a448b5a63c9c2e3c778d2219d15c5b9566"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714364595, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714561073, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 371503330, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 369263881, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249302013, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249313288, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137370825, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137326126, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
