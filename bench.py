@@ -54,13 +54,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # profiles/hessian_apply_traffic_24cube_q3.md.
 _SHA_C2 = "14294b8c0035855e0a7164300cd683a448b5a63c9c2e3c778d2219d15c5b9566"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714561073, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714390638, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 369263881, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 369473930, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249313288, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249322771, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137326126, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137317691, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
