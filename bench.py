@@ -192,8 +192,12 @@ def sweep_fma(dim, p, nq):
 def kernel_leg(ctx, x, ne, nqe, S, dim, p, nq, reps=20):
     """The other steps of the path on the headline context, each call timed alone
     (median of `reps`, HIP events on the context's stream): setup (a8), gradient
-    (a7), energy (a6), diagonal (a10).  Sweep GFLOP/s counts only the
-    sum-factorized sweeps (2 FLOP per multiply-add), not the point stage."""
+    (a7), energy (a6), diagonal (a10), and the two fused passes the Newton step
+    runs, each beside the pair of calls it replaces: setup + diagonal
+    (tmop_hessian_setup_diag, the Jacobi preconditioner's) and energy +
+    gradient (tmop_energy_gradient, the line search's).  Sweep GFLOP/s counts
+    only the sum-factorized sweeps (2 FLOP per multiply-add), not the point
+    stage."""
     import numpy as np
     import torch
     g = torch.empty_like(x)
@@ -219,6 +223,10 @@ def kernel_leg(ctx, x, ne, nqe, S, dim, p, nq, reps=20):
     t_en = med(lambda: ctx.energy(x))
     ctx.hessian_setup(x)
     t_diag = med(lambda: ctx.hessian_diag(d))
+    t_sd_pair = med(lambda: (ctx.hessian_setup(x), ctx.hessian_diag(d)))
+    t_sd = med(lambda: ctx.hessian_setup_diag(x, d))
+    t_eg_pair = med(lambda: (ctx.energy(x), ctx.gradient(x, g)))
+    t_eg = med(lambda: ctx.energy_gradient(x, g))
     tens = ne * nqe * S * 8
     r2 = lambda v: round(v, 2)  # noqa: E731
     return {
@@ -229,6 +237,9 @@ def kernel_leg(ctx, x, ne, nqe, S, dim, p, nq, reps=20):
         "energy": {"us": r2(t_en), "sweep_GFLOP_s": r2(fw / t_en / 1e3),
                    "note": "includes the copy of the result to the host"},
         "diagonal": {"us": r2(t_diag), "tensor_GB_s_read": r2(tens / t_diag / 1e3)},
+        "setup_diag": {"us": r2(t_sd), "separate_calls_us": r2(t_sd_pair)},
+        "energy_gradient": {"us": r2(t_eg), "separate_calls_us": r2(t_eg_pair),
+                            "note": "both include the copy of the scalars to the host"},
         "action_GFLOP_s": None,
     }
 
