@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "14294b8c0035855e0a7164300cd683a448b5a63c9c2e3c778d2219d15c5b9566"
+_SHA_C2 = "4b68cd0026790a23ea58a85348bcb79b98c9c6360574b36b81cc66c26b003656"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714390638, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714440477, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 369473930, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 369472740, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249322771, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249301253, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137317691, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137370831, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 

@@ -504,19 +504,35 @@ __device__ __forceinline__ void qdata_load(const TT *__restrict__ he, int q, TT 
     }
 }
 
+// Where a run's (a plane's) data ends inside a 128-byte line, the lanes of
+// its last PR (PP) points also write zeros into the padding points that fill
+// that line, so that the wave writing the line's data writes all of it.
 template <typename TT, int NS, int NQT>
 __device__ __forceinline__ void qdata_store(TT *__restrict__ he, int q, const TT *in)
 {
     using L = QLay<TT, NS, NQT>;
+    constexpr int TB = (int)sizeof(TT);
+    constexpr int PR = (NQT * 16) % 128 ? (128 - (NQT * 16) % 128) / 16 : 0;
+    constexpr int PP = (NQT * TB) % 128 ? (128 - (NQT * TB) % 128) / TB : 0;
+    static_assert(PR <= L::NQP - NQT && PP <= L::NQP - NQT, "padding within the block");
 #pragma unroll
     for (int r = 0; r < L::NV; ++r) {
         Vec16<TT> w;
 #pragma unroll
         for (int k = 0; k < L::VEC; ++k) w.v[k] = in[r * L::VEC + k];
         *(Vec16<TT> *)(he + (r * L::NQP + q) * L::VEC) = w;
+        if (PR && q >= NQT - PR) {
+            Vec16<TT> z;
+#pragma unroll
+            for (int k = 0; k < L::VEC; ++k) z.v[k] = (TT)0;
+            *(Vec16<TT> *)(he + (r * L::NQP + q + PR) * L::VEC) = z;
+        }
     }
 #pragma unroll
-    for (int s = L::TAIL; s < NS; ++s) he[L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q] = in[s];
+    for (int s = L::TAIL; s < NS; ++s) {
+        he[L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q] = in[s];
+        if (PP && q >= NQT - PP) he[L::TAIL * L::NQP + (s - L::TAIL) * L::NQP + q + PP] = (TT)0;
+    }
 }
 
 // one value s (diagonal kernels read a subset)
