@@ -90,3 +90,13 @@ def test_pool_rejects_gauss_lobatto_on_host():
     assert "Gauss-Legendre" in lib.tmop_pool_last_error().decode()
     prm.quad_rule = 0
     assert lib.tmop_pool_request_bytes(ctypes.byref(md), ctypes.byref(prm), ctypes.byref(b)) == 0
+
+
+def test_fused_entry_points_reject_null_arguments():
+    """The one-pass calls check their arguments on the host before any device work."""
+    from paper_2205_12721_amd import tmop
+    lib = tmop.lib()
+    assert lib.tmop_energy_gradient(None, None, None, None, None, None) == 1
+    assert "null" in lib.tmop_last_error().decode()
+    assert lib.tmop_hessian_setup_diag(None, None, None) == 1
+    assert "null" in lib.tmop_last_error().decode()
