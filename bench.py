@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "4b68cd0026790a23ea58a85348bcb79b98c9c6360574b36b81cc66c26b003656"
+_SHA_C2 = "13d71c743ade0df7e383d2dc4f06106e1ccd812c9bd118ec1a7617971ad2ed94"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714440477, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714332326, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 369472740, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 371886352, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249301253, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249292281, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137370831, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137368731, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 

@@ -537,30 +537,35 @@ __device__ inline bool metric_second(const Target &t, const double *A, double z,
     // general constant W: each entry H_A[an][bp] = sum_kl d2mu[ak][bl] Winv_nk Winv_pl,
     // with d2mu evaluated entry by entry (keeps register use low).  The loops
     // index at run time, so they work on copies (Tg, Cg, Hg): the arrays of
-    // the ideal-target path above then stay in registers.
-    constexpr int NS = D2 * (D2 + 1) / 2;
-    double Tg[D2], Cg[D2], Hg[NS];
+    // the ideal-target path above then stay in registers.  Multiply-adds are
+    // fused per source expression only (not where the code generator finds
+    // them), so every kernel that inlines this code rounds the same way.
+    {
+#pragma clang fp contract(on)
+        constexpr int NS = D2 * (D2 + 1) / 2;
+        double Tg[D2], Cg[D2], Hg[NS];
 #pragma unroll
-    for (int k = 0; k < D2; ++k) {
-        Tg[k] = T[k];
-        Cg[k] = C[k];
-    }
-    for (int r = 0; r < D2; ++r)
-        for (int s = r; s < D2; ++s) {
-            const int a = r / D, n = r % D, b = s / D, p = s % D;
-            double acc = 0.0;
-            for (int k = 0; k < D; ++k)
-                for (int l = 0; l < D; ++l) {
-                    const int rr = a * D + k, ss = b * D + l;
-                    double v = m.c_tc * (Tg[rr] * Cg[ss] + Cg[rr] * Tg[ss]) +
-                               m.c_cc * Cg[rr] * Cg[ss] + m.c_dc * dcof<D>(Tg, rr, ss);
-                    if (rr == ss) v += m.c_id;
-                    acc += v * t.Winv[n * D + k] * t.Winv[p * D + l];
-                }
-            Hg[sym_index<D2>(r, s)] = z * acc;
+        for (int k = 0; k < D2; ++k) {
+            Tg[k] = T[k];
+            Cg[k] = C[k];
         }
+        for (int r = 0; r < D2; ++r)
+            for (int s = r; s < D2; ++s) {
+                const int a = r / D, n = r % D, b = s / D, p = s % D;
+                double acc = 0.0;
+                for (int k = 0; k < D; ++k)
+                    for (int l = 0; l < D; ++l) {
+                        const int rr = a * D + k, ss = b * D + l;
+                        double v = m.c_tc * (Tg[rr] * Cg[ss] + Cg[rr] * Tg[ss]) +
+                                   m.c_cc * Cg[rr] * Cg[ss] + m.c_dc * dcof<D>(Tg, rr, ss);
+                        if (rr == ss) v += m.c_id;
+                        acc += v * t.Winv[n * D + k] * t.Winv[p * D + l];
+                    }
+                Hg[sym_index<D2>(r, s)] = z * acc;
+            }
 #pragma unroll
-    for (int k = 0; k < NS; ++k) Hp[k] = Hg[k];
+        for (int k = 0; k < NS; ++k) Hp[k] = Hg[k];
+    }
     return true;
 }
 

@@ -6,8 +6,8 @@ it feeds the diagonal, as the separate diagonal kernel reads it back, so the
 diagonal and every later Hessian action are bitwise equal; the diagonal is
 also checked against the oracle (1e-11 FP64, 1e-6 mixed).  Every hex class
 (one-pass classes take the fused kernel, the others the two kernels), quads,
-tensor and compact storage, FP64 and mixed, the limiting term and the
-matrix-core sweeps (which keep the two kernels).
+tensor and compact storage, FP64 and mixed, the limiting term, a sheared
+constant target and the matrix-core sweeps (which keep the two kernels).
 """
 import numpy as np
 import pytest
@@ -46,14 +46,22 @@ def test_setup_diag_bitwise(dim, ns, p, nq, precision, storage):
     assert rel(d1, pb.diag(x)) <= (TOL64 if precision == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("variant", ["compact_limiting", "limiting", "mfma"])
+@pytest.mark.parametrize("variant", ["compact_limiting", "limiting", "mfma", "target",
+                                     "compact_target"])
 def test_setup_diag_other_paths(variant):
     from paper_2205_12721_amd.tmop import Context
     log("variant", variant)
     dim, ns, p, nq = 3, (3, 3, 2), 3, 5
-    pb, x = make_case(dim, ns, p, nq, seed=9)
+    W = None
+    if variant.endswith("target"):  # a sheared constant target (general-W paths)
+        rng = np.random.default_rng(41)
+        W = np.eye(3) + 0.2 * rng.standard_normal((3, 3))
+        if np.linalg.det(W) < 0:
+            W[:, 0] *= -1
+    pb, x = make_case(dim, ns, p, nq, seed=9, W=W)
     v = inputs.gaussian_vector(pb.ndof, 14, pb.ess)
-    ctx = Context(dim, ns, p, nq, storage="compact" if variant == "compact_limiting" else "tensor")
+    ctx = Context(dim, ns, p, nq, storage="compact" if variant.startswith("compact") else "tensor",
+                  W=W)
     if variant in ("limiting", "compact_limiting"):
         x0 = x + 0.01 * np.random.default_rng(31).standard_normal(x.size)
         pb.set_limiting(x0, 0.6, 0.05)
