@@ -52,15 +52,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # entry names the SHA-256 of the kernel sources (csrc_sha256()) and is
 # reported as null once they differ.  Summary and commands:
 # profiles/hessian_apply_traffic_24cube_q3.md.
-_SHA_C2 = "13d71c743ade0df7e383d2dc4f06106e1ccd812c9bd118ec1a7617971ad2ed94"
+_SHA_C2 = "a40a481d36b6bc943531a4a21cf3d3373af65a4006afbdadefbf6a753cfb6637"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714332326, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714408124, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 371886352, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 371703004, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249292281, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249300138, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137368731, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137330401, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 

@@ -202,10 +202,9 @@ int tmop_gradient(tmop_ctx *ctx, const double *x_dev, double *g_dev);
 /* F, min det A (to host), g_c (device, d*N_x) and |g_c|^2 (to host) at one
  * point in one element pass: the gradient kernel also sums the energy terms
  * (Sec. 3.3), as the line search of the Newton solver needs all four.
- * Synchronises.  |g_c|^2 is the sum of squares of g_c in the library's
- * reduction order; F, min det A and g_c agree with tmop_energy_mindet and
- * tmop_gradient to rounding (about 1e-15 relative: the same terms in the
- * same order, in differently compiled code).  Returns TMOP_ERR_INVERTED
+ * Synchronises.  F, min det A and g_c are bitwise those of
+ * tmop_energy_mindet and tmop_gradient, and |g_c|^2 is the sum of squares
+ * of g_c in the library's reduction order.  Returns TMOP_ERR_INVERTED
  * (F = +inf, g_c of no use) when det T <= 0 at a quadrature point.  Any
  * host pointer may be NULL. */
 int tmop_energy_gradient(tmop_ctx *ctx, const double *x_dev, double *F_host,

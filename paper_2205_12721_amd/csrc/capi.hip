@@ -553,11 +553,9 @@ static void gradient_impl(tmop_ctx *c, const double *x, double *g)
 
 // Energy, min det A, gradient and |g|^2 of one point in one element pass
 // (the gradient kernel also sums the energy) and one host synchronisation.
-// g2 is a dot of g with itself; F, md and g agree with energy_mindet_impl
-// and gradient_impl up to rounding (the same terms in the same order, but
-// the compiler fuses the products of mu and of P differently when both are
-// live).  F = inf and TMOP_ERR_INVERTED when det T <= 0 somewhere (g is then
-// of no use).
+// F, md and g are bitwise those of energy_mindet_impl and gradient_impl, g2
+// a dot of g with itself.  F = inf and TMOP_ERR_INVERTED when det T <= 0
+// somewhere (g is then of no use).
 static int energy_gradient_impl(tmop_ctx *c, const double *x, double *F, double *md, double *g,
                                 double *g2)
 {

@@ -641,9 +641,8 @@ __device__ __forceinline__ void b3_energy(const Geom &g, const Tables &tb, const
 // EN: also the energy partials of b3_energy (the point stage evaluates mu
 // anyway): the sums, the min det and the count of points with det T <= 0 go
 // to the planes bad[blockIdx], bad[grid + blockIdx], bad[2 grid + blockIdx]
-// (the same terms in the same order as b3_energy; with mu and P both live
-// the compiler may fuse their products differently, so the energy and the
-// gradient can differ from the separate kernels' in the last bits).
+// (the same terms in the same order as b3_energy: bitwise its partials, and
+// the gradient bitwise that of EN = false).
 template <int P, int NQ, bool LIM = false, bool EN = false, bool MF = false>
 __device__ __forceinline__ void b3_gradient(const Geom &g, const Tables &tb, const Target &tg,
                                    const double *__restrict__ x, double *__restrict__ gE,

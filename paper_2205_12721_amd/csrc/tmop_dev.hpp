@@ -333,8 +333,14 @@ struct MetricCoef {
 //   9   mu_9   = tau |T - T^{-t}|^2 = I1 (tau + 1/tau) - 4 tau (2D shape+size)
 // (the 2D forms of mu_7, mu_9 use |C| = |T| and T : C = 2 tau; metric_value
 // evaluates them from their definition instead, which is exact at T = I).
+// The metric code below fuses multiply-adds per source expression only
+// (fp contract(on)), not wherever the code generator finds them after
+// inlining, so every kernel that evaluates a metric at a point rounds the
+// same way (the one-pass kernels give bitwise the results of the separate
+// ones).
 __device__ inline MetricCoef metric_coef(int metric, double I1, double tau)
 {
+#pragma clang fp contract(on)
     MetricCoef m;
     if (metric == 2) {
         const double it = 1.0 / tau;
@@ -395,6 +401,7 @@ template <int D>
 __device__ inline double metric_value(int metric, const double *T, const double *C, double I1,
                                       double tau, const MetricCoef &m)
 {
+#pragma clang fp contract(on)
     if (metric != 7 && metric != 9) return m.mu;
     const double it = 1.0 / tau;
     double s = 0.0;
@@ -409,6 +416,7 @@ __device__ inline double metric_value(int metric, const double *T, const double 
 template <int D>
 __device__ inline void apply_winv(const Target &t, const double *A, double *T)
 {
+#pragma clang fp contract(on)
     if (t.ideal) {
 #pragma unroll
         for (int k = 0; k < D * D; ++k) T[k] = A[k];
@@ -428,6 +436,7 @@ __device__ inline void apply_winv(const Target &t, const double *A, double *T)
 template <int D>
 __device__ inline double det_cof(const double *T, double *C)
 {
+#pragma clang fp contract(on)
     if constexpr (D == 2) {
         C[0] = T[3];
         C[1] = -T[2];
@@ -451,6 +460,7 @@ __device__ inline double det_cof(const double *T, double *C)
 template <int D>
 __device__ inline double det_only(const double *A)
 {
+#pragma clang fp contract(on)
     if constexpr (D == 2) return A[0] * A[3] - A[1] * A[2];
     return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
            A[2] * (A[3] * A[7] - A[4] * A[6]);
@@ -461,6 +471,7 @@ __device__ inline double det_only(const double *A)
 template <int D>
 __device__ inline double dcof(const double *T, int r, int s)
 {
+#pragma clang fp contract(on)
     const int i = r / D, j = r % D, k = s / D, l = s % D;
     if constexpr (D == 2) {
         if (i != k && j != l) return (i == j) ? 1.0 : -1.0;
@@ -479,6 +490,7 @@ template <int D>
 __device__ inline bool metric_first(const Target &t, const double *A, double z, double *mu,
                                     double *P)
 {
+#pragma clang fp contract(on)
     double T[D * D], C[D * D];
     apply_winv<D>(t, A, T);
     const double tau = det_cof<D>(T, C);
@@ -513,6 +525,7 @@ __device__ inline bool metric_first(const Target &t, const double *A, double z, 
 template <int D>
 __device__ inline bool metric_second(const Target &t, const double *A, double z, double *Hp)
 {
+#pragma clang fp contract(on)
     constexpr int D2 = D * D;
     double T[D2], C[D2];
     apply_winv<D>(t, A, T);
@@ -537,11 +550,8 @@ __device__ inline bool metric_second(const Target &t, const double *A, double z,
     // general constant W: each entry H_A[an][bp] = sum_kl d2mu[ak][bl] Winv_nk Winv_pl,
     // with d2mu evaluated entry by entry (keeps register use low).  The loops
     // index at run time, so they work on copies (Tg, Cg, Hg): the arrays of
-    // the ideal-target path above then stay in registers.  Multiply-adds are
-    // fused per source expression only (not where the code generator finds
-    // them), so every kernel that inlines this code rounds the same way.
+    // the ideal-target path above then stay in registers.
     {
-#pragma clang fp contract(on)
         constexpr int NS = D2 * (D2 + 1) / 2;
         double Tg[D2], Cg[D2], Hg[NS];
 #pragma unroll
