@@ -54,13 +54,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # profiles/hessian_apply_traffic_24cube_q3.md.
 _SHA_C2 = "a40a481d36b6bc943531a4a21cf3d3373af65a4006afbdadefbf6a753cfb6637"
 TRAFFIC = {
-    ("c2", "tensor_fp64"): {"bytes": 714408124, "elements_per_workgroup": 2,
+    ("c2", "tensor_fp64"): {"bytes": 714546511, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "tensor_mixed"): {"bytes": 371703004, "elements_per_workgroup": 2,
+    ("c2", "tensor_mixed"): {"bytes": 371956710, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_fp64"): {"bytes": 249300138, "elements_per_workgroup": 2,
+    ("c2", "compact_fp64"): {"bytes": 249300935, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
-    ("c2", "compact_mixed"): {"bytes": 137330401, "elements_per_workgroup": 2,
+    ("c2", "compact_mixed"): {"bytes": 137360473, "elements_per_workgroup": 2,
                         "csrc_sha256": _SHA_C2},
 }
 
